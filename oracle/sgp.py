@@ -1,0 +1,445 @@
+"""Plain float64 CPU oracle for SGP / Richardson-Lucy Poisson deconvolution.
+
+TEST INFRASTRUCTURE ONLY.  Only ``tests/``, ``__graft_entry__.smoke()`` and the
+``cpu_baseline`` leg of ``bench.py`` may import this module.  It shares no code,
+table or helper with the HIP library and imports nothing from it.
+
+It follows Prato, Cavicchioli, Zanni, Boccacci, Bertero, "Efficient
+deconvolution methods for astronomical imaging: algorithms and IDL-GPU codes"
+(A&A 539, A133, 2012; arXiv:1210.2258):
+
+* imaging model and RL iteration ............ Sect. 1, Eq. (RL)
+* KL divergence ............................. Sect. 1, Eq. (divergence)
+* SGP ....................................... Sect. 2.1, Algorithm 1
+* scaled BB rules, safeguards, alternation .. Sect. 2.1, Eqs. (BB1), (BB2), (alphadef)
+* RL scaling matrix ......................... Sect. 2.1, Eq. (Dk)
+* single-image gradient ..................... Sect. 2.2, Eq. (KLgrad)
+* multiple images ........................... Sect. 2.3, Eqs. (multipleKL), (multipleRL), (multiplegradient)
+* boundary effect correction ................ Sect. 2.4, Eqs. (projection), (backprojection),
+                                              (gradientboundary), (Rdef), (boundaryRL), (Dkbound)
+* start, parameters, adaptive bounds ........ Sect. 3.1, 3.2
+* stopping rules ............................ Sect. 3.3, Eqs. (convergence), (discrepancy)
+* flux-constrained projection ............... Sect. 2 intro (constraint set named, algorithm
+                                              not given); derived here from the KKT conditions
+
+Every array is float64.  Inputs given in float32 are promoted.  The iteration
+is written step by step in the paper's order and notation; library primitives
+(``numpy.fft``, ``numpy.sort``) are the only building blocks.
+
+Readings of points the paper leaves open (each is a named parameter or a
+documented choice, shared with the HIP library by specification, not by code):
+
+* which D in the BB rules: the scaling of the new iterate, D_{k+1}=D(f^{(k+1)});
+* the first ``n_bb2_only`` (20) steplengths use the min-rule of Eq. (alphadef)
+  without touching tau; alternation starts afterwards;
+* the memory of alpha^(2) values holds only the values computed so far;
+* "10 alpha_{k-1}" is the steplength used in the step just taken;
+* the RL step of Sect. 3.2 only sets (L1, L2); SGP starts from f^(0);
+* a term with g = 0 contributes y to the KL sum;
+* boundary weights alpha_j = K_j (correlated with) M_S, i.e. A_j^T 1 before M_R;
+* multi-image scaling D = clip(f, L1, L2) / p;
+* flat start = mean_j sum_S (g_j - b_j) / |S|, put on R only;
+* discrepancy stop at the first k with 2 J / (p |S|) <= b_D; KL summed over S;
+* backtracking capped at ``max_backtracks``; d = 0 stops as stationary;
+* BB sums taken over pixels with D > 0 (D^{-1} is undefined off R).
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+
+STOP_FIXED = 1
+STOP_CONV = 2
+STOP_DISCREPANCY = 4
+STOP_RMSE = 8
+
+REASON_MAXITER = 0
+REASON_CONV = 1
+REASON_DISCREPANCY = 2
+REASON_RMSE = 3
+REASON_STATIONARY = 4
+REASON_ARMIJO = 5
+
+
+@dataclass
+class Params:
+    """Sect. 3.2 defaults (beta, theta, alpha0, tau1, alpha_max, M_alpha,
+    alpha_min) plus the Sect. 3.3 stopping controls."""
+    max_iter: int = 1000
+    stop: int = STOP_FIXED
+    tol: float = 1e-4
+    disc_target: float = 1.0
+    beta: float = 1e-4
+    theta: float = 0.4
+    alpha0: float = 1.3
+    alpha_min: float = 1e-5
+    alpha_max: float = 1e5
+    tau1: float = 0.5
+    m_alpha: int = 3
+    n_bb2_only: int = 20
+    auto_bounds: bool = True
+    L1: float = 1e-10
+    L2: float = 1e10
+    flux_constraint: bool = False
+    flux: float = -1.0
+    max_backtracks: int = 40
+    f_true: np.ndarray | None = None
+
+
+def _as_stack(a, p=None):
+    a = np.asarray(a, dtype=np.float64)
+    if a.ndim == 2:
+        a = a[None]
+    return a
+
+
+class Problem:
+    """p images g_j observed on S (ny x nx), PSFs K_j on Sbar (NY x NX),
+    backgrounds b_j on S.  Without ``domain`` the problem is periodic and
+    Sbar = S.  With ``domain=(NY, NX, oy, ox)`` S sits at offset (oy, ox)
+    inside Sbar (Sect. 2.4)."""
+
+    def __init__(self, g, psf, b, domain=None, sigma_R=1e-3):
+        g = _as_stack(g)
+        self.p, self.ny, self.nx = g.shape
+        psf = _as_stack(psf)
+        if domain is None:
+            self.NY, self.NX, self.oy, self.ox = self.ny, self.nx, 0, 0
+            self.boundary = False
+        else:
+            self.NY, self.NX, self.oy, self.ox = (int(v) for v in domain)
+            self.boundary = True
+        if psf.shape != (self.p, self.NY, self.NX):
+            raise ValueError("PSF stack must be [p, NY, NX]")
+        b = np.asarray(b, dtype=np.float64)
+        if b.ndim == 0:
+            b = np.full((self.p, self.ny, self.nx), float(b))
+        elif b.ndim == 1:
+            b = b[:, None, None] * np.ones((1, self.ny, self.nx))
+        elif b.ndim == 2:
+            b = b[None] * np.ones((self.p, 1, 1))
+        self.g, self.b = g, b
+        self.S = (slice(self.oy, self.oy + self.ny), slice(self.ox, self.ox + self.nx))
+        # Sect. 2.2-2.4: every PSF normalised to unit volume (over Sbar)
+        K = psf / psf.sum(axis=(1, 2), keepdims=True)
+        # PSF centre at (NY//2, NX//2) is moved to the origin before the FFT
+        self.K = K
+        self.Khat = np.fft.fft2(np.fft.ifftshift(K, axes=(1, 2)), axes=(1, 2))
+        self.MS = np.zeros((self.NY, self.NX))
+        self.MS[self.S] = 1.0
+        if self.boundary:
+            # weights of Sect. 2.4: alpha_j(n) = sum_m K_j(m-n) M_S(m)
+            self.alpha_j = np.stack([self._corr(j, self.MS) for j in range(self.p)])
+            # Eq. (Rdef): R = {n : alpha_j(n) >= sigma for all j}
+            self.MR = np.all(self.alpha_j >= sigma_R, axis=0).astype(np.float64)
+        else:
+            self.alpha_j = np.ones((self.p, self.NY, self.NX))
+            self.MR = np.ones((self.NY, self.NX))
+        self.alpha = self.alpha_j.sum(axis=0)
+        # M_R / alpha, the quotient being zero outside R (Eqs. boundaryRL, Dkbound);
+        # 1/p for periodic multiple images (scaling f/p of Sect. 2.3)
+        self.invw = np.where(self.MR > 0, 1.0 / np.where(self.MR > 0, self.alpha, 1.0), 0.0)
+        self.nS = self.ny * self.nx
+
+    # ---------------------------------------------------------------- operators
+    def _conv(self, j, x):
+        return np.real(np.fft.ifft2(self.Khat[j] * np.fft.fft2(x)))
+
+    def _corr(self, j, x):
+        return np.real(np.fft.ifft2(np.conj(self.Khat[j]) * np.fft.fft2(x)))
+
+    def embed(self, x_S):
+        """Zero-pad an array on S into Sbar (the M_S o . of Eq. backprojection)."""
+        out = np.zeros((self.NY, self.NX))
+        out[self.S] = x_S
+        return out
+
+    def A(self, j, f):
+        """Eq. (projection): (A_j f) = M_S o (K_j * (M_R o f)); returned on S."""
+        return self._conv(j, self.MR * f)[self.S]
+
+    def AT(self, j, y_S):
+        """Eq. (backprojection): A_j^T y = M_R o (K_j correlated with M_S o y)."""
+        return self.MR * self._corr(j, self.embed(y_S))
+
+    def A_direct(self, j, f):
+        """Brute-force O(N^2) periodic convolution, for tests only."""
+        NY, NX = self.NY, self.NX
+        K0 = np.fft.ifftshift(self.K[j])
+        fm = self.MR * f
+        out = np.zeros((NY, NX))
+        ys, xs = np.nonzero(fm)
+        for n_y, n_x in zip(ys, xs):
+            out += fm[n_y, n_x] * np.roll(np.roll(K0, n_y, axis=0), n_x, axis=1)
+        return out[self.S]
+
+    # ------------------------------------------------------------- objective
+    def y(self, j, f):
+        return self.A(j, f) + self.b[j]
+
+    def kl(self, f):
+        """Eqs. (divergence) / (multipleKL), summed over S; g = 0 terms give y."""
+        J = 0.0
+        for j in range(self.p):
+            y = self.y(j, f)
+            g = self.g[j]
+            if np.any((y <= 0) & (g > 0)):
+                raise FloatingPointError("A f + b <= 0 where g > 0")
+            pos = g > 0
+            t = y - g
+            t[pos] += g[pos] * np.log(g[pos] / y[pos])
+            J += t.sum()
+        return J
+
+    def grad(self, f):
+        """Eqs. (KLgrad), (multiplegradient), (gradientboundary):
+        sum_j {A_j^T 1 - A_j^T (g_j / (A_j f + b_j))}."""
+        G = np.zeros((self.NY, self.NX))
+        for j in range(self.p):
+            G += self.MR * self.alpha_j[j] - self.AT(j, self.g[j] / self.y(j, f))
+        return G
+
+    def discrepancy(self, J):
+        """Eq. (discrepancy), N^2 read as the pixel count of one observed image."""
+        return 2.0 * J / (self.p * self.nS)
+
+    # ---------------------------------------------------------- RL family
+    def rl_step(self, f):
+        """Eqs. (RL), (multipleRL), (boundaryRL):
+        f <- (M_R / alpha) o f o sum_j A_j^T (g_j / (A_j f + b_j))."""
+        s = np.zeros((self.NY, self.NX))
+        for j in range(self.p):
+            s += self.AT(j, self.g[j] / self.y(j, f))
+        return self.invw * f * s
+
+    def start(self, kind="flat", user=None):
+        """Sect. 3.1 initial points."""
+        if kind == "zero":
+            return np.zeros((self.NY, self.NX))
+        if kind == "data":
+            return self.MR * self.embed(self.g[0])
+        if kind == "user":
+            return np.asarray(user, dtype=np.float64).copy()
+        c = np.mean([(self.g[j] - self.b[j]).sum() for j in range(self.p)]) / self.nS
+        if c <= 0:
+            c = 1e-6 * max(self.g.mean(), 1e-30)
+        return c * self.MR
+
+    def bounds(self, f0):
+        """Sect. 3.2: one RL step, min positive / max of the result."""
+        yr = self.rl_step(f0)
+        pos = yr[(yr > 0) & (self.MR > 0)]
+        ymin, ymax = pos.min(), pos.max()
+        if ymax / ymin < 50:
+            return ymin / 10.0, ymax * 10.0
+        return ymin, ymax
+
+    def rl(self, f0, n_iter, params: Params | None = None):
+        """Plain RL iteration with the Sect. 3.3 stopping rules."""
+        prm = params or Params(max_iter=n_iter)
+        f = f0.copy()
+        J = self.kl(f)
+        hist = [J]
+        reason = REASON_MAXITER
+        k = 0
+        if (prm.stop & STOP_DISCREPANCY) and self.discrepancy(J) <= prm.disc_target:
+            return f, dict(iters=0, kl=J, history=hist, reason=REASON_DISCREPANCY)
+        while k < n_iter:
+            f = self.rl_step(f)
+            Jn = self.kl(f)
+            k += 1
+            hist.append(Jn)
+            if (prm.stop & STOP_DISCREPANCY) and self.discrepancy(Jn) <= prm.disc_target:
+                reason = REASON_DISCREPANCY
+                J = Jn
+                break
+            if (prm.stop & STOP_CONV) and abs(Jn - J) <= prm.tol * J:
+                reason = REASON_CONV
+                J = Jn
+                break
+            J = Jn
+        return f, dict(iters=k, kl=J, history=hist, reason=reason)
+
+    # --------------------------------------------------------------- SGP
+    def scaling(self, f, L1, L2):
+        """Eqs. (Dk), (Dkbound): D = (M_R / alpha) o min[L2, max{L1, f}]."""
+        return self.invw * np.minimum(L2, np.maximum(L1, f))
+
+    def flux_value(self, prm: Params):
+        if prm.flux >= 0:
+            return prm.flux
+        return np.mean([(self.g[j] - self.b[j]).sum() for j in range(self.p)])
+
+    def project(self, z, D, prm: Params, c=None):
+        """P_+ of Algorithm 1 step 2 (orthant), or, with the flux constraint,
+        the D^{-1}-metric projection onto {x >= 0, sum x = c}."""
+        if not prm.flux_constraint:
+            return np.maximum(0.0, z)
+        return flux_projection(z, D, c)
+
+    def sgp(self, f0, params: Params | None = None, force_alpha=None,
+            force_lambda=None, bounds=None):
+        """Algorithm 1 with the Sect. 2.1 steplength rules and Sect. 3 policies.
+
+        ``force_alpha`` / ``force_lambda`` pin alpha_k / lambda_k (tests only:
+        the RL identity of Eq. (RL2) with lambda = 1).
+        Returns (f, info) where info carries the per-iteration decision log."""
+        prm = params or Params()
+        if bounds is not None:
+            L1, L2 = bounds
+        elif prm.auto_bounds:
+            L1, L2 = self.bounds(f0)
+        else:
+            L1, L2 = prm.L1, prm.L2
+        c = self.flux_value(prm) if prm.flux_constraint else None
+        f = f0.copy()
+        if prm.flux_constraint:
+            tot = f.sum()
+            if tot > 0:
+                f *= c / tot
+        J = self.kl(f)
+        G = self.grad(f)
+        alpha = prm.alpha0
+        tau = prm.tau1
+        Q: list[float] = []
+        log = []
+        hist = [J]
+        reason = REASON_MAXITER
+        k = 0
+        if (prm.stop & STOP_DISCREPANCY) and self.discrepancy(J) <= prm.disc_target:
+            return f, dict(iters=0, kl=J, history=hist, log=log, L1=L1, L2=L2,
+                           reason=REASON_DISCREPANCY, alpha=alpha)
+        rmse_prev = np.inf
+        while k < prm.max_iter:
+            if force_alpha is not None:
+                alpha = force_alpha
+            # steps 1-3: scaling, projection, direction
+            D = self.scaling(f, L1, L2)
+            yk = self.project(f - alpha * D * G, D, prm, c)
+            d = yk - f
+            gd = float(np.sum(G * d))
+            if gd == 0.0:
+                reason = REASON_STATIONARY
+                break
+            # steps 4-5: monotone Armijo backtracking
+            lam = 1.0
+            nback = 0
+            armijo_ok = True
+            if force_lambda is not None:
+                lam = force_lambda
+                f_new = f + lam * d
+                J_new = self.kl(f_new)
+            else:
+                while True:
+                    f_new = f + lam * d
+                    J_new = self.kl(f_new)
+                    if J_new <= J + prm.beta * lam * gd:
+                        break
+                    if nback >= prm.max_backtracks:
+                        armijo_ok = False
+                        break
+                    lam *= prm.theta
+                    nback += 1
+            if not armijo_ok:
+                reason = REASON_ARMIJO
+                break
+            # step 6: update
+            G_new = self.grad(f_new)
+            s = f_new - f
+            z = G_new - G
+            # Eqs. (BB1), (BB2) with D of the new iterate, over pixels with D > 0
+            Dn = self.scaling(f_new, L1, L2)
+            m = Dn > 0
+            sm, zm, Dm = s[m], z[m], Dn[m]
+            a_num = float(np.sum(sm * sm / (Dm * Dm)))
+            c1 = float(np.sum(sm * zm / Dm))
+            c2 = float(np.sum(sm * zm * Dm))
+            e_den = float(np.sum(zm * zm * Dm * Dm))
+            a1, a2, br1, br2, alpha_next, tau, Q, alt = steplength_update(
+                alpha, tau, Q, k, a_num, c1, c2, e_den, prm)
+            log.append(dict(k=k, alpha=alpha, gd=gd, backtracks=nback, lam=lam,
+                            J=J_new, a=a_num, c1=c1, c2=c2, e=e_den,
+                            a1=a1, a2=a2, br1=br1, br2=br2, alt=alt, tau=tau,
+                            alpha_next=alpha_next))
+            J_prev = J
+            f, J, G, alpha = f_new, J_new, G_new, alpha_next
+            k += 1
+            hist.append(J)
+            if (prm.stop & STOP_DISCREPANCY) and self.discrepancy(J) <= prm.disc_target:
+                reason = REASON_DISCREPANCY
+                break
+            if (prm.stop & STOP_CONV) and abs(J - J_prev) <= prm.tol * J_prev:
+                reason = REASON_CONV
+                break
+            if (prm.stop & STOP_RMSE) and prm.f_true is not None:
+                ft = np.asarray(prm.f_true, dtype=np.float64)
+                rmse = np.linalg.norm(f - ft) / np.linalg.norm(ft)
+                if rmse > rmse_prev:
+                    reason = REASON_RMSE
+                    break
+                rmse_prev = rmse
+        return f, dict(iters=k, kl=J, history=hist, log=log, L1=L1, L2=L2,
+                       reason=reason, alpha=alpha)
+
+
+def steplength_update(alpha, tau, Q, k, a_num, c1, c2, e_den, prm: Params):
+    """Sect. 2.1 steplength rule after iteration k (producing alpha_{k+1}).
+
+    a_num = s^T D^-1 D^-1 s, c1 = s^T D^-1 z (Eq. BB1);
+    c2 = s^T D z, e_den = z^T D D z (Eq. BB2).
+    Safeguards: a non-positive denominator gives min{10 alpha, alpha_max},
+    otherwise the BB value is clamped to [alpha_min, alpha_max].
+    Eq. (alphadef): the memory Q keeps the last M_alpha values of alpha^(2);
+    the first ``n_bb2_only`` steplengths take min Q, later ones alternate on
+    alpha^(2)/alpha^(1) <= tau (tau <- 0.9 tau) else alpha^(1) (tau <- 1.1 tau).
+    Returns (a1, a2, br1, br2, alpha_next, tau, Q, alt)."""
+    if c1 <= 0:
+        a1, br1 = min(10.0 * alpha, prm.alpha_max), 0
+    else:
+        a1, br1 = min(prm.alpha_max, max(prm.alpha_min, a_num / c1)), 1
+    if c2 <= 0:
+        a2, br2 = min(10.0 * alpha, prm.alpha_max), 0
+    else:
+        a2, br2 = min(prm.alpha_max, max(prm.alpha_min, c2 / e_den)), 1
+    Q = (list(Q) + [a2])[-prm.m_alpha:]
+    if k + 1 <= prm.n_bb2_only:
+        return a1, a2, br1, br2, min(Q), tau, Q, 0
+    if a2 / a1 <= tau:
+        return a1, a2, br1, br2, min(Q), 0.9 * tau, Q, 1
+    return a1, a2, br1, br2, a1, 1.1 * tau, Q, 2
+
+
+def flux_projection(z, D, c):
+    """argmin_{x >= 0, sum x = c} (x - z)^T D^{-1} (x - z).
+
+    KKT: x_i = max(0, z_i - mu D_i) for one multiplier mu, where
+    phi(mu) = sum_i max(0, z_i - mu D_i) - c = 0.  phi is piecewise linear and
+    non-increasing with breakpoints t_i = z_i / D_i; the oracle sorts them and
+    scans the pieces (brute force).  Pixels with D_i = 0 are held at
+    max(0, z_i)."""
+    z = np.asarray(z, dtype=np.float64)
+    D = np.asarray(D, dtype=np.float64)
+    act = D > 0
+    zf, Df = z[act], D[act]
+    fixed = np.maximum(0.0, z[~act]).sum()
+    target = c - fixed
+    t = zf / Df
+    order = np.argsort(-t)          # descending breakpoints
+    ts, zs, Ds = t[order], zf[order], Df[order]
+    # with mu in [ts[i], ts[i-1]] the active set is the first i entries
+    Sz = np.cumsum(zs)
+    SD = np.cumsum(Ds)
+    mu = None
+    for i in range(1, ts.size + 1):
+        m = (Sz[i - 1] - target) / SD[i - 1]
+        lo = ts[i] if i < ts.size else -np.inf
+        hi = ts[i - 1]
+        if lo <= m <= hi:
+            mu = m
+            break
+    if mu is None:
+        raise ValueError("flux projection: no root (c must be positive)")
+    x = np.maximum(0.0, z) * (~act)
+    x[act] = np.maximum(0.0, zf - mu * Df)
+    return x
