@@ -1,0 +1,185 @@
+/* sgpdeconv.h -- C ABI of the MI355X (gfx950) SGP / Richardson-Lucy library.
+ *
+ * Method: Prato, Cavicchioli, Zanni, Boccacci, Bertero, "Efficient
+ * deconvolution methods for astronomical imaging: algorithms and IDL-GPU
+ * codes", A&A 539, A133 (2012).  Given detected images g_j, PSFs K_j and
+ * backgrounds b_j, the calls below return f >= 0 minimising the
+ * Kullback-Leibler divergence J_0(f; g) of Sect. 1 Eq. (divergence) (summed
+ * over the images, Sect. 2.3 Eq. (multipleKL)) by scaled gradient projection
+ * (Sect. 2.1, Algorithm 1) or by the Richardson-Lucy iteration (Sect. 1,
+ * Eq. (RL); Sect. 2.3 Eq. (multipleRL); Sect. 2.4 Eq. (boundaryRL)).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Array pointers are DEVICE pointers (hipMalloc / torch CUDA tensors on the
+ *   current HIP device), float32, C-contiguous row-major with x fastest.
+ *   Image stacks are [p][ny][nx].  The caller owns every array; the library
+ *   never frees or keeps them after return.  Inputs are never modified; f is
+ *   overwritten.
+ * - Every PSF has the size of its FFT domain, its centre at (NY/2, NX/2), and
+ *   is normalised to unit volume by the library (Sect. 1; Sect. 2.4: over the
+ *   broader domain).  Negative or non-finite PSF entries, or a zero sum, give
+ *   SGP_E_BAD_PSF.
+ * - The background is a map (b_map, same layout as g) or, when b_map is NULL,
+ *   one constant per image (Sect. 1: b is a known array).  g must be finite
+ *   and >= 0 (SGP_E_BAD_DATA); b must be >= 0 (SGP_E_BAD_DATA).
+ * - FFT lengths (ny, nx; NY, NX for the boundary call) must be one of
+ *   16 32 64 128 256 512 1024 2048 80 160 320 640 1280; anything else gives
+ *   SGP_E_UNSUPPORTED_SIZE.
+ * - Calls are ordered on hip_stream (NULL = the null stream) and synchronous
+ *   on return: the report is filled in and f is ready.  A call allocates the
+ *   workspace it needs (kept in a per-shape cache until sgp_release_cache).
+ *   Calls are thread-safe; concurrent calls on one device serialise.
+ * - Return value: 0 on success; positive warnings leave a valid f;
+ *   negative errors leave f unspecified.  sgp_last_error() gives a
+ *   thread-local message for the last failing call.  No exception crosses
+ *   the ABI.
+ */
+#ifndef SGPDECONV_H
+#define SGPDECONV_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* return codes */
+#define SGP_OK 0
+#define SGP_W_MAXITER 1            /* max_iter reached before the requested stop rule */
+#define SGP_W_ARMIJO_EXHAUSTED 2   /* backtracking cap hit (Algorithm 1, step 5) */
+#define SGP_W_STATIONARY 3         /* grad^T d = 0: f is stationary */
+#define SGP_E_INVALID_ARG -1
+#define SGP_E_UNSUPPORTED_SIZE -2
+#define SGP_E_BAD_PSF -3
+#define SGP_E_BAD_DATA -4
+#define SGP_E_HIP -5
+#define SGP_E_NUMERIC -6           /* NaN / Inf appeared mid-run */
+#define SGP_E_NO_DEVICE -7
+
+/* stopping rules, Sect. 3.3 (bitmask; the first rule met ends the run) */
+#define SGP_STOP_FIXED 1           /* max_iter iterations */
+#define SGP_STOP_CONV 2            /* Eq. (convergence): |J(k+1) - J(k)| <= tol J(k) */
+#define SGP_STOP_DISCREPANCY 4     /* Eq. (discrepancy): 2 J / (p ny nx) <= disc_target */
+
+/* stop reasons reported in sgp_report.stop_reason */
+#define SGP_REASON_MAXITER 0
+#define SGP_REASON_CONV 1
+#define SGP_REASON_DISCREPANCY 2
+#define SGP_REASON_STATIONARY 4
+#define SGP_REASON_ARMIJO 5
+#define SGP_REASON_NUMERIC 6
+
+/* initial point, Sect. 3.1 */
+#define SGP_INIT_FLAT 0   /* (mean) background-subtracted flux / (ny nx), on R only */
+#define SGP_INIT_ZERO 1   /* not valid for RL, whose iterates stay at 0 */
+#define SGP_INIT_DATA 2   /* g (g_1 for several images), embedded on R */
+#define SGP_INIT_USER 3   /* f0 below (device pointer, [NY][NX]); negative values clipped */
+
+/* per-iteration trace columns (one row of SGP_TRACE_COLS doubles per iteration) */
+#define SGP_TRACE_COLS 20
+enum {
+  SGP_TR_K = 0, SGP_TR_ALPHA, SGP_TR_GD, SGP_TR_BACKTRACKS, SGP_TR_LAMBDA, SGP_TR_J,
+  SGP_TR_A, SGP_TR_C1, SGP_TR_C2, SGP_TR_E, SGP_TR_ALPHA1, SGP_TR_ALPHA2, SGP_TR_BB1_BRANCH,
+  SGP_TR_BB2_BRANCH, SGP_TR_ALT_BRANCH, SGP_TR_TAU, SGP_TR_ALPHA_NEXT, SGP_TR_FLUX_MU
+};
+
+/* Solver parameters.  sgp_params_init() fills in the paper's defaults
+ * (Sect. 3.2: beta 1e-4, theta 0.4, alpha0 1.3, tau1 0.5, alpha_max 1e5,
+ * alpha_min 1e-5, M_alpha 3; adaptive (L1, L2)). */
+typedef struct sgp_params {
+  int max_iter;          /* cap on iterations (default 1000) */
+  int stop;              /* SGP_STOP_* bitmask (default SGP_STOP_FIXED) */
+  double tol;            /* Eq. (convergence) tolerance (default 1e-4) */
+  double disc_target;    /* b of Eq. (discrepancy) (default 1.0) */
+  int init;              /* SGP_INIT_* (default SGP_INIT_FLAT) */
+  const float* f0;       /* SGP_INIT_USER start, device pointer [NY][NX] */
+  double beta, theta;    /* Armijo parameters, Algorithm 1 step 5 */
+  double alpha0, alpha_min, alpha_max, tau1; /* steplength rules, Sect. 2.1 */
+  int m_alpha;           /* memory of Eq. (alphadef), 1..8 (default 3) */
+  int n_bb2_only;        /* iterations using Eq. (alphadef) before alternation (default 20) */
+  int auto_bounds;       /* 1: (L1, L2) by the Sect. 3.2 rule; 0: use L1, L2 below */
+  double L1, L2;         /* scaling bounds of Eq. (Dk) when auto_bounds = 0 */
+  int flux_constraint;   /* reserved, must be 0 (projection onto f >= 0 only) */
+  double flux;           /* reserved */
+  double sigma_R;        /* threshold sigma of Eq. (Rdef) (default 1e-3) */
+  int max_backtracks;    /* Armijo reductions allowed, 0..40 (default 40) */
+  double* trace;         /* optional HOST buffer [(max_iter + 1) * SGP_TRACE_COLS] doubles */
+} sgp_params;
+
+typedef struct sgp_report {
+  int iters;             /* iterations performed */
+  int stop_reason;       /* SGP_REASON_* */
+  int backtracks;        /* total Armijo reductions */
+  int used_fallback;     /* reserved (warm start) */
+  double kl;             /* J_0 at the returned f */
+  double discrepancy;    /* 2 J_0 / (p ny nx) */
+  double flux;           /* sum of f */
+  double L1, L2;         /* scaling bounds used */
+  double seconds;        /* wall time of the call */
+} sgp_report;
+
+/* Fills *p with the defaults above.  Returns SGP_E_INVALID_ARG on NULL. */
+int sgp_params_init(sgp_params* p);
+
+/* Richardson-Lucy, Sect. 1 Eq. (RL) with a periodic convolution A f = K * f.
+ * g, f: [ny][nx]; psf: [ny][nx]; b_map: [ny][nx] or NULL (then b_const).
+ * Uses max_iter, stop, tol, disc_target, init, f0, trace of *prm; one
+ * iteration costs two FFT convolutions. */
+int rl_deconv(const float* g, const float* psf, const float* b_map, float b_const,
+              int ny, int nx, const sgp_params* prm, float* f, sgp_report* rep,
+              void* hip_stream);
+
+/* SGP for one image (Sect. 2.1 Algorithm 1 with the RL scaling Eq. (Dk) and
+ * the gradient of Sect. 2.2 Eq. (KLgrad)).  Arguments as rl_deconv. */
+int sgp_deconv(const float* g, const float* psf, const float* b_map, float b_const,
+               int ny, int nx, const sgp_params* prm, float* f, sgp_report* rep,
+               void* hip_stream);
+
+/* SGP for p images of one object (Sect. 2.3 Eqs. (multipleKL),
+ * (multiplegradient); scaling f/p).  g, psf, b_map: [p][ny][nx];
+ * b_const: HOST array of p constants (used when b_map is NULL); f: [ny][nx].
+ * 1 <= p <= 8. */
+int sgp_multi_deconv(const float* g, const float* psf, const float* b_map,
+                     const float* b_const, int p, int ny, int nx,
+                     const sgp_params* prm, float* f, sgp_report* rep, void* hip_stream);
+
+/* RL for p images (Sect. 2.3 Eq. (multipleRL)); arguments as sgp_multi_deconv. */
+int rl_multi_deconv(const float* g, const float* psf, const float* b_map,
+                    const float* b_const, int p, int ny, int nx,
+                    const sgp_params* prm, float* f, sgp_report* rep, void* hip_stream);
+
+/* SGP with boundary-effect correction (Sect. 2.4): the object lives on the
+ * NY x NX domain Sbar, the images g_j ([p][ny][nx], with b_map likewise) are
+ * observed on the window S at rows oy..oy+ny-1, columns ox..ox+nx-1 of Sbar.
+ * psf: [p][NY][NX].  A_j = M_S o (K_j * (M_R o .)) (Eq. (projection)), the
+ * weights alpha_j = A_j^T 1 before M_R, R by Eq. (Rdef) with sigma_R, scaling
+ * Eq. (Dkbound).  f: [NY][NX] (zero outside R on return). */
+int sgp_boundary_deconv(const float* g, const float* psf, const float* b_map,
+                        const float* b_const, int p, int ny, int nx, int NY, int NX,
+                        int oy, int ox, const sgp_params* prm, float* f,
+                        sgp_report* rep, void* hip_stream);
+
+/* RL with boundary-effect correction (Sect. 2.4 Eq. (boundaryRL)). */
+int rl_boundary_deconv(const float* g, const float* psf, const float* b_map,
+                       const float* b_const, int p, int ny, int nx, int NY, int NX,
+                       int oy, int ox, const sgp_params* prm, float* f,
+                       sgp_report* rep, void* hip_stream);
+
+/* Operator application for checks and callers that build their own loops:
+ * out = A_j x (adjoint = 0) or A_j^T x (adjoint = 1) for the periodic
+ * operator of Sect. 1 (K_j unit-volume, centred).  x, out: [ny][nx];
+ * psf: [ny][nx]. */
+int sgp_apply_operator(const float* psf, const float* x, int ny, int nx, int adjoint,
+                       float* out, void* hip_stream);
+
+/* Releases every cached workspace of the calling process on the current device. */
+int sgp_release_cache(void);
+
+const char* sgp_strerror(int code);
+const char* sgp_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SGPDECONV_H */

@@ -1,0 +1,14 @@
+"""MI355X-native SGP / Richardson-Lucy Poisson deconvolution.
+
+Python face of libsgpdeconv.so (C ABI in include/sgpdeconv.h).  Implements
+Prato et al., "Efficient deconvolution methods for astronomical imaging:
+algorithms and IDL-GPU codes" (2012): scaled gradient projection with RL
+scaling for the Kullback-Leibler divergence, single / multiple images and
+boundary-effect correction, plus the RL iterations.
+"""
+from ._lib import (  # noqa: F401
+    EXPORTS, LIB_PATH, REASONS, STOP_CONV, STOP_DISCREPANCY, STOP_FIXED, INIT_DATA, INIT_FLAT,
+    INIT_USER, INIT_ZERO, SgpError, apply_operator, default_params, load, release_cache,
+    rl_boundary_deconv, rl_deconv, rl_multi_deconv, sgp_boundary_deconv, sgp_deconv,
+    sgp_multi_deconv,
+)

@@ -1,0 +1,256 @@
+"""ctypes binding of libsgpdeconv.so (argument marshalling only).
+
+Every computation runs in the HIP library; this module checks tensor
+placement and dtype, converts keyword parameters into ``sgp_params`` and
+turns return codes into exceptions.  PyTorch provides device memory and the
+current stream.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libsgpdeconv.so")
+
+TRACE_COLS = 20
+TRACE_FIELDS = ["k", "alpha", "gd", "backtracks", "lam", "J", "a", "c1", "c2", "e",
+                "a1", "a2", "br1", "br2", "alt", "tau", "alpha_next", "flux_mu"]
+
+STOP_FIXED, STOP_CONV, STOP_DISCREPANCY = 1, 2, 4
+INIT_FLAT, INIT_ZERO, INIT_DATA, INIT_USER = 0, 1, 2, 3
+REASONS = {0: "maxiter", 1: "convergence", 2: "discrepancy", 4: "stationary", 5: "armijo", 6: "numeric"}
+
+
+class SgpError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"sgpdeconv error {code}: {msg}")
+        self.code = code
+
+
+class _Params(ctypes.Structure):
+    _fields_ = [
+        ("max_iter", ctypes.c_int), ("stop", ctypes.c_int), ("tol", ctypes.c_double),
+        ("disc_target", ctypes.c_double), ("init", ctypes.c_int), ("f0", ctypes.c_void_p),
+        ("beta", ctypes.c_double), ("theta", ctypes.c_double), ("alpha0", ctypes.c_double),
+        ("alpha_min", ctypes.c_double), ("alpha_max", ctypes.c_double), ("tau1", ctypes.c_double),
+        ("m_alpha", ctypes.c_int), ("n_bb2_only", ctypes.c_int), ("auto_bounds", ctypes.c_int),
+        ("L1", ctypes.c_double), ("L2", ctypes.c_double), ("flux_constraint", ctypes.c_int),
+        ("flux", ctypes.c_double), ("sigma_R", ctypes.c_double), ("max_backtracks", ctypes.c_int),
+        ("trace", ctypes.c_void_p),
+    ]
+
+
+class _Report(ctypes.Structure):
+    _fields_ = [
+        ("iters", ctypes.c_int), ("stop_reason", ctypes.c_int), ("backtracks", ctypes.c_int),
+        ("used_fallback", ctypes.c_int), ("kl", ctypes.c_double), ("discrepancy", ctypes.c_double),
+        ("flux", ctypes.c_double), ("L1", ctypes.c_double), ("L2", ctypes.c_double),
+        ("seconds", ctypes.c_double),
+    ]
+
+
+EXPORTS = [
+    "sgp_params_init", "rl_deconv", "sgp_deconv", "sgp_multi_deconv", "rl_multi_deconv",
+    "sgp_boundary_deconv", "rl_boundary_deconv", "sgp_apply_operator", "sgp_release_cache",
+    "sgp_strerror", "sgp_last_error",
+]
+
+_lib = None
+
+
+def load():
+    """Loads the library; raises if it has not been built (no fallback)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: run paper_1210_2258_amd.build.build() first")
+    lib = ctypes.CDLL(LIB_PATH)
+    P, R, vp, i, f, d = (ctypes.POINTER(_Params), ctypes.POINTER(_Report), ctypes.c_void_p,
+                         ctypes.c_int, ctypes.c_float, ctypes.c_double)
+    lib.sgp_params_init.argtypes = [P]
+    for name in ("rl_deconv", "sgp_deconv"):
+        getattr(lib, name).argtypes = [vp, vp, vp, f, i, i, P, vp, R, vp]
+    for name in ("sgp_multi_deconv", "rl_multi_deconv"):
+        getattr(lib, name).argtypes = [vp, vp, vp, vp, i, i, i, P, vp, R, vp]
+    for name in ("sgp_boundary_deconv", "rl_boundary_deconv"):
+        getattr(lib, name).argtypes = [vp, vp, vp, vp, i, i, i, i, i, i, i, P, vp, R, vp]
+    lib.sgp_apply_operator.argtypes = [vp, vp, i, i, i, vp, vp]
+    lib.sgp_strerror.restype = ctypes.c_char_p
+    lib.sgp_strerror.argtypes = [i]
+    lib.sgp_last_error.restype = ctypes.c_char_p
+    for name in EXPORTS:
+        if name not in ("sgp_strerror", "sgp_last_error"):
+            getattr(lib, name).restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def default_params() -> dict:
+    lib = load()
+    p = _Params()
+    lib.sgp_params_init(ctypes.byref(p))
+    return {name: getattr(p, name) for name, _ in _Params._fields_ if name not in ("f0", "trace")}
+
+
+def _make_params(kw: dict, trace_rows: int | None):
+    lib = load()
+    p = _Params()
+    lib.sgp_params_init(ctypes.byref(p))
+    keep = []
+    for k, v in kw.items():
+        if k == "f0":
+            _check_dev(v, "f0")
+            p.f0 = v.data_ptr()
+            keep.append(v)
+        elif k == "trace":
+            continue
+        elif not hasattr(p, k):
+            raise TypeError(f"unknown parameter {k}")
+        else:
+            setattr(p, k, v)
+    if "f0" in kw and "init" not in kw:
+        p.init = INIT_USER
+    trace = None
+    if trace_rows:
+        trace = np.zeros((trace_rows, TRACE_COLS), dtype=np.float64)
+        p.trace = trace.ctypes.data
+    return p, trace, keep
+
+
+def _check_dev(t, name):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype != torch.float32 or not t.is_contiguous():
+        raise TypeError(f"{name} must be contiguous float32")
+
+
+def _stream(stream):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _raise(rc):
+    lib = load()
+    if rc < 0:
+        raise SgpError(rc, lib.sgp_last_error().decode() or lib.sgp_strerror(rc).decode())
+
+
+def _report(rep: _Report, rc: int, trace):
+    out = {name: getattr(rep, name) for name, _ in _Report._fields_}
+    out["reason"] = REASONS.get(rep.stop_reason, str(rep.stop_reason))
+    out["rc"] = rc
+    if trace is not None:
+        n = rep.iters + 1
+        out["trace"] = {f: trace[:n, c].copy() for c, f in enumerate(TRACE_FIELDS)}
+    return out
+
+
+def _bconst(b, p):
+    arr = (ctypes.c_float * 8)()
+    vals = np.broadcast_to(np.asarray(b, dtype=np.float32).ravel() if np.ndim(b) else np.float32(b), (p,))
+    for j in range(p):
+        arr[j] = float(vals[j])
+    return arr
+
+
+def _solve_single(fn, g, psf, b, b_map, f, stream, trace, kw):
+    import torch
+    _check_dev(g, "g")
+    _check_dev(psf, "psf")
+    ny, nx = g.shape[-2], g.shape[-1]
+    if b_map is not None:
+        _check_dev(b_map, "b_map")
+    if f is None:
+        f = torch.empty((ny, nx), dtype=torch.float32, device=g.device)
+    _check_dev(f, "f")
+    prm, tr, keep = _make_params(kw, (kw.get("max_iter", 1000) + 1) if trace else None)
+    rep = _Report()
+    rc = fn(ctypes.c_void_p(g.data_ptr()), ctypes.c_void_p(psf.data_ptr()),
+            ctypes.c_void_p(b_map.data_ptr() if b_map is not None else 0), ctypes.c_float(float(b)),
+            ny, nx, ctypes.byref(prm), ctypes.c_void_p(f.data_ptr()), ctypes.byref(rep), _stream(stream))
+    _raise(rc)
+    return f, _report(rep, rc, tr)
+
+
+def sgp_deconv(g, psf, b=0.0, *, b_map=None, f=None, stream=None, trace=False, **params):
+    """SGP single-image deconvolution; returns (f, report)."""
+    return _solve_single(load().sgp_deconv, g, psf, b, b_map, f, stream, trace, params)
+
+
+def rl_deconv(g, psf, b=0.0, *, b_map=None, f=None, stream=None, trace=False, **params):
+    """Richardson-Lucy single-image deconvolution; returns (f, report)."""
+    return _solve_single(load().rl_deconv, g, psf, b, b_map, f, stream, trace, params)
+
+
+def _solve_stack(fn, g, psf, b, b_map, f, stream, trace, kw, domain=None):
+    import torch
+    _check_dev(g, "g")
+    _check_dev(psf, "psf")
+    if g.dim() == 2:
+        g = g.unsqueeze(0)
+    if psf.dim() == 2:
+        psf = psf.unsqueeze(0)
+    p, ny, nx = g.shape
+    if b_map is not None:
+        _check_dev(b_map, "b_map")
+    NY, NX, oy, ox = domain if domain is not None else (ny, nx, 0, 0)
+    if f is None:
+        f = torch.empty((NY, NX), dtype=torch.float32, device=g.device)
+    _check_dev(f, "f")
+    prm, tr, keep = _make_params(kw, (kw.get("max_iter", 1000) + 1) if trace else None)
+    rep = _Report()
+    bc = _bconst(b, p)
+    args = [ctypes.c_void_p(g.data_ptr()), ctypes.c_void_p(psf.data_ptr()),
+            ctypes.c_void_p(b_map.data_ptr() if b_map is not None else 0), ctypes.cast(bc, ctypes.c_void_p),
+            p, ny, nx]
+    if domain is not None:
+        args += [NY, NX, oy, ox]
+    rc = fn(*args, ctypes.byref(prm), ctypes.c_void_p(f.data_ptr()), ctypes.byref(rep), _stream(stream))
+    _raise(rc)
+    return f, _report(rep, rc, tr)
+
+
+def sgp_multi_deconv(g, psf, b, *, b_map=None, f=None, stream=None, trace=False, **params):
+    """SGP for p images [p, ny, nx] of one object; returns (f, report)."""
+    return _solve_stack(load().sgp_multi_deconv, g, psf, b, b_map, f, stream, trace, params)
+
+
+def rl_multi_deconv(g, psf, b, *, b_map=None, f=None, stream=None, trace=False, **params):
+    """Multiple-image RL; returns (f, report)."""
+    return _solve_stack(load().rl_multi_deconv, g, psf, b, b_map, f, stream, trace, params)
+
+
+def sgp_boundary_deconv(g, psf, b, domain, *, b_map=None, f=None, stream=None, trace=False, **params):
+    """SGP with boundary-effect correction; domain = (NY, NX, oy, ox)."""
+    return _solve_stack(load().sgp_boundary_deconv, g, psf, b, b_map, f, stream, trace, params, domain)
+
+
+def rl_boundary_deconv(g, psf, b, domain, *, b_map=None, f=None, stream=None, trace=False, **params):
+    """RL with boundary-effect correction; domain = (NY, NX, oy, ox)."""
+    return _solve_stack(load().rl_boundary_deconv, g, psf, b, b_map, f, stream, trace, params, domain)
+
+
+def apply_operator(psf, x, adjoint=False, out=None, stream=None):
+    """out = A x (or A^T x) for the periodic operator of a unit-volume PSF."""
+    import torch
+    _check_dev(psf, "psf")
+    _check_dev(x, "x")
+    ny, nx = x.shape
+    if out is None:
+        out = torch.empty_like(x)
+    rc = load().sgp_apply_operator(ctypes.c_void_p(psf.data_ptr()), ctypes.c_void_p(x.data_ptr()),
+                                   ny, nx, 1 if adjoint else 0, ctypes.c_void_p(out.data_ptr()),
+                                   _stream(stream))
+    _raise(rc)
+    return out
+
+
+def release_cache():
+    return load().sgp_release_cache()

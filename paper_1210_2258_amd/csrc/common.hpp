@@ -1,0 +1,119 @@
+// Shared host/device definitions of the SGP deconvolution library.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace sgp {
+
+constexpr int kMaxP = 8;          // images per problem (multi-image deconvolution)
+constexpr int kMaxCand = 41;      // Armijo candidates theta^0 .. theta^40
+constexpr int kTraceCols = 20;    // columns of the per-iteration trace
+constexpr int kTile = 8;          // rows per block of the spectrum layout
+constexpr int kRP = 4;            // row pairs per row-kernel workgroup (kTile / 2)
+constexpr int kPixThreads = 256;  // threads of the pointwise kernels
+constexpr int kMaxPixBlocks = 1024;
+
+// stop-rule bits (Sect. 3.3)
+enum { STOP_FIXED = 1, STOP_CONV = 2, STOP_DISCREPANCY = 4, STOP_RMSE = 8 };
+// stop reasons reported back
+enum { REASON_MAXITER = 0, REASON_CONV = 1, REASON_DISCREPANCY = 2, REASON_RMSE = 3,
+       REASON_STATIONARY = 4, REASON_ARMIJO = 5, REASON_NUMERIC = 6 };
+// start options (Sect. 3.1)
+enum { INIT_FLAT = 0, INIT_ZERO = 1, INIT_DATA = 2, INIT_USER = 3 };
+// data validation flags
+enum { FLAG_BAD_DATA = 1, FLAG_BAD_PSF = 2, FLAG_BAD_BG = 4 };
+
+// Trace columns, one row per iteration (the same fields as the oracle's log).
+enum { TR_K = 0, TR_ALPHA, TR_GD, TR_BACK, TR_LAM, TR_J, TR_A, TR_C1, TR_C2, TR_E,
+       TR_A1, TR_A2, TR_BR1, TR_BR2, TR_ALT, TR_TAU, TR_ALPHA_NEXT, TR_FLUXMU };
+
+// Device-resident solver state: parameters, scalars and flags.  Written by
+// the single finalising thread of each reduction, read by every workgroup of
+// the following kernels.
+struct DevState {
+  // parameters
+  int max_iter, stop, m_alpha, n_bb2_only, auto_bounds, max_backtracks, flux_constraint, trace_on;
+  int init, p;
+  double tol, disc_target, beta, theta, alpha0, alpha_min, alpha_max, tau1, L1p, L2p, sigma_R, flux;
+  // iteration scalars
+  double alpha, tau, L1, L2, J, Jprev, gd, lam, flux_c;
+  double Q[8];
+  int nQ, k, done, reason, need_more, nback, total_back, flags;
+  double lam_tab[kMaxCand];
+  double psf_scale[kMaxP];
+  double norm_disc;  // 2 / (p |S|), Eq. (discrepancy)
+  double cflat, ymin, ymax;
+  double mu;         // flux-projection multiplier
+  double* trace;     // [max_iter + 1][kTraceCols] or null
+};
+
+// Kernel arguments (passed by value).
+struct Args {
+  int NY, NX;            // FFT domain Sbar
+  int ny, nx, oy, ox;    // observed window S inside Sbar
+  int p;                 // number of images
+  int nblk;              // workgroups taking part in this launch's reduction
+  int iter;              // 1: iteration kernel, exits when the solver is done
+  int flag;              // op-specific switch
+  int jsel;              // op-specific image index
+  const float* g;        // [p][ny][nx]
+  const float* bmap;     // [p][ny][nx] or null
+  float b[kMaxP];        // constant backgrounds (used when bmap is null)
+  float* f;              // [NY][NX] iterate
+  float* grad;           // [NY][NX]
+  float* d;              // [NY][NX]
+  const float* invw;     // [NY][NX] M_R / alpha, or null for the scalar invw_s
+  float invw_s;
+  float* Af;             // [p][ny][nx]
+  float* Ad;             // [p][ny][nx]
+  float2* spec;          // [p][NY * NX / 2] row-blocked half spectra
+  float2* khat;          // [p][NY * NX / 2] transfer functions / (NY NX)
+  float2* knyq;          // [p][NY]       Nyquist column of each transfer function
+  const float* psf;      // [p][NY][NX]
+  float* aux;            // [p][NY][NX] scratch field (boundary weights)
+  const float* src;      // generic input field
+  const float2* tw_row;  // twiddles for length NX
+  const float2* tw_col;  // twiddles for length NY
+  double* part;          // reduction partials [slot][nblk]
+  unsigned* counter;     // arrival counter of the reduction
+  DevState* st;
+};
+
+// Row-kernel operations: pointwise work fused into the row FFT passes.
+enum RowOp {
+  ROW_PSF = 0,      // fwd: shifted, scaled PSF  -> spec[j]
+  ROW_MASKS,        // fwd: M_S                   -> spec[0]
+  ROW_STORE,        // inv: spec[j]               -> aux[j]
+  ROW_FIELD,        // fwd: src                   -> spec[0]
+  ROW_RATIO,        // inv+fwd: A_j f -> rho_j, KL (RL step / setup)
+  ROW_RLUPD,        // inv+fwd: RL update of f    -> spec[0]
+  ROW_SETUPGRAD,    // inv: gradient at f0, min/max of one RL step (bounds)
+  ROW_DIR,          // fwd: scaling, projection, direction d -> spec[0]
+  ROW_AD,           // inv: A_j d, Armijo candidates lambda = 1, theta
+  ROW_UPD,          // fwd: f += lam d, A_j f += lam A_j d, rho_j -> spec[j]
+  ROW_GRAD,         // inv: new gradient, BB sums
+  ROW_NOPS
+};
+
+// Column-kernel modes.
+enum ColMode {
+  COL_FWD = 0,      // spec[j] -> khat[j], knyq[j]   (setup)
+  COL_CONV,         // spec[0] -> spec[j] = K_j x (or conj K_j x)
+  COL_CORRSUM,      // spec[j] -> spec[0] = sum_j conj(K_j) x_j
+  COL_NMODES
+};
+
+// Pointwise (non-FFT) kernels.
+enum PixOp {
+  PIX_VALIDATE = 0, // g, b checks
+  PIX_PSFSUM,       // PSF sum, sign and finiteness (image jsel)
+  PIX_FLATSUM,      // sum_S (g - b) over all images -> flat start value
+  PIX_INITF,        // write the start image
+  PIX_INVW,         // boundary: R mask and M_R / alpha from aux (alpha_j)
+  PIX_ARMIJO_MORE,  // further Armijo candidates theta^2 ..
+  PIX_NOPS
+};
+
+__host__ __device__ inline long long spec_elems(int NY, int NX) { return (long long)NY * (NX / 2); }
+
+}  // namespace sgp

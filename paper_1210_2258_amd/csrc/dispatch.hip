@@ -1,0 +1,92 @@
+// Size dispatch and the size-independent pointwise kernels.
+#include "launch.hpp"
+#include "pix.hpp"
+
+#define SGP_SIZES(X) X(16) X(32) X(64) X(128) X(256) X(512) X(1024) X(2048) \
+                     X(80) X(160) X(320) X(640) X(1280)
+
+namespace sgp {
+
+#define SGP_DECL(L)                                                           \
+  void launch_row_##L(int op, dim3 grid, const Args& a, hipStream_t s);       \
+  void launch_col_##L(int mode, int conj, dim3 grid, const Args& a, hipStream_t s); \
+  int col_width_##L();                                                        \
+  int row_threads_##L();                                                      \
+  int col_threads_##L();
+SGP_SIZES(SGP_DECL)
+#undef SGP_DECL
+
+bool size_supported(int L) {
+  switch (L) {
+#define SGP_CASE(L) case L: return true;
+    SGP_SIZES(SGP_CASE)
+#undef SGP_CASE
+    default: return false;
+  }
+}
+
+int col_width(int L) {
+  switch (L) {
+#define SGP_CASE(L) case L: return col_width_##L();
+    SGP_SIZES(SGP_CASE)
+#undef SGP_CASE
+    default: return 0;
+  }
+}
+
+int row_threads(int L) {
+  switch (L) {
+#define SGP_CASE(L) case L: return row_threads_##L();
+    SGP_SIZES(SGP_CASE)
+#undef SGP_CASE
+    default: return 0;
+  }
+}
+
+int col_threads(int L) {
+  switch (L) {
+#define SGP_CASE(L) case L: return col_threads_##L();
+    SGP_SIZES(SGP_CASE)
+#undef SGP_CASE
+    default: return 0;
+  }
+}
+
+void launch_row(int L, int op, dim3 grid, const Args& a, hipStream_t s) {
+  switch (L) {
+#define SGP_CASE(L) case L: launch_row_##L(op, grid, a, s); break;
+    SGP_SIZES(SGP_CASE)
+#undef SGP_CASE
+    default: break;
+  }
+}
+
+void launch_col(int L, int mode, int conj, dim3 grid, const Args& a, hipStream_t s) {
+  switch (L) {
+#define SGP_CASE(L) case L: launch_col_##L(mode, conj, grid, a, s); break;
+    SGP_SIZES(SGP_CASE)
+#undef SGP_CASE
+    default: break;
+  }
+}
+
+void launch_pix(int op, dim3 grid, const Args& a, hipStream_t s) {
+  const dim3 blk(kPixThreads);
+  switch (op) {
+#define SGP_PIX_CASE(OPV) case OPV: hipLaunchKernelGGL((pix_kernel<OPV>), grid, blk, 0, s, a); break;
+    SGP_PIX_CASE(PIX_VALIDATE)
+    SGP_PIX_CASE(PIX_PSFSUM)
+    SGP_PIX_CASE(PIX_FLATSUM)
+    SGP_PIX_CASE(PIX_INITF)
+    SGP_PIX_CASE(PIX_INVW)
+    SGP_PIX_CASE(PIX_ARMIJO_MORE)
+#undef SGP_PIX_CASE
+    default: break;
+  }
+}
+
+void launch_twiddle(float2* tw, int L, hipStream_t s) {
+  hipLaunchKernelGGL(twiddle_kernel, dim3((L + 255) / 256), dim3(256), 0, s, tw, L);
+}
+
+}  // namespace sgp

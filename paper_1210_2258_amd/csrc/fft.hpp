@@ -1,0 +1,159 @@
+// Stockham FFTs staged in LDS for gfx950 (wave64).
+//
+// A length-L complex transform is split into radix-8/4/5 passes.  Pass p with
+// radix R and stride Ns (product of the earlier radices) reads butterfly j's
+// inputs at j + i*L/R, applies the twiddles W_{Ns R}^{i (j mod Ns)}, runs an
+// R-point DFT in registers and writes the outputs at
+// (j / Ns) * Ns * R + (j mod Ns) + i*Ns (the self-sorting Stockham order, so
+// the result lands in natural order with no bit reversal).  Each pass stages
+// its reads in registers, so one LDS buffer per transform is enough.
+//
+// Several transforms share a workgroup; thread t works on transform t / TF
+// with lane t % TF.  Twiddles come from a per-length table
+// tw[m] = exp(-2 pi i m / L) built once per plan in double precision and
+// rounded to float.  Inverse transforms use conj(FFT(conj(x))).
+#pragma once
+#include <hip/hip_runtime.h>
+
+namespace sgp {
+
+__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+  return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ float2 cmulc(float2 a, float2 b) {  // a * conj(b)
+  return make_float2(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y);
+}
+__device__ __forceinline__ float2 cconj(float2 a) { return make_float2(a.x, -a.y); }
+__device__ __forceinline__ float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
+__device__ __forceinline__ float2 mul_mi(float2 a) { return make_float2(a.y, -a.x); }  // a * (-i)
+__device__ __forceinline__ float2 mul_pi(float2 a) { return make_float2(-a.y, a.x); }  // a * (+i)
+
+// ------------------------------------------------------------------ plans
+// L: transform length; E: elements per thread (a multiple of every radix);
+// TF = L / E threads per transform; R[]: radices in pass order.
+template <int L> struct FftPlan;
+#define SGP_FFT_PLAN(L_, E_, NP_, R0, R1, R2, R3)                            \
+  template <> struct FftPlan<L_> {                                          \
+    static constexpr int len = L_, E = E_, TF = L_ / E_, NP = NP_;          \
+    static constexpr int r0 = R0, r1 = R1, r2 = R2, r3 = R3;                \
+  };
+SGP_FFT_PLAN(16, 4, 2, 4, 4, 1, 1)
+SGP_FFT_PLAN(32, 8, 2, 8, 4, 1, 1)
+SGP_FFT_PLAN(64, 8, 2, 8, 8, 1, 1)
+SGP_FFT_PLAN(128, 8, 3, 8, 4, 4, 1)
+SGP_FFT_PLAN(256, 8, 3, 8, 8, 4, 1)
+SGP_FFT_PLAN(512, 8, 3, 8, 8, 8, 1)
+SGP_FFT_PLAN(1024, 8, 4, 8, 8, 4, 4)
+SGP_FFT_PLAN(2048, 16, 4, 8, 8, 8, 4)
+SGP_FFT_PLAN(4096, 16, 4, 8, 8, 8, 8)
+SGP_FFT_PLAN(80, 20, 3, 5, 4, 4, 1)
+SGP_FFT_PLAN(160, 40, 3, 5, 8, 4, 1)
+SGP_FFT_PLAN(320, 40, 3, 5, 8, 8, 1)
+SGP_FFT_PLAN(640, 40, 4, 5, 8, 4, 4)
+SGP_FFT_PLAN(1280, 40, 4, 5, 8, 8, 4)
+SGP_FFT_PLAN(2560, 40, 4, 5, 8, 8, 8)
+#undef SGP_FFT_PLAN
+
+// ------------------------------------------------------------- butterflies
+// Forward DFT of R points held in registers, X_k = sum_n x_n exp(-2 pi i n k / R).
+template <int R> __device__ __forceinline__ void dft(float2* v);
+
+template <> __device__ __forceinline__ void dft<2>(float2* v) {
+  float2 a = v[0], b = v[1];
+  v[0] = cadd(a, b);
+  v[1] = csub(a, b);
+}
+
+template <> __device__ __forceinline__ void dft<4>(float2* v) {
+  float2 t0 = cadd(v[0], v[2]), t1 = csub(v[0], v[2]);
+  float2 t2 = cadd(v[1], v[3]), t3 = mul_mi(csub(v[1], v[3]));
+  v[0] = cadd(t0, t2);
+  v[2] = csub(t0, t2);
+  v[1] = cadd(t1, t3);
+  v[3] = csub(t1, t3);
+}
+
+template <> __device__ __forceinline__ void dft<8>(float2* v) {
+  // two 4-point DFTs on even / odd samples, combined with W8^k
+  float2 e[4] = {v[0], v[2], v[4], v[6]};
+  float2 o[4] = {v[1], v[3], v[5], v[7]};
+  dft<4>(e);
+  dft<4>(o);
+  const float h = 0.70710678118654752440f;
+  float2 w1 = make_float2(h * (o[1].x + o[1].y), h * (o[1].y - o[1].x));   // o1 * e^{-i pi/4}
+  float2 w2 = mul_mi(o[2]);                                                // o2 * e^{-i pi/2}
+  float2 w3 = make_float2(h * (o[3].y - o[3].x), -h * (o[3].x + o[3].y));  // o3 * e^{-3 i pi/4}
+  v[0] = cadd(e[0], o[0]);
+  v[4] = csub(e[0], o[0]);
+  v[1] = cadd(e[1], w1);
+  v[5] = csub(e[1], w1);
+  v[2] = cadd(e[2], w2);
+  v[6] = csub(e[2], w2);
+  v[3] = cadd(e[3], w3);
+  v[7] = csub(e[3], w3);
+}
+
+template <> __device__ __forceinline__ void dft<5>(float2* v) {
+  const float c1 = 0.30901699437494742410f;   // cos(2 pi / 5)
+  const float c2 = -0.80901699437494742410f;  // cos(4 pi / 5)
+  const float s1 = 0.95105651629515357212f;   // sin(2 pi / 5)
+  const float s2 = 0.58778525229247312917f;   // sin(4 pi / 5)
+  float2 a1 = cadd(v[1], v[4]), a2 = cadd(v[2], v[3]);
+  float2 b1 = csub(v[1], v[4]), b2 = csub(v[2], v[3]);
+  float2 x0 = v[0];
+  float2 t1 = make_float2(x0.x + c1 * a1.x + c2 * a2.x, x0.y + c1 * a1.y + c2 * a2.y);
+  float2 t2 = make_float2(x0.x + c2 * a1.x + c1 * a2.x, x0.y + c2 * a1.y + c1 * a2.y);
+  float2 u1 = make_float2(s1 * b1.x + s2 * b2.x, s1 * b1.y + s2 * b2.y);
+  float2 u2 = make_float2(s2 * b1.x - s1 * b2.x, s2 * b1.y - s1 * b2.y);
+  v[0] = make_float2(x0.x + a1.x + a2.x, x0.y + a1.y + a2.y);
+  v[1] = cadd(t1, mul_mi(u1));
+  v[4] = cadd(t1, mul_pi(u1));
+  v[2] = cadd(t2, mul_mi(u2));
+  v[3] = cadd(t2, mul_pi(u2));
+}
+
+// ------------------------------------------------------------------ passes
+template <int L, int TF, int R, int NS>
+__device__ __forceinline__ void stockham_pass(float2* buf, int lane, const float2* __restrict__ tw) {
+  constexpr int NB = L / R;
+  constexpr int PER = NB / TF;
+  static_assert(PER * TF == NB, "threads per transform must divide the butterfly count");
+  float2 v[PER][R];
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int j = lane + q * TF;
+#pragma unroll
+    for (int i = 0; i < R; ++i) v[q][i] = buf[j + i * NB];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int j = lane + q * TF;
+    const int k = j % NS;
+    if constexpr (NS > 1) {
+#pragma unroll
+      for (int i = 1; i < R; ++i) v[q][i] = cmul(v[q][i], tw[i * k * (L / (NS * R))]);
+    }
+    dft<R>(v[q]);
+    const int base = (j / NS) * NS * R + k;
+#pragma unroll
+    for (int i = 0; i < R; ++i) buf[base + i * NS] = v[q][i];
+  }
+  __syncthreads();
+}
+
+// Forward FFT of buf[0..L) in place (natural order in and out).  Every thread
+// of the workgroup must call this (it contains barriers).
+template <int L>
+__device__ __forceinline__ void fft_lds(float2* buf, int lane, const float2* __restrict__ tw) {
+  using P = FftPlan<L>;
+  constexpr int TF = P::TF;
+  stockham_pass<L, TF, P::r0, 1>(buf, lane, tw);
+  stockham_pass<L, TF, P::r1, P::r0>(buf, lane, tw);
+  if constexpr (P::NP > 2) stockham_pass<L, TF, P::r2, P::r0 * P::r1>(buf, lane, tw);
+  if constexpr (P::NP > 3) stockham_pass<L, TF, P::r3, P::r0 * P::r1 * P::r2>(buf, lane, tw);
+}
+
+}  // namespace sgp

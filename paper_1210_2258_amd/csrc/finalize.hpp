@@ -1,0 +1,190 @@
+// Scalar control of the solvers, run on device by the thread that finalises a
+// reduction.  Each function follows one step of the method:
+//   fin_dir      Algorithm 1, steps 2-3: grad^T d and the stationarity test
+//   fin_armijo   Algorithm 1, steps 4-5: first lambda = theta^m passing
+//                J(f + lambda d) <= J(f) + beta lambda grad^T d
+//   fin_update   Algorithm 1, step 6 and the stopping rules of Sect. 3.3
+//   fin_bb       Sect. 2.1: Eqs. (BB1), (BB2), safeguards and Eq. (alphadef)
+//   fin_bounds   Sect. 3.2: (L1, L2) from one RL step
+//   fin_rl       Eq. (RL): stopping rules evaluated on J(f^(k))
+#pragma once
+#include "common.hpp"
+
+namespace sgp {
+
+__device__ inline double* trace_row(DevState* st, int k) {
+  if (!st->trace_on || !st->trace || k < 0 || k > st->max_iter) return nullptr;
+  return st->trace + (size_t)k * kTraceCols;
+}
+
+__device__ inline void fin_dir(DevState* st, double gd) {
+  st->gd = gd;
+  double* tr = trace_row(st, st->k);
+  if (tr) {
+    tr[TR_K] = st->k;
+    tr[TR_ALPHA] = st->alpha;
+    tr[TR_GD] = gd;
+    tr[TR_FLUXMU] = st->mu;
+  }
+  if (!__builtin_isfinite(gd)) {
+    st->done = 1;
+    st->reason = REASON_NUMERIC;
+  } else if (gd == 0.0) {
+    st->done = 1;
+    st->reason = REASON_STATIONARY;
+  }
+}
+
+// dJ[m] = J(f + theta^(m0+m) d) - J(f) for m = 0..n-1.
+__device__ inline void fin_armijo(DevState* st, const double* dJ, int m0, int n) {
+  st->need_more = 0;
+  for (int m = 0; m < n; ++m) {
+    const int mm = m0 + m;
+    if (mm > st->max_backtracks) break;
+    const double lam = st->lam_tab[mm];
+    if (!__builtin_isfinite(dJ[m])) {
+      st->done = 1;
+      st->reason = REASON_NUMERIC;
+      return;
+    }
+    if (dJ[m] <= st->beta * lam * st->gd) {
+      st->lam = lam;
+      st->nback = mm;
+      return;
+    }
+  }
+  if (m0 + n <= st->max_backtracks) {
+    st->need_more = 1;
+  } else {
+    st->done = 1;
+    st->reason = REASON_ARMIJO;
+  }
+}
+
+__device__ inline void fin_update(DevState* st, double Jn) {
+  const int k = st->k;
+  double* tr = trace_row(st, k);
+  if (tr) {
+    tr[TR_BACK] = st->nback;
+    tr[TR_LAM] = st->lam;
+    tr[TR_J] = Jn;
+  }
+  st->Jprev = st->J;
+  st->J = Jn;
+  st->k = k + 1;
+  st->total_back += st->nback;
+  if (!__builtin_isfinite(Jn)) {
+    st->done = 1;
+    st->reason = REASON_NUMERIC;
+  } else if ((st->stop & STOP_DISCREPANCY) && st->norm_disc * Jn <= st->disc_target) {
+    st->done = 1;
+    st->reason = REASON_DISCREPANCY;
+  } else if ((st->stop & STOP_CONV) && fabs(Jn - st->Jprev) <= st->tol * st->Jprev) {
+    st->done = 1;
+    st->reason = REASON_CONV;
+  } else if (st->k >= st->max_iter) {
+    st->done = 1;
+    st->reason = REASON_MAXITER;
+  }
+}
+
+// a = s'D^-2 s, c1 = s'D^-1 z, c2 = s'D z, e = z'D^2 z
+__device__ inline void fin_bb(DevState* st, double a, double c1, double c2, double e) {
+  const double alpha = st->alpha;
+  double a1, a2;
+  int br1, br2;
+  if (c1 <= 0) { a1 = fmin(10.0 * alpha, st->alpha_max); br1 = 0; }
+  else { a1 = fmin(st->alpha_max, fmax(st->alpha_min, a / c1)); br1 = 1; }
+  if (c2 <= 0) { a2 = fmin(10.0 * alpha, st->alpha_max); br2 = 0; }
+  else { a2 = fmin(st->alpha_max, fmax(st->alpha_min, c2 / e)); br2 = 1; }
+  // memory of the last m_alpha values of alpha^(2)
+  if (st->nQ < st->m_alpha) {
+    st->Q[st->nQ++] = a2;
+  } else {
+    for (int i = 1; i < st->m_alpha; ++i) st->Q[i - 1] = st->Q[i];
+    st->Q[st->m_alpha - 1] = a2;
+  }
+  double qmin = st->Q[0];
+  for (int i = 1; i < st->nQ; ++i) qmin = fmin(qmin, st->Q[i]);
+  const int kdone = st->k;  // iterations completed, i.e. k + 1 of the step just taken
+  int alt;
+  double next;
+  if (kdone <= st->n_bb2_only) { next = qmin; alt = 0; }
+  else if (a2 / a1 <= st->tau) { next = qmin; st->tau *= 0.9; alt = 1; }
+  else { next = a1; st->tau *= 1.1; alt = 2; }
+  double* tr = trace_row(st, kdone - 1);
+  if (tr) {
+    tr[TR_A] = a; tr[TR_C1] = c1; tr[TR_C2] = c2; tr[TR_E] = e;
+    tr[TR_A1] = a1; tr[TR_A2] = a2; tr[TR_BR1] = br1; tr[TR_BR2] = br2;
+    tr[TR_ALT] = alt; tr[TR_TAU] = st->tau; tr[TR_ALPHA_NEXT] = next;
+  }
+  if (!__builtin_isfinite(next)) {
+    st->done = 1;
+    st->reason = REASON_NUMERIC;
+  }
+  st->alpha = next;
+}
+
+__device__ inline void fin_bounds(DevState* st, double ymin, double ymax) {
+  st->ymin = ymin;
+  st->ymax = ymax;
+  if (st->auto_bounds) {
+    if (ymax / ymin < 50.0) { st->L1 = ymin / 10.0; st->L2 = ymax * 10.0; }
+    else { st->L1 = ymin; st->L2 = ymax; }
+  } else {
+    st->L1 = st->L1p;
+    st->L2 = st->L2p;
+  }
+  st->alpha = st->alpha0;
+  st->tau = st->tau1;
+  st->nQ = 0;
+  st->k = 0;
+  st->total_back = 0;
+  st->nback = 0;
+  st->lam = 1.0;
+  double lam = 1.0;
+  for (int m = 0; m < kMaxCand; ++m) {  // the backtracking sequence lambda <- theta lambda
+    st->lam_tab[m] = lam;
+    lam *= st->theta;
+  }
+  if (!__builtin_isfinite(st->J)) {
+    st->done = 1;
+    st->reason = REASON_NUMERIC;
+  } else if ((st->stop & STOP_DISCREPANCY) && st->norm_disc * st->J <= st->disc_target) {
+    st->done = 1;
+    st->reason = REASON_DISCREPANCY;
+  } else if (st->max_iter <= 0) {
+    st->done = 1;
+    st->reason = REASON_MAXITER;
+  }
+}
+
+// RL: J(f^(k)) has just been formed; decide whether f^(k) is returned.
+__device__ inline void fin_rl(DevState* st, double J) {
+  const int k = st->k;
+  double* tr = trace_row(st, k);
+  if (tr) {
+    tr[TR_K] = k;
+    tr[TR_J] = J;
+  }
+  const double Jprev = st->J;
+  st->Jprev = Jprev;
+  st->J = J;
+  if (!__builtin_isfinite(J)) {
+    st->done = 1;
+    st->reason = REASON_NUMERIC;
+  } else if ((st->stop & STOP_DISCREPANCY) && st->norm_disc * J <= st->disc_target) {
+    st->done = 1;
+    st->reason = REASON_DISCREPANCY;
+  } else if ((st->stop & STOP_CONV) && k > 0 && fabs(J - Jprev) <= st->tol * Jprev) {
+    st->done = 1;
+    st->reason = REASON_CONV;
+  } else if (k >= st->max_iter) {
+    st->done = 1;
+    st->reason = REASON_MAXITER;
+  } else {
+    st->k = k + 1;
+  }
+}
+
+}  // namespace sgp

@@ -1,0 +1,435 @@
+// Device kernels of the SGP / RL deconvolution path.
+//
+// Spectrum layout ("row-blocked"): the half spectrum of a real NY x NX field
+// after the row transforms, or of a 2D transform, is stored as NY x NX/2
+// complex values.  Packed column 0 holds (DC, Nyquist) of each real row, both
+// real.  Element (y, kx) lives at ((y / 8) * (NX/2) + kx) * 8 + (y % 8), so a
+// row kernel that owns 8 rows writes one contiguous block, and a column kernel
+// that owns C columns reads 8*C contiguous values per block of rows.
+//
+// Row kernels own 8 rows (4 pairs).  Two real rows a, b travel through one
+// complex FFT as z = a + i b; the half spectra are separated with
+// A[k] = (Z[k] + conj Z[L-k]) / 2, B[k] = (Z[k] - conj Z[L-k]) / (2 i).
+// Pointwise work of the solver runs between the inverse and forward row
+// transforms, so every field is read and written once per kernel.
+//
+// Column kernels own C packed columns: forward FFT along y, multiplication by
+// the transfer function (already divided by NY*NX), inverse FFT.  Column 0
+// carries two real sequences (DC and Nyquist columns) and is split with the
+// same even/odd rule before multiplying by its two transfer functions.
+#pragma once
+#include "common.hpp"
+#include "fft.hpp"
+#include "finalize.hpp"
+#include "reduce.hpp"
+
+namespace sgp {
+
+__device__ __forceinline__ long long sidx(int y, int kx, int NXh) {
+  return ((long long)(y >> 3) * NXh + kx) * 8 + (y & 7);
+}
+
+// ------------------------------------------------------------- op traits
+__host__ __device__ constexpr bool row_has_inv(int op) {
+  return op == ROW_STORE || op == ROW_RATIO || op == ROW_RLUPD || op == ROW_SETUPGRAD ||
+         op == ROW_AD || op == ROW_GRAD;
+}
+__host__ __device__ constexpr bool row_has_fwd(int op) {
+  return op == ROW_PSF || op == ROW_MASKS || op == ROW_FIELD || op == ROW_RATIO ||
+         op == ROW_RLUPD || op == ROW_DIR || op == ROW_UPD;
+}
+__host__ __device__ constexpr int row_nslots(int op) {
+  return op == ROW_RATIO ? 1 : op == ROW_SETUPGRAD ? 2 : op == ROW_DIR ? 1 :
+         op == ROW_AD ? 2 : op == ROW_UPD ? 1 : op == ROW_GRAD ? 4 : 0;
+}
+// image index of the spectrum read / written
+__host__ __device__ constexpr bool row_per_image(int op) {
+  return op == ROW_PSF || op == ROW_STORE || op == ROW_RATIO || op == ROW_AD || op == ROW_UPD;
+}
+
+struct Pix {
+  const Args& a;
+  int j;
+  __device__ Pix(const Args& a_, int j_) : a(a_), j(j_) {}
+  __device__ bool inS(int y, int x) const {
+    return (unsigned)(y - a.oy) < (unsigned)a.ny && (unsigned)(x - a.ox) < (unsigned)a.nx;
+  }
+  __device__ long long s_of(int y, int x) const {
+    return (long long)j * a.ny * a.nx + (long long)(y - a.oy) * a.nx + (x - a.ox);
+  }
+  __device__ float bg(long long s) const { return a.bmap ? a.bmap[s] : a.b[j]; }
+  __device__ float w(long long pix) const { return a.invw ? a.invw[pix] : a.invw_s; }
+};
+
+// KL term g ln(g / y) + y - g (y when g = 0), Eq. (divergence), in FP64.
+__device__ __forceinline__ double kl_term(float g, float y) {
+  const double gd = g, yd = y;
+  return g > 0.f ? gd * log(gd / yd) + yd - gd : yd;
+}
+
+// One pixel of the pointwise stage.  v: result of the inverse transform at
+// this pixel (conv / corr value); returns the value fed to the forward
+// transform.  acc: per-thread FP64 accumulators.
+template <int OP, int NS>
+__device__ __forceinline__ float row_point(const Args& a, const DevState* st, int j, int y, int x,
+                                           float v, double (&acc)[NS > 0 ? NS : 1]) {
+  Pix P(a, j);
+  const long long pix = (long long)y * a.NX + x;
+  if constexpr (OP == ROW_PSF) {
+    // K0 = ifftshift(K): K0[y][x] = K[(y + NY/2) % NY][(x + NX/2) % NX], scaled by 1/(sum NY NX)
+    const int ys = (y + a.NY / 2) % a.NY, xs = (x + a.NX / 2) % a.NX;
+    return (float)((double)a.psf[(long long)j * a.NY * a.NX + (long long)ys * a.NX + xs] * st->psf_scale[j]);
+  } else if constexpr (OP == ROW_MASKS) {
+    return P.inS(y, x) ? 1.f : 0.f;
+  } else if constexpr (OP == ROW_STORE) {
+    a.aux[(long long)j * a.NY * a.NX + pix] = v;
+    return 0.f;
+  } else if constexpr (OP == ROW_FIELD) {
+    return a.src[pix];
+  } else if constexpr (OP == ROW_RATIO) {
+    if (!P.inS(y, x)) return 0.f;
+    const long long s = P.s_of(y, x);
+    if (a.flag) a.Af[s] = v;
+    const float g = a.g[s];
+    const float yv = fmaxf(v + P.bg(s), 1e-30f);
+    acc[0] += kl_term(g, yv);
+    return (g - yv) / yv;
+  } else if constexpr (OP == ROW_RLUPD) {
+    const float w = P.w(pix);
+    const float f = a.f[pix];
+    const float fn = w > 0.f ? fmaxf(0.f, f * (1.f + w * v)) : 0.f;
+    a.f[pix] = fn;
+    return fn;
+  } else if constexpr (OP == ROW_SETUPGRAD) {
+    const float w = P.w(pix);
+    const float mr = w > 0.f ? 1.f : 0.f;
+    a.grad[pix] = -mr * v;
+    const float yr = w > 0.f ? a.f[pix] * (1.f + w * v) : 0.f;  // one RL step from f0
+    if (yr > 0.f) {
+      acc[0] = fmin(acc[0], (double)yr);
+      acc[1] = fmax(acc[1], (double)yr);
+    }
+    return 0.f;
+  } else if constexpr (OP == ROW_DIR) {
+    const float f = a.f[pix], gr = a.grad[pix];
+    const float D = P.w(pix) * fminf((float)st->L2, fmaxf((float)st->L1, f));
+    const float z = f - (float)st->alpha * D * gr;
+    const float dd = fmaxf(0.f, z) - f;
+    a.d[pix] = dd;
+    acc[0] += (double)gr * (double)dd;
+    return dd;
+  } else if constexpr (OP == ROW_AD) {
+    if (!P.inS(y, x)) return 0.f;
+    const long long s = P.s_of(y, x);
+    a.Ad[s] = v;
+    const float g = a.g[s];
+    const float yv = fmaxf(a.Af[s] + P.bg(s), 1e-30f);
+#pragma unroll
+    for (int m = 0; m < 2; ++m) {
+      const float t = (float)st->lam_tab[m] * v;
+      double term = t;
+      if (g > 0.f) term -= (double)g * (double)log1pf(t / yv);
+      acc[m] += term;
+    }
+    return 0.f;
+  } else if constexpr (OP == ROW_UPD) {
+    const float lam = (float)st->lam;
+    if (j == 0) a.f[pix] = a.f[pix] + lam * a.d[pix];
+    if (!P.inS(y, x)) return 0.f;
+    const long long s = P.s_of(y, x);
+    const float afn = a.Af[s] + lam * a.Ad[s];
+    a.Af[s] = afn;
+    const float g = a.g[s];
+    const float yv = fmaxf(afn + P.bg(s), 1e-30f);
+    acc[0] += kl_term(g, yv);
+    return (g - yv) / yv;
+  } else if constexpr (OP == ROW_GRAD) {
+    const float w = P.w(pix);
+    const float gn = w > 0.f ? -v : 0.f;
+    const float go = a.grad[pix];
+    a.grad[pix] = gn;
+    const double s = (double)st->lam * (double)a.d[pix];
+    const double z = (double)gn - (double)go;
+    const float fp = a.f[pix];
+    const double D = (double)(w * fminf((float)st->L2, fmaxf((float)st->L1, fp)));
+    if (D > 0) {
+      acc[0] += s * s / (D * D);
+      acc[1] += s * z / D;
+      acc[2] += s * z * D;
+      acc[3] += z * z * D * D;
+    }
+    return 0.f;
+  } else {
+    return 0.f;
+  }
+}
+
+template <int OP>
+__device__ __forceinline__ void row_finalize(DevState* st, const Args& a, const double* t) {
+  if constexpr (OP == ROW_RATIO) {
+    if (a.iter) fin_rl(st, t[0]);
+    else st->J = t[0];
+  } else if constexpr (OP == ROW_SETUPGRAD) {
+    fin_bounds(st, t[0], t[1]);
+  } else if constexpr (OP == ROW_DIR) {
+    fin_dir(st, t[0]);
+  } else if constexpr (OP == ROW_AD) {
+    fin_armijo(st, t, 0, 2);
+  } else if constexpr (OP == ROW_UPD) {
+    fin_update(st, t[0]);
+  } else if constexpr (OP == ROW_GRAD) {
+    fin_bb(st, t[0], t[1], t[2], t[3]);
+  }
+}
+
+struct RowKinds {
+  int op;
+  __device__ int operator()(int s) const {
+    if (op == ROW_SETUPGRAD) return s == 0 ? RED_MIN : RED_MAX;
+    return RED_SUM;
+  }
+};
+
+// ------------------------------------------------------------------ rows
+template <int L, int OP>
+__global__ __launch_bounds__(kRP * FftPlan<L>::TF) void row_kernel(Args a) {
+  using P = FftPlan<L>;
+  constexpr int TF = P::TF;
+  constexpr int NT = kRP * TF;
+  constexpr int HALF = L / 2;
+  constexpr int NS = row_nslots(OP);
+  __shared__ float2 buf[kRP][L];
+  DevState* st = a.st;
+  if (a.iter && st->done) return;
+  const int tid = threadIdx.x;
+  const int j = blockIdx.y;
+  const int y0 = blockIdx.x * kTile;
+  const long long sstride = spec_elems(a.NY, a.NX);
+  float2* spec = a.spec + (row_per_image(OP) ? j : 0) * sstride + (long long)blockIdx.x * HALF * kTile;
+
+  double acc[NS > 0 ? NS : 1];
+  {
+    RowKinds kinds{OP};
+#pragma unroll
+    for (int s = 0; s < (NS > 0 ? NS : 1); ++s) acc[s] = red_identity(kinds(s));
+  }
+
+  if constexpr (row_has_inv(OP)) {
+    const float4* S4 = reinterpret_cast<const float4*>(spec);
+    for (int u = tid; u < HALF * kRP; u += NT) {
+      const int q = u & (kRP - 1), k = u >> 2;
+      const float4 ab = S4[u];  // (A, B) of rows 2q, 2q+1 at column k
+      if (k == 0) {
+        buf[q][0] = make_float2(ab.x, -ab.z);       // conj(A0 + i B0)
+        buf[q][HALF] = make_float2(ab.y, -ab.w);    // conj(AN + i BN)
+      } else {
+        buf[q][k] = make_float2(ab.x - ab.w, -(ab.y + ab.z));      // conj(A + iB)
+        buf[q][L - k] = make_float2(ab.x + ab.w, -(-ab.y + ab.z)); // conj(conj A + i conj B)
+      }
+    }
+    __syncthreads();
+    fft_lds<L>(buf[tid / TF], tid % TF, a.tw_row);
+  }
+
+  for (int u = tid; u < kRP * L; u += NT) {
+    const int q = u / L, x = u % L;
+    const int ya = y0 + 2 * q;
+    float2 v = make_float2(0.f, 0.f);
+    if constexpr (row_has_inv(OP)) {
+      const float2 w = buf[q][x];
+      v = make_float2(w.x, -w.y);
+    }
+    const float ua = row_point<OP, NS>(a, st, j, ya, x, v.x, acc);
+    const float ub = row_point<OP, NS>(a, st, j, ya + 1, x, v.y, acc);
+    if constexpr (row_has_fwd(OP)) buf[q][x] = make_float2(ua, ub);
+  }
+
+  if constexpr (row_has_fwd(OP)) {
+    __syncthreads();
+    fft_lds<L>(buf[tid / TF], tid % TF, a.tw_row);
+    float4* O4 = reinterpret_cast<float4*>(spec);
+    for (int u = tid; u < HALF * kRP; u += NT) {
+      const int q = u & (kRP - 1), k = u >> 2;
+      const float2 zk = buf[q][k];
+      float4 o;
+      if (k == 0) {
+        const float2 zn = buf[q][HALF];
+        o = make_float4(zk.x, zn.x, zk.y, zn.y);
+      } else {
+        const float2 zm = buf[q][L - k];
+        o = make_float4(0.5f * (zk.x + zm.x), 0.5f * (zk.y - zm.y),
+                        0.5f * (zk.y + zm.y), -0.5f * (zk.x - zm.x));
+      }
+      O4[u] = o;
+    }
+  }
+
+  if constexpr (NS > 0) {
+    double tot[NS];
+    const int bid = blockIdx.y * gridDim.x + blockIdx.x;
+    if (grid_reduce<NT, NS>(acc, RowKinds{OP}, a.part, a.counter, a.nblk, bid, tot))
+      row_finalize<OP>(st, a, tot);
+  }
+}
+
+// --------------------------------------------------------------- columns
+template <int LY> struct ColCfg {
+  static constexpr int TF = FftPlan<LY>::TF;
+  static constexpr int C1 = 256 / TF;
+  static constexpr int C2 = 40960 / (LY * 8);
+  static constexpr int C = (C1 < C2 ? C1 : C2) < 1 ? 1 : (C1 < C2 ? C1 : C2);
+  static constexpr int NT = C * TF;
+};
+
+template <int LY, int MODE, int CONJ>
+__global__ __launch_bounds__(ColCfg<LY>::NT) void col_kernel(Args a) {
+  constexpr int TF = FftPlan<LY>::TF;
+  constexpr int C = ColCfg<LY>::C;
+  constexpr int NT = ColCfg<LY>::NT;
+  constexpr int E = LY * C / NT;  // units per thread
+  __shared__ float2 buf[C][LY];
+  DevState* st = a.st;
+  if (a.iter && st->done) return;
+  const int NXh = a.NX / 2;
+  const int kx0 = blockIdx.x * C;
+  const int tid = threadIdx.x;
+  const long long sstride = spec_elems(a.NY, a.NX);
+  const int jin = (MODE == COL_FWD) ? blockIdx.y : 0;
+
+  // unit e of this thread -> (column c, row y) and its offset in the layout
+  auto unit = [&](int e, int& c, int& y, long long& off) {
+    const int u = tid + e * NT;
+    const int yb = u / (8 * C), r = u % (8 * C);
+    c = r >> 3;
+    y = yb * 8 + (r & 7);
+    off = ((long long)yb * NXh + kx0) * 8 + r;
+  };
+  auto load = [&](const float2* S) {
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      int c, y; long long off;
+      unit(e, c, y, off);
+      buf[c][y] = (kx0 + c < NXh) ? S[off] : make_float2(0.f, 0.f);
+    }
+  };
+  const bool has_col0 = (kx0 == 0);
+
+  if constexpr (MODE == COL_FWD) {
+    load(a.spec + jin * sstride);
+    __syncthreads();
+    fft_lds<LY>(buf[tid / TF], tid % TF, a.tw_col);
+    float2* K = a.khat + jin * sstride;
+    float2* KN = a.knyq + (long long)jin * LY;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      int c, y; long long off;
+      unit(e, c, y, off);
+      if (kx0 + c >= NXh) continue;
+      const float2 v = buf[c][y];
+      if (has_col0 && c == 0) {
+        const float2 m = cconj(buf[0][(LY - y) % LY]);
+        K[off] = cscale(cadd(v, m), 0.5f);                   // DC column transfer function
+        KN[y] = cscale(mul_mi(csub(v, m)), 0.5f);            // Nyquist column transfer function
+      } else {
+        K[off] = v;
+      }
+    }
+  } else if constexpr (MODE == COL_CONV) {
+    load(a.spec);
+    __syncthreads();
+    fft_lds<LY>(buf[tid / TF], tid % TF, a.tw_col);
+    float2 x0[E], x1[E];  // spectrum (or its even / odd parts for column 0)
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      int c, y; long long off;
+      unit(e, c, y, off);
+      const float2 v = buf[c][y];
+      if (has_col0 && c == 0) {
+        const float2 m = cconj(buf[0][(LY - y) % LY]);
+        x0[e] = cscale(cadd(v, m), 0.5f);
+        x1[e] = cscale(mul_mi(csub(v, m)), 0.5f);
+      } else {
+        x0[e] = v;
+        x1[e] = make_float2(0.f, 0.f);
+      }
+    }
+    __syncthreads();
+    for (int jo = 0; jo < a.p; ++jo) {
+      const float2* K = a.khat + jo * sstride;
+      const float2* KN = a.knyq + (long long)jo * LY;
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        int c, y; long long off;
+        unit(e, c, y, off);
+        float2 pr = make_float2(0.f, 0.f);
+        if (kx0 + c < NXh) {
+          const float2 kv = K[off];
+          if (has_col0 && c == 0) {
+            const float2 kn = KN[y];
+            const float2 p0 = CONJ ? cmulc(x0[e], kv) : cmul(x0[e], kv);
+            const float2 p1 = CONJ ? cmulc(x1[e], kn) : cmul(x1[e], kn);
+            pr = cadd(p0, mul_pi(p1));
+          } else {
+            pr = CONJ ? cmulc(x0[e], kv) : cmul(x0[e], kv);
+          }
+        }
+        buf[c][y] = cconj(pr);
+      }
+      __syncthreads();
+      fft_lds<LY>(buf[tid / TF], tid % TF, a.tw_col);
+      float2* O = a.spec + jo * sstride;
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        int c, y; long long off;
+        unit(e, c, y, off);
+        if (kx0 + c < NXh) O[off] = cconj(buf[c][y]);
+      }
+      __syncthreads();
+    }
+  } else {  // COL_CORRSUM
+    float2 acc[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) acc[e] = make_float2(0.f, 0.f);
+    for (int ji = 0; ji < a.p; ++ji) {
+      load(a.spec + ji * sstride);
+      __syncthreads();
+      fft_lds<LY>(buf[tid / TF], tid % TF, a.tw_col);
+      const float2* K = a.khat + ji * sstride;
+      const float2* KN = a.knyq + (long long)ji * LY;
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        int c, y; long long off;
+        unit(e, c, y, off);
+        if (kx0 + c >= NXh) continue;
+        const float2 v = buf[c][y];
+        const float2 kv = K[off];
+        if (has_col0 && c == 0) {
+          const float2 m = cconj(buf[0][(LY - y) % LY]);
+          const float2 ev = cscale(cadd(v, m), 0.5f);
+          const float2 od = cscale(mul_mi(csub(v, m)), 0.5f);
+          const float2 kn = KN[y];
+          acc[e] = cadd(acc[e], cadd(cmulc(ev, kv), mul_pi(cmulc(od, kn))));
+        } else {
+          acc[e] = cadd(acc[e], cmulc(v, kv));
+        }
+      }
+      __syncthreads();
+    }
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      int c, y; long long off;
+      unit(e, c, y, off);
+      buf[c][y] = cconj(acc[e]);
+    }
+    __syncthreads();
+    fft_lds<LY>(buf[tid / TF], tid % TF, a.tw_col);
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      int c, y; long long off;
+      unit(e, c, y, off);
+      if (kx0 + c < NXh) a.spec[off] = cconj(buf[c][y]);
+    }
+  }
+}
+
+}  // namespace sgp

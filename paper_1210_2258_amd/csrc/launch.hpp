@@ -1,0 +1,17 @@
+// Host-side launchers of the size-specialised kernels.
+#pragma once
+#include "common.hpp"
+
+namespace sgp {
+
+bool size_supported(int L);
+// columns handled by one column-kernel workgroup for FFT length L
+int col_width(int L);
+int row_threads(int L);
+int col_threads(int L);
+void launch_row(int L, int op, dim3 grid, const Args& a, hipStream_t s);
+void launch_col(int L, int mode, int conj, dim3 grid, const Args& a, hipStream_t s);
+void launch_pix(int op, dim3 grid, const Args& a, hipStream_t s);
+void launch_twiddle(float2* tw, int L, hipStream_t s);
+
+}  // namespace sgp

@@ -1,0 +1,149 @@
+// Pointwise (non-FFT) kernels: validation, PSF normalisation sums, start
+// image, boundary weights, and the rare extra Armijo candidates.
+#pragma once
+#include "common.hpp"
+#include "finalize.hpp"
+#include "reduce.hpp"
+
+namespace sgp {
+
+constexpr int kMoreCand = kMaxCand - 2;  // theta^2 .. theta^40
+
+__host__ __device__ constexpr int pix_nslots(int op) {
+  return op == PIX_VALIDATE ? 3 : op == PIX_PSFSUM ? 3 : op == PIX_FLATSUM ? 2 :
+         op == PIX_ARMIJO_MORE ? kMoreCand : 0;
+}
+
+struct PixKinds {
+  int op;
+  __device__ int operator()(int s) const {
+    if (op == PIX_VALIDATE) return s == 1 ? RED_SUM : RED_MIN;  // min g, #non-finite, min b
+    if (op == PIX_PSFSUM) return s == 1 ? RED_MIN : RED_SUM;    // sum, min, #non-finite
+    return RED_SUM;
+  }
+};
+
+template <int OP>
+__global__ __launch_bounds__(kPixThreads) void pix_kernel(Args a) {
+  constexpr int NS = pix_nslots(OP);
+  DevState* st = a.st;
+  if (a.iter && st->done) return;
+  if constexpr (OP == PIX_ARMIJO_MORE) {
+    if (!st->need_more) return;
+  }
+  const long long nS = (long long)a.ny * a.nx;
+  const long long nF = (long long)a.NY * a.NX;
+  const long long stride = (long long)gridDim.x * kPixThreads;
+  const long long i0 = (long long)blockIdx.x * kPixThreads + threadIdx.x;
+  double acc[NS > 0 ? NS : 1];
+  PixKinds kinds{OP};
+#pragma unroll
+  for (int s = 0; s < (NS > 0 ? NS : 1); ++s) acc[s] = red_identity(kinds(s));
+
+  if constexpr (OP == PIX_VALIDATE) {
+    for (long long i = i0; i < a.p * nS; i += stride) {
+      const float g = a.g[i];
+      if (!__builtin_isfinite(g)) acc[1] += 1.0;
+      else acc[0] = fmin(acc[0], (double)g);
+      if (a.bmap) {
+        const float b = a.bmap[i];
+        if (!__builtin_isfinite(b)) acc[1] += 1.0;
+        else acc[2] = fmin(acc[2], (double)b);
+      }
+    }
+  } else if constexpr (OP == PIX_PSFSUM) {
+    const float* K = a.psf + (long long)a.jsel * nF;
+    for (long long i = i0; i < nF; i += stride) {
+      const float k = K[i];
+      if (!__builtin_isfinite(k)) acc[2] += 1.0;
+      else {
+        acc[0] += k;
+        acc[1] = fmin(acc[1], (double)k);
+      }
+    }
+  } else if constexpr (OP == PIX_FLATSUM) {
+    for (long long i = i0; i < a.p * nS; i += stride) {
+      const int j = (int)(i / nS);
+      const float b = a.bmap ? a.bmap[i] : a.b[j];
+      acc[0] += (double)a.g[i] - (double)b;
+      acc[1] += (double)a.g[i];
+    }
+  } else if constexpr (OP == PIX_INITF) {
+    for (long long i = i0; i < nF; i += stride) {
+      const float w = a.invw ? a.invw[i] : a.invw_s;
+      const float mr = w > 0.f ? 1.f : 0.f;
+      float v = 0.f;
+      if (st->init == INIT_FLAT) {
+        v = mr * (float)st->cflat;
+      } else if (st->init == INIT_DATA) {
+        const int y = (int)(i / a.NX), x = (int)(i % a.NX);
+        const bool in = (unsigned)(y - a.oy) < (unsigned)a.ny && (unsigned)(x - a.ox) < (unsigned)a.nx;
+        v = in ? mr * a.g[(long long)(y - a.oy) * a.nx + (x - a.ox)] : 0.f;
+      } else if (st->init == INIT_USER) {
+        v = fmaxf(0.f, a.src[i]);
+      }
+      a.f[i] = v;
+    }
+  } else if constexpr (OP == PIX_INVW) {
+    // Eq. (Rdef): R = {alpha_j >= sigma for all j}; invw = M_R / sum_j alpha_j
+    for (long long i = i0; i < nF; i += stride) {
+      bool inR = true;
+      double sum = 0.0;
+      for (int j = 0; j < a.p; ++j) {
+        const float al = a.aux[(long long)j * nF + i];
+        inR = inR && ((double)al >= st->sigma_R);
+        sum += al;
+      }
+      a.d[i] = inR ? (float)(1.0 / sum) : 0.f;  // a.d points at the invw buffer for this launch
+    }
+  } else if constexpr (OP == PIX_ARMIJO_MORE) {
+    const int n = st->max_backtracks - 1;  // candidates theta^2 .. theta^max_backtracks
+    for (long long i = i0; i < a.p * nS; i += stride) {
+      const int j = (int)(i / nS);
+      const float adv = a.Ad[i];
+      const float g = a.g[i];
+      const float yv = fmaxf(a.Af[i] + (a.bmap ? a.bmap[i] : a.b[j]), 1e-30f);
+#pragma unroll
+      for (int m = 0; m < kMoreCand; ++m) {
+        if (m < n) {
+          const float t = (float)st->lam_tab[m + 2] * adv;
+          double term = t;
+          if (g > 0.f) term -= (double)g * (double)log1pf(t / yv);
+          acc[m] += term;
+        }
+      }
+    }
+  }
+
+  if constexpr (NS > 0) {
+    double tot[NS];
+    if (grid_reduce<kPixThreads, NS>(acc, kinds, a.part, a.counter, a.nblk, blockIdx.x, tot)) {
+      if constexpr (OP == PIX_VALIDATE) {
+        if (tot[0] < 0.0 || tot[1] > 0.0) st->flags |= FLAG_BAD_DATA;
+        if (tot[2] < 0.0) st->flags |= FLAG_BAD_BG;
+      } else if constexpr (OP == PIX_PSFSUM) {
+        if (!(tot[0] > 0.0) || tot[1] < 0.0 || tot[2] > 0.0) st->flags |= FLAG_BAD_PSF;
+        else st->psf_scale[a.jsel] = 1.0 / (tot[0] * (double)a.NY * (double)a.NX);
+      } else if constexpr (OP == PIX_FLATSUM) {
+        // Sect. 3.1: background-subtracted (mean) flux divided by the pixel count
+        double c = tot[0] / ((double)a.p * (double)nS);
+        if (!(c > 0.0)) c = 1e-6 * fmax(tot[1] / ((double)a.p * (double)nS), 1e-30);
+        st->cflat = c;
+      } else if constexpr (OP == PIX_ARMIJO_MORE) {
+        fin_armijo(st, tot, 2, st->max_backtracks - 1);
+      }
+    }
+  }
+}
+
+// exp(-2 pi i m / L) for m < L, in double precision, rounded to float.
+__global__ void twiddle_kernel(float2* tw, int L) {
+  const int m = blockIdx.x * blockDim.x + threadIdx.x;
+  if (m < L) {
+    double s, c;
+    sincospi(2.0 * (double)m / (double)L, &s, &c);
+    tw[m] = make_float2((float)c, (float)(-s));
+  }
+}
+
+}  // namespace sgp

@@ -1,0 +1,169 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+Bar: after a fixed iteration count from the same start, relative L2 error of
+f <= 1e-4 and relative error of the KL divergence <= 1e-6; decision logs
+(Armijo backtracks, BB safeguard branches, alternation branch) equal."""
+import numpy as np
+import pytest
+
+from oracle import sgp as O
+from synth import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+F_TOL = 1e-4
+KL_TOL = 1e-6
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1210_2258_amd as m
+    m.load()
+    return torch
+
+
+def _dev(torch, a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(np.asarray(a, np.float64) - b) / np.linalg.norm(b))
+
+
+def _oracle(w):
+    return O.Problem(w.g, w.psf, w.b, domain=w.domain)
+
+
+def _check_log(tr, log, n):
+    for k in range(n):
+        L = log[k]
+        assert int(tr["backtracks"][k]) == L["backtracks"], (k, tr["backtracks"][k], L["backtracks"])
+        assert int(tr["br1"][k]) == L["br1"] and int(tr["br2"][k]) == L["br2"], k
+        assert int(tr["alt"][k]) == L["alt"], k
+        assert abs(tr["alpha"][k] - L["alpha"]) <= 1e-3 * L["alpha"], (k, tr["alpha"][k], L["alpha"])
+
+
+# ------------------------------------------------------------------ operators
+@pytest.mark.parametrize("shape", [(16, 16), (64, 64), (32, 80), (80, 160), (256, 128), (1280, 640), (2048, 2048)])
+def test_operator_matches_oracle(torch_dev, shape):
+    import paper_1210_2258_amd as m
+    torch = torch_dev
+    rng = np.random.default_rng(sum(shape))
+    ny, nx = shape
+    psf = rng.random((ny, nx)) * W.gaussian_psf(ny, nx, 3.0)
+    psf[ny // 2 + 1, nx // 2 - 2] += 0.3 * psf.max()   # asymmetric
+    x = rng.random((ny, nx)) * 100
+    P = O.Problem(np.ones((ny, nx)), psf.astype(np.float32), 1.0)
+    xf = x.astype(np.float32).astype(np.float64)
+    for adj in (False, True):
+        out = m.apply_operator(_dev(torch, psf), _dev(torch, x), adjoint=adj).cpu().numpy()
+        ref = P.AT(0, xf) if adj else P.A(0, xf)
+        assert _rel(out, ref) < 2e-6, (shape, adj, _rel(out, ref))
+
+
+# ------------------------------------------------------------------ solvers
+def _run_gpu(torch, fn, w, **kw):
+    import paper_1210_2258_amd as m
+    g = _dev(torch, w.g if w.p > 1 or w.domain else w.g[0])
+    psf = _dev(torch, w.psf if w.p > 1 or w.domain else w.psf[0])
+    if fn in ("sgp_deconv", "rl_deconv"):
+        return getattr(m, fn)(g, psf, float(w.b[0]), trace=True, **kw)
+    if w.domain is not None:
+        return getattr(m, fn)(g, psf, w.b, w.domain, trace=True, **kw)
+    return getattr(m, fn)(g, psf, w.b, trace=True, **kw)
+
+
+CASES = {
+    "single_64x80": lambda: W.small_single(64, 80),
+    "single_c0_256": W.config0,
+    "multi_3x64": lambda: W.small_multi(64, 64),
+    "boundary_64x48_in_80x64": lambda: W.small_boundary(80, 64, 64, 48, 8, 8),
+}
+
+
+@pytest.mark.parametrize("case", list(CASES))
+def test_rl_fixed_iterations(torch_dev, case):
+    w = CASES[case]()
+    n = 100 if case == "single_c0_256" else 30
+    fn = {1: "rl_deconv"}.get(w.p, "rl_multi_deconv") if w.domain is None else "rl_boundary_deconv"
+    if w.domain is None and w.p == 1:
+        fn = "rl_deconv"
+    f, rep = _run_gpu(torch_dev, fn, w, max_iter=n)
+    P = _oracle(w)
+    fo, io = P.rl(P.start("flat"), n)
+    assert rep["iters"] == n
+    assert _rel(f.cpu().numpy(), fo) <= F_TOL, _rel(f.cpu().numpy(), fo)
+    assert abs(rep["kl"] - io["kl"]) <= KL_TOL * io["kl"], (rep["kl"], io["kl"])
+
+
+@pytest.mark.parametrize("case", list(CASES))
+def test_sgp_fixed_iterations(torch_dev, case):
+    w = CASES[case]()
+    n = 100 if case == "single_c0_256" else 30
+    fn = "sgp_deconv" if (w.domain is None and w.p == 1) else (
+        "sgp_multi_deconv" if w.domain is None else "sgp_boundary_deconv")
+    f, rep = _run_gpu(torch_dev, fn, w, max_iter=n)
+    P = _oracle(w)
+    fo, io = P.sgp(P.start("flat"), O.Params(max_iter=n))
+    assert rep["iters"] == n
+    assert abs(rep["L1"] - io["L1"]) <= 1e-5 * io["L1"] and abs(rep["L2"] - io["L2"]) <= 1e-5 * io["L2"]
+    _check_log(rep["trace"], io["log"], n)
+    assert _rel(f.cpu().numpy(), fo) <= F_TOL, _rel(f.cpu().numpy(), fo)
+    assert abs(rep["kl"] - io["kl"]) <= KL_TOL * io["kl"], (rep["kl"], io["kl"])
+
+
+def test_sgp_discrepancy_stop_matches(torch_dev):
+    import paper_1210_2258_amd as m
+    w = W.config0()
+    f, rep = _run_gpu(torch_dev, "sgp_deconv", w, max_iter=1000, stop=m.STOP_DISCREPANCY)
+    P = _oracle(w)
+    fo, io = P.sgp(P.start("flat"), O.Params(max_iter=1000, stop=O.STOP_DISCREPANCY))
+    assert rep["reason"] == "discrepancy" and io["reason"] == O.REASON_DISCREPANCY
+    assert rep["iters"] == io["iters"]
+    assert rep["discrepancy"] <= 1.0
+    assert _rel(f.cpu().numpy(), fo) <= F_TOL
+
+
+def test_rl_discrepancy_stop_matches(torch_dev):
+    import paper_1210_2258_amd as m
+    w = W.small_single(64, 80)
+    f, rep = _run_gpu(torch_dev, "rl_deconv", w, max_iter=2000, stop=m.STOP_DISCREPANCY)
+    P = _oracle(w)
+    fo, io = P.rl(P.start("flat"), 2000, O.Params(max_iter=2000, stop=O.STOP_DISCREPANCY))
+    assert rep["iters"] == io["iters"]
+    assert _rel(f.cpu().numpy(), fo) <= F_TOL
+
+
+def test_sgp_run_to_run_bitwise(torch_dev):
+    w = W.small_single(64, 80)
+    f1, r1 = _run_gpu(torch_dev, "sgp_deconv", w, max_iter=40)
+    f2, r2 = _run_gpu(torch_dev, "sgp_deconv", w, max_iter=40)
+    assert torch_dev.equal(f1, f2)
+    assert r1["kl"] == r2["kl"]
+
+
+def test_gpu_errors(torch_dev):
+    import paper_1210_2258_amd as m
+    torch = torch_dev
+    g = torch.full((64, 64), 5.0, device="cuda")
+    psf = torch.zeros((64, 64), device="cuda")
+    with pytest.raises(m.SgpError) as e:
+        m.sgp_deconv(g, psf, 1.0, max_iter=5)
+    assert e.value.code == -3
+    psf[32, 32] = 1.0
+    psf[0, 0] = -0.1
+    with pytest.raises(m.SgpError) as e:
+        m.sgp_deconv(g, psf, 1.0, max_iter=5)
+    assert e.value.code == -3
+    psf[0, 0] = 0.0
+    g[3, 3] = float("nan")
+    with pytest.raises(m.SgpError) as e:
+        m.sgp_deconv(g, psf, 1.0, max_iter=5)
+    assert e.value.code == -4
+    g[3, 3] = -1.0
+    with pytest.raises(m.SgpError) as e:
+        m.sgp_deconv(g, psf, 1.0, max_iter=5)
+    assert e.value.code == -4
