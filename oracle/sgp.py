@@ -34,7 +34,8 @@ documented choice, shared with the HIP library by specification, not by code):
   without touching tau; alternation starts afterwards;
 * the memory of alpha^(2) values holds only the values computed so far;
 * "10 alpha_{k-1}" is the steplength used in the step just taken;
-* the RL step of Sect. 3.2 only sets (L1, L2); SGP starts from f^(0);
+* the RL step of Sect. 3.2 only sets (L1, L2); SGP starts from f^(0); its
+  min / max are taken over S (equal to R unless boundary-corrected);
 * a term with g = 0 contributes y to the KL sum;
 * boundary weights alpha_j = K_j (correlated with) M_S, i.e. A_j^T 1 before M_R;
 * multi-image scaling D = clip(f, L1, L2) / p;
@@ -227,9 +228,14 @@ class Problem:
         return c * self.MR
 
     def bounds(self, f0):
-        """Sect. 3.2: one RL step, min positive / max of the result."""
+        """Sect. 3.2: one RL step, min positive / max of the result.
+
+        With boundary correction the extrema are taken over the observed
+        window S: outside S the RL values rest on weights alpha_j that may be
+        as small as sigma, a region the paper itself calls unreliable, and
+        there the step is a ratio of two tiny numbers."""
         yr = self.rl_step(f0)
-        pos = yr[(yr > 0) & (self.MR > 0)]
+        pos = yr[(yr > 0) & (self.MS > 0)]
         ymin, ymax = pos.min(), pos.max()
         if ymax / ymin < 50:
             return ymin / 10.0, ymax * 10.0
