@@ -1,0 +1,174 @@
+"""Benchmark: SGP iterations per second on the 2048x2048 galaxy workload.
+
+One "step" is one SGP iteration (scaling, projection, direction, forward
+convolution, Armijo test, update, adjoint convolution, gradient and BB
+steplength) over the whole image, through the stepping C ABI with the
+iteration loop replayed as a HIP graph.  Inputs are resident in HBM before
+the timed region starts.  Also reported: the time to reach the discrepancy
+stop (call to return, setup included), the roofline of the dominant kernel
+(from HIP events on the solver's stream), and the FP64 oracle timed on the
+host's cores on a bounded sample.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "SGP iter/s & time-to-discrepancy at 2048² FP32; warm-start+batch vs plain"
+HBM_PEAK_GBS = 8000.0
+
+# Algorithmic bytes per pixel and launch (FP32 fields, complex64 half spectra,
+# one HBM pass per 2D-FFT transpose), single image with a constant background:
+#   row_dir  reads f, grad            writes d, spectrum           16 B/px
+#   col_conv reads spectrum, K         writes spectrum              12 B/px
+#   row_ad   reads spectrum, Af, g     writes Ad                    16 B/px
+#   row_upd  reads f, d, Af, Ad, g     writes f, Af, spectrum       32 B/px
+#   col_corr reads spectrum, K         writes spectrum              12 B/px
+#   row_grad reads spectrum, grad, f, d writes grad                 20 B/px
+BYTES_PER_PX = {"row_dir": 16, "col_conv": 12, "row_ad": 16, "row_upd": 32, "col_corr": 12,
+                "row_grad": 20}
+ITER_BYTES_PER_PX = sum(BYTES_PER_PX.values())  # 108
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=400)
+    ap.add_argument("--warmup", type=int, default=40)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle timing")
+    ap.add_argument("--cpu-iters", type=int, default=3)
+    ap.add_argument("--size", type=int, default=2048)
+    return ap.parse_args()
+
+
+def cpu_baseline(w, iters):
+    """The FP64 oracle on the host: s/iteration from SGP runs with 0 and
+    `iters` iterations (setup cancels)."""
+    import numpy as np
+    from oracle import sgp as O
+    P = O.Problem(w.g, w.psf, w.b)
+    f0 = P.start("flat")
+    t0 = time.perf_counter()
+    P.sgp(f0, O.Params(max_iter=0))
+    t1 = time.perf_counter()
+    P.sgp(f0, O.Params(max_iter=iters))
+    t2 = time.perf_counter()
+    per_iter = max((t2 - t1) - (t1 - t0), 1e-9) / iters
+    cores = 1  # numpy.fft (pocketfft) runs single-threaded
+    return {"value": 1.0 / per_iter, "unit": "iter/s", "cores": cores, "kind": "oracle",
+            "sample": f"{iters} SGP iterations of the {w.g.shape[-2]}x{w.g.shape[-1]} workload "
+                      f"(oracle setup time subtracted; {t2 - t0:.1f} s of CPU work); host has "
+                      f"{os.cpu_count()} logical CPUs"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+              "(the multi-GPU design is described in DESIGN.md, not built)", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import paper_1210_2258_amd as m
+    from synth import workloads as W
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    m.load()
+    w = W.config1(size=args.size)
+    ny, nx = w.g.shape[-2:]
+    npx = ny * nx
+    g = torch.from_numpy(w.g[0]).cuda()
+    psf = torch.from_numpy(w.psf[0]).cuda()
+    b = float(w.b[0])
+    torch.cuda.synchronize()
+
+    # ---- throughput: W warm-up iterations, then exactly K timed iterations
+    total = args.warmup + args.steps
+    S = m.Solver(m.KIND_SGP, g, psf, b, max_iter=total + 10)
+    S.step(args.warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    done = S.step(args.steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    rep = S.report()
+    assert not done and rep["iters"] == total, (done, rep["iters"], total)
+    elapsed = t1 - t0
+    ms_per_step = 1e3 * elapsed / args.steps
+    its = args.steps / elapsed
+
+    # ---- per-kernel durations (HIP events around each launch, no graph)
+    S.set_timing(True)
+    S.step(8)
+    tm = S.timing()
+    S.close()
+    kern = {k: (ms / c if c else 0.0, c, ms) for k, (ms, c) in tm.items() if c}
+    dom = max((k for k in kern if k in BYTES_PER_PX), key=lambda k: kern[k][2])
+    avg_ms = kern[dom][0]
+    achieved = BYTES_PER_PX[dom] * npx / (avg_ms * 1e-3) / 1e9
+    iter_ms_events = sum(v[2] for v in kern.values()) / 8
+    iter_roofline = ITER_BYTES_PER_PX * npx / (ms_per_step * 1e-3) / 1e9
+
+    # ---- time to discrepancy (call to return, setup included)
+    f_out = torch.empty_like(g)
+    m.sgp_deconv(g, psf, b, f=f_out, max_iter=10, stop=m.STOP_FIXED)  # warm the plan cache
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    f_out, drep = m.sgp_deconv(g, psf, b, f=f_out, max_iter=5000, stop=m.STOP_DISCREPANCY)
+    torch.cuda.synchronize()
+    ttd = time.perf_counter() - t2
+    t3 = time.perf_counter()
+    f_rl, rrep = m.rl_deconv(g, psf, b, max_iter=20000, stop=m.STOP_DISCREPANCY)
+    torch.cuda.synchronize()
+    ttd_rl = time.perf_counter() - t3
+
+    out = {
+        "metric": METRIC,
+        "value": its,
+        "unit": "iter/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"c1 galaxy field {ny}x{nx}: 20 Sersic profiles + 500 stars, 1e8 counts, "
+                               "Airy (first zero 4 px) + 1% Gaussian halo PSF, b = 50, single-image SGP "
+                               "with RL scaling, FP64 reductions",
+                   "image": [ny, nx], "images_per_step": 1, "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": dom,
+                     "avg_ms": avg_ms, "bytes_per_launch": BYTES_PER_PX[dom] * npx},
+        "iteration_roofline": {"bytes_per_iter": ITER_BYTES_PER_PX * npx, "achieved_GBs": iter_roofline,
+                               "frac": iter_roofline / HBM_PEAK_GBS},
+        "kernels_ms": {k: v[0] for k, v in kern.items()},
+        "iteration_ms_events": iter_ms_events,
+        "time_to_discrepancy_s": ttd,
+        "iters_to_discrepancy": drep["iters"],
+        "discrepancy_final": drep["discrepancy"],
+        "kl_final": drep["kl"],
+        "rl_time_to_discrepancy_s": ttd_rl,
+        "rl_iters_to_discrepancy": rrep["iters"],
+    }
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(w, args.cpu_iters)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

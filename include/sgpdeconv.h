@@ -173,6 +173,66 @@ int rl_boundary_deconv(const float* g, const float* psf, const float* b_map,
 int sgp_apply_operator(const float* psf, const float* x, int ny, int nx, int adjoint,
                        float* out, void* hip_stream);
 
+/* ---------------------------------------------------------------------------
+ * Stepping interface.  A solver owns its workspace; create() runs the setup of
+ * the one-shot calls above (validation, transfer functions, weights, start,
+ * and for SGP the RL step that sets (L1, L2) and the first gradient);
+ * step() advances by up to n iterations (fewer if a stop rule fires) and can
+ * be called repeatedly, continuing exactly where the previous call stopped;
+ * report() fills the report of the iterations so far.  The iteration loop is
+ * captured once as a HIP graph of `block` iterations and replayed.
+ * ------------------------------------------------------------------------- */
+#define SGP_KIND_RL 0
+#define SGP_KIND_SGP 1
+
+typedef struct sgp_problem {
+  const float* g;        /* device [p][ny][nx] */
+  const float* psf;      /* device [p][NY][NX] */
+  const float* b_map;    /* device [p][ny][nx] or NULL */
+  const float* b_const;  /* HOST [p], used when b_map is NULL */
+  int p, ny, nx;
+  int NY, NX, oy, ox;    /* object domain; NY = ny, NX = nx, oy = ox = 0 when periodic */
+  int boundary;          /* 1: Sect. 2.4 boundary-effect correction */
+} sgp_problem;
+
+typedef struct sgp_solver sgp_solver;
+
+/* kind: SGP_KIND_RL or SGP_KIND_SGP.  f: device [NY][NX], the iterate, owned
+ * by the caller and updated in place by step().  The parameters are copied;
+ * prm->trace (if set) must stay valid until sgp_solver_destroy. */
+int sgp_solver_create(int kind, const sgp_problem* prob, const sgp_params* prm, float* f,
+                      void* hip_stream, sgp_solver** out);
+/* Runs up to n more iterations; *done (optional) becomes 1 once a stop rule
+ * or max_iter has ended the run.  Synchronous on return. */
+int sgp_solver_step(sgp_solver* s, int n, int* done);
+int sgp_solver_report(sgp_solver* s, sgp_report* rep);
+/* Kernel timing of later step() calls (HIP events around every launch on the
+ * solver's stream; graphs are not used while enabled).  ms[i] receives the
+ * summed milliseconds and counts[i] the launches of kernel class i:
+ * see SGP_KCLASS_*; ncls is the array length. */
+#define SGP_KCLASS_ROW_DIR 0      /* scaling, projection, direction + row FFT */
+#define SGP_KCLASS_COL_CONV 1     /* column FFT x K x IFFT */
+#define SGP_KCLASS_ROW_AD 2       /* row IFFT -> A d, Armijo candidates */
+#define SGP_KCLASS_ARMIJO_MORE 3  /* further Armijo candidates (early exit if not needed) */
+#define SGP_KCLASS_ROW_UPD 4      /* update f, A f, residual change + row FFT */
+#define SGP_KCLASS_COL_CORR 5     /* column FFT x conj K x IFFT, summed over images */
+#define SGP_KCLASS_ROW_GRAD 6     /* row IFFT -> gradient, BB sums */
+#define SGP_KCLASS_ROW_RATIO 7    /* RL: row IFFT -> ratio, KL -> row FFT */
+#define SGP_KCLASS_ROW_RLUPD 8    /* RL: row IFFT -> update -> row FFT */
+#define SGP_KCLASS_COUNT 9
+int sgp_solver_set_timing(sgp_solver* s, int enable);
+int sgp_solver_timing(sgp_solver* s, double* ms, long long* counts, int ncls);
+int sgp_solver_destroy(sgp_solver* s);
+
+/* The steplength rule of Sect. 2.1 exactly as the device runs it, callable on
+ * the host for validation.  k: index of the iteration just completed;
+ * alpha: steplength used in it; Q/nQ: memory of alpha^(2) values (oldest
+ * first); a, c1, c2, e: the sums s'D^-2 s, s'D^-1 z, s'D z, z'D^2 z.
+ * out (16 doubles): alpha1, alpha2, alpha_next, tau_next, alternation branch,
+ * BB1 branch, BB2 branch, nQ, then the updated Q. */
+int sgp_steplength_rule(const sgp_params* prm, int k, double alpha, double tau, const double* Q,
+                        int nQ, double a, double c1, double c2, double e, double* out);
+
 /* Releases every cached workspace of the calling process on the current device. */
 int sgp_release_cache(void);
 

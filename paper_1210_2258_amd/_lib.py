@@ -53,10 +53,24 @@ class _Report(ctypes.Structure):
     ]
 
 
+class _Problem(ctypes.Structure):
+    _fields_ = [
+        ("g", ctypes.c_void_p), ("psf", ctypes.c_void_p), ("b_map", ctypes.c_void_p),
+        ("b_const", ctypes.c_void_p), ("p", ctypes.c_int), ("ny", ctypes.c_int), ("nx", ctypes.c_int),
+        ("NY", ctypes.c_int), ("NX", ctypes.c_int), ("oy", ctypes.c_int), ("ox", ctypes.c_int),
+        ("boundary", ctypes.c_int),
+    ]
+
+
+KIND_RL, KIND_SGP = 0, 1
+KCLASSES = ["row_dir", "col_conv", "row_ad", "armijo_more", "row_upd", "col_corr", "row_grad",
+            "row_ratio", "row_rlupd"]
+
 EXPORTS = [
     "sgp_params_init", "rl_deconv", "sgp_deconv", "sgp_multi_deconv", "rl_multi_deconv",
     "sgp_boundary_deconv", "rl_boundary_deconv", "sgp_apply_operator", "sgp_release_cache",
-    "sgp_strerror", "sgp_last_error",
+    "sgp_strerror", "sgp_last_error", "sgp_solver_create", "sgp_solver_step", "sgp_solver_report",
+    "sgp_solver_set_timing", "sgp_solver_timing", "sgp_solver_destroy", "sgp_steplength_rule",
 ]
 
 _lib = None
@@ -80,6 +94,13 @@ def load():
     for name in ("sgp_boundary_deconv", "rl_boundary_deconv"):
         getattr(lib, name).argtypes = [vp, vp, vp, vp, i, i, i, i, i, i, i, P, vp, R, vp]
     lib.sgp_apply_operator.argtypes = [vp, vp, i, i, i, vp, vp]
+    lib.sgp_solver_create.argtypes = [i, ctypes.POINTER(_Problem), P, vp, vp, ctypes.POINTER(vp)]
+    lib.sgp_solver_step.argtypes = [vp, i, ctypes.POINTER(i)]
+    lib.sgp_solver_report.argtypes = [vp, R]
+    lib.sgp_solver_set_timing.argtypes = [vp, i]
+    lib.sgp_solver_timing.argtypes = [vp, ctypes.POINTER(d), ctypes.POINTER(ctypes.c_longlong), i]
+    lib.sgp_solver_destroy.argtypes = [vp]
+    lib.sgp_steplength_rule.argtypes = [P, i, d, d, ctypes.POINTER(d), i, d, d, d, d, ctypes.POINTER(d)]
     lib.sgp_strerror.restype = ctypes.c_char_p
     lib.sgp_strerror.argtypes = [i]
     lib.sgp_last_error.restype = ctypes.c_char_p
@@ -254,3 +275,83 @@ def apply_operator(psf, x, adjoint=False, out=None, stream=None):
 
 def release_cache():
     return load().sgp_release_cache()
+
+
+class Solver:
+    """Stepping solver (sgp_solver_* of the C ABI).  ``g``/``psf`` are
+    [p, ny, nx] / [p, NY, NX] (or 2D) CUDA tensors; ``domain`` = (NY, NX, oy,
+    ox) selects boundary-effect correction.  The tensors must stay alive while
+    the solver exists; ``f`` is updated in place."""
+
+    def __init__(self, kind, g, psf, b, *, domain=None, b_map=None, f=None, stream=None,
+                 trace=False, **params):
+        import torch
+        lib = load()
+        _check_dev(g, "g")
+        _check_dev(psf, "psf")
+        g3 = g.unsqueeze(0) if g.dim() == 2 else g
+        psf3 = psf.unsqueeze(0) if psf.dim() == 2 else psf
+        p, ny, nx = g3.shape
+        NY, NX, oy, ox = domain if domain is not None else (ny, nx, 0, 0)
+        if f is None:
+            f = torch.empty((NY, NX), dtype=torch.float32, device=g.device)
+        _check_dev(f, "f")
+        if b_map is not None:
+            _check_dev(b_map, "b_map")
+        self._bc = _bconst(b, p)
+        pr = _Problem(g3.data_ptr(), psf3.data_ptr(), b_map.data_ptr() if b_map is not None else None,
+                      ctypes.cast(self._bc, ctypes.c_void_p), p, ny, nx, NY, NX, oy, ox,
+                      1 if domain is not None else 0)
+        self._prm, self._trace, self._keep = _make_params(
+            params, (params.get("max_iter", 1000) + 1) if trace else None)
+        self._keep += [g3, psf3, b_map, f]
+        self.f = f
+        self._h = ctypes.c_void_p()
+        rc = lib.sgp_solver_create(kind, ctypes.byref(pr), ctypes.byref(self._prm),
+                                   ctypes.c_void_p(f.data_ptr()), _stream(stream), ctypes.byref(self._h))
+        _raise(rc)
+
+    def step(self, n):
+        done = ctypes.c_int(0)
+        _raise(load().sgp_solver_step(self._h, int(n), ctypes.byref(done)))
+        return bool(done.value)
+
+    def report(self):
+        rep = _Report()
+        rc = load().sgp_solver_report(self._h, ctypes.byref(rep))
+        _raise(rc)
+        return _report(rep, rc, self._trace)
+
+    def set_timing(self, on=True):
+        _raise(load().sgp_solver_set_timing(self._h, 1 if on else 0))
+
+    def timing(self):
+        n = len(KCLASSES)
+        ms = (ctypes.c_double * n)()
+        cnt = (ctypes.c_longlong * n)()
+        _raise(load().sgp_solver_timing(self._h, ms, cnt, n))
+        return {KCLASSES[i]: (ms[i], cnt[i]) for i in range(n)}
+
+    def close(self):
+        if self._h:
+            load().sgp_solver_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def steplength_rule(k, alpha, tau, Q, a, c1, c2, e, **params):
+    """The device steplength rule (Sect. 2.1) evaluated on the host."""
+    prm, _, _ = _make_params(params, None)
+    q = (ctypes.c_double * 8)(*list(Q)[:8])
+    out = (ctypes.c_double * 16)()
+    rc = load().sgp_steplength_rule(ctypes.byref(prm), int(k), float(alpha), float(tau), q, len(Q),
+                                    float(a), float(c1), float(c2), float(e), out)
+    _raise(rc)
+    nq = int(out[7])
+    return dict(a1=out[0], a2=out[1], alpha_next=out[2], tau=out[3], alt=int(out[4]),
+                br1=int(out[5]), br2=int(out[6]), Q=[out[8 + i] for i in range(nq)])

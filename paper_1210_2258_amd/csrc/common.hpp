@@ -39,6 +39,7 @@ struct DevState {
   double alpha, tau, L1, L2, J, Jprev, gd, lam, flux_c;
   double Q[8];
   int nQ, k, done, reason, need_more, nback, total_back, flags;
+  int pause, k_stop;  // a stepping call stops (resumably) once k reaches k_stop
   double lam_tab[kMaxCand];
   double psf_scale[kMaxP];
   double norm_disc;  // 2 / (p |S|), Eq. (discrepancy)
@@ -90,8 +91,8 @@ enum RowOp {
   ROW_SETUPGRAD,    // inv: gradient at f0, min/max of one RL step (bounds)
   ROW_DIR,          // fwd: scaling, projection, direction d -> spec[0]
   ROW_AD,           // inv: A_j d, Armijo candidates lambda = 1, theta
-  ROW_UPD,          // fwd: f += lam d, A_j f += lam A_j d, rho_j -> spec[j]
-  ROW_GRAD,         // inv: new gradient, BB sums
+  ROW_UPD,          // fwd: f += lam d, A_j f += lam A_j d, delta rho_j -> spec[j]
+  ROW_GRAD,         // inv: gradient change z, new gradient, BB sums
   ROW_NOPS
 };
 

@@ -85,6 +85,10 @@ void launch_pix(int op, dim3 grid, const Args& a, hipStream_t s) {
   }
 }
 
+void launch_resume(DevState* st, int n, hipStream_t s) {
+  hipLaunchKernelGGL(resume_kernel, dim3(1), dim3(64), 0, s, st, n);
+}
+
 void launch_twiddle(float2* tw, int L, hipStream_t s) {
   hipLaunchKernelGGL(twiddle_kernel, dim3((L + 255) / 256), dim3(256), 0, s, tw, L);
 }

@@ -12,12 +12,12 @@
 
 namespace sgp {
 
-__device__ inline double* trace_row(DevState* st, int k) {
+__host__ __device__ inline double* trace_row(DevState* st, int k) {
   if (!st->trace_on || !st->trace || k < 0 || k > st->max_iter) return nullptr;
   return st->trace + (size_t)k * kTraceCols;
 }
 
-__device__ inline void fin_dir(DevState* st, double gd) {
+__host__ __device__ inline void fin_dir(DevState* st, double gd) {
   st->gd = gd;
   double* tr = trace_row(st, st->k);
   if (tr) {
@@ -36,7 +36,7 @@ __device__ inline void fin_dir(DevState* st, double gd) {
 }
 
 // dJ[m] = J(f + theta^(m0+m) d) - J(f) for m = 0..n-1.
-__device__ inline void fin_armijo(DevState* st, const double* dJ, int m0, int n) {
+__host__ __device__ inline void fin_armijo(DevState* st, const double* dJ, int m0, int n) {
   st->need_more = 0;
   for (int m = 0; m < n; ++m) {
     const int mm = m0 + m;
@@ -61,7 +61,7 @@ __device__ inline void fin_armijo(DevState* st, const double* dJ, int m0, int n)
   }
 }
 
-__device__ inline void fin_update(DevState* st, double Jn) {
+__host__ __device__ inline void fin_update(DevState* st, double Jn) {
   const int k = st->k;
   double* tr = trace_row(st, k);
   if (tr) {
@@ -88,44 +88,54 @@ __device__ inline void fin_update(DevState* st, double Jn) {
   }
 }
 
-// a = s'D^-2 s, c1 = s'D^-1 z, c2 = s'D z, e = z'D^2 z
-__device__ inline void fin_bb(DevState* st, double a, double c1, double c2, double e) {
+struct BBInfo {
+  double a1, a2, next;
+  int br1, br2, alt;
+};
+
+// Steplength rule after a completed iteration (st->k iterations done).
+// a = s'D^-2 s, c1 = s'D^-1 z, c2 = s'D z, e = z'D^2 z.  Updates tau and the
+// memory Q; returns alpha^(1), alpha^(2), the next steplength and branches.
+__host__ __device__ inline BBInfo bb_rule(DevState* st, double a, double c1, double c2, double e) {
   const double alpha = st->alpha;
-  double a1, a2;
-  int br1, br2;
-  if (c1 <= 0) { a1 = fmin(10.0 * alpha, st->alpha_max); br1 = 0; }
-  else { a1 = fmin(st->alpha_max, fmax(st->alpha_min, a / c1)); br1 = 1; }
-  if (c2 <= 0) { a2 = fmin(10.0 * alpha, st->alpha_max); br2 = 0; }
-  else { a2 = fmin(st->alpha_max, fmax(st->alpha_min, c2 / e)); br2 = 1; }
+  BBInfo r;
+  if (c1 <= 0) { r.a1 = fmin(10.0 * alpha, st->alpha_max); r.br1 = 0; }
+  else { r.a1 = fmin(st->alpha_max, fmax(st->alpha_min, a / c1)); r.br1 = 1; }
+  if (c2 <= 0) { r.a2 = fmin(10.0 * alpha, st->alpha_max); r.br2 = 0; }
+  else { r.a2 = fmin(st->alpha_max, fmax(st->alpha_min, c2 / e)); r.br2 = 1; }
   // memory of the last m_alpha values of alpha^(2)
   if (st->nQ < st->m_alpha) {
-    st->Q[st->nQ++] = a2;
+    st->Q[st->nQ++] = r.a2;
   } else {
     for (int i = 1; i < st->m_alpha; ++i) st->Q[i - 1] = st->Q[i];
-    st->Q[st->m_alpha - 1] = a2;
+    st->Q[st->m_alpha - 1] = r.a2;
   }
   double qmin = st->Q[0];
   for (int i = 1; i < st->nQ; ++i) qmin = fmin(qmin, st->Q[i]);
   const int kdone = st->k;  // iterations completed, i.e. k + 1 of the step just taken
-  int alt;
-  double next;
-  if (kdone <= st->n_bb2_only) { next = qmin; alt = 0; }
-  else if (a2 / a1 <= st->tau) { next = qmin; st->tau *= 0.9; alt = 1; }
-  else { next = a1; st->tau *= 1.1; alt = 2; }
-  double* tr = trace_row(st, kdone - 1);
+  if (kdone <= st->n_bb2_only) { r.next = qmin; r.alt = 0; }
+  else if (r.a2 / r.a1 <= st->tau) { r.next = qmin; st->tau *= 0.9; r.alt = 1; }
+  else { r.next = r.a1; st->tau *= 1.1; r.alt = 2; }
+  return r;
+}
+
+__host__ __device__ inline void fin_bb(DevState* st, double a, double c1, double c2, double e) {
+  const BBInfo r = bb_rule(st, a, c1, c2, e);
+  double* tr = trace_row(st, st->k - 1);
   if (tr) {
     tr[TR_A] = a; tr[TR_C1] = c1; tr[TR_C2] = c2; tr[TR_E] = e;
-    tr[TR_A1] = a1; tr[TR_A2] = a2; tr[TR_BR1] = br1; tr[TR_BR2] = br2;
-    tr[TR_ALT] = alt; tr[TR_TAU] = st->tau; tr[TR_ALPHA_NEXT] = next;
+    tr[TR_A1] = r.a1; tr[TR_A2] = r.a2; tr[TR_BR1] = r.br1; tr[TR_BR2] = r.br2;
+    tr[TR_ALT] = r.alt; tr[TR_TAU] = st->tau; tr[TR_ALPHA_NEXT] = r.next;
   }
-  if (!__builtin_isfinite(next)) {
+  if (!__builtin_isfinite(r.next)) {
     st->done = 1;
     st->reason = REASON_NUMERIC;
   }
-  st->alpha = next;
+  st->alpha = r.next;
+  if (st->k >= st->k_stop) st->pause = 1;
 }
 
-__device__ inline void fin_bounds(DevState* st, double ymin, double ymax) {
+__host__ __device__ inline void fin_bounds(DevState* st, double ymin, double ymax) {
   st->ymin = ymin;
   st->ymax = ymax;
   if (st->auto_bounds) {
@@ -159,8 +169,10 @@ __device__ inline void fin_bounds(DevState* st, double ymin, double ymax) {
   }
 }
 
-// RL: J(f^(k)) has just been formed; decide whether f^(k) is returned.
-__device__ inline void fin_rl(DevState* st, double J) {
+// RL: J(f^(k)) has just been formed; decide whether f^(k) is returned, or
+// whether a stepping call pauses before the next update (J is then not
+// committed, so the resumed call re-forms it with the same previous value).
+__host__ __device__ inline void fin_rl(DevState* st, double J) {
   const int k = st->k;
   double* tr = trace_row(st, k);
   if (tr) {
@@ -168,8 +180,6 @@ __device__ inline void fin_rl(DevState* st, double J) {
     tr[TR_J] = J;
   }
   const double Jprev = st->J;
-  st->Jprev = Jprev;
-  st->J = J;
   if (!__builtin_isfinite(J)) {
     st->done = 1;
     st->reason = REASON_NUMERIC;
@@ -182,9 +192,14 @@ __device__ inline void fin_rl(DevState* st, double J) {
   } else if (k >= st->max_iter) {
     st->done = 1;
     st->reason = REASON_MAXITER;
+  } else if (k >= st->k_stop) {
+    st->pause = 1;
+    return;
   } else {
     st->k = k + 1;
   }
+  st->Jprev = Jprev;
+  st->J = J;
 }
 
 }  // namespace sgp

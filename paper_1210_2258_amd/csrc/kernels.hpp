@@ -105,7 +105,8 @@ __device__ __forceinline__ float row_point(const Args& a, const DevState* st, in
     const float mr = w > 0.f ? 1.f : 0.f;
     a.grad[pix] = -mr * v;
     const float yr = w > 0.f ? a.f[pix] * (1.f + w * v) : 0.f;  // one RL step from f0
-    if (yr > 0.f) {
+    // bounds from the observed window S (equal to R for periodic problems)
+    if (yr > 0.f && P.inS(y, x)) {
       acc[0] = fmin(acc[0], (double)yr);
       acc[1] = fmax(acc[1], (double)yr);
     }
@@ -133,23 +134,31 @@ __device__ __forceinline__ float row_point(const Args& a, const DevState* st, in
     }
     return 0.f;
   } else if constexpr (OP == ROW_UPD) {
+    // f += lam d, A_j f += lam A_j d; feeds delta rho_j = g/y_new - g/y_old
+    // = -g lam A_j d / (y_old y_new) to the transform (no cancellation), so
+    // the adjoint directly yields z = grad_new - grad_old
     const float lam = (float)st->lam;
     if (j == 0) a.f[pix] = a.f[pix] + lam * a.d[pix];
     if (!P.inS(y, x)) return 0.f;
     const long long s = P.s_of(y, x);
-    const float afn = a.Af[s] + lam * a.Ad[s];
+    const float bgv = P.bg(s);
+    const float afo = a.Af[s];
+    const float step = lam * a.Ad[s];
+    const float afn = afo + step;
     a.Af[s] = afn;
     const float g = a.g[s];
-    const float yv = fmaxf(afn + P.bg(s), 1e-30f);
-    acc[0] += kl_term(g, yv);
-    return (g - yv) / yv;
+    const float yo = fmaxf(afo + bgv, 1e-30f);
+    const float yn = fmaxf(afn + bgv, 1e-30f);
+    acc[0] += kl_term(g, yn);
+    return g > 0.f ? -g * step / (yo * yn) : 0.f;
   } else if constexpr (OP == ROW_GRAD) {
+    // v = sum_j A_j^T delta rho_j, so z = grad_new - grad_old = -M_R v
     const float w = P.w(pix);
-    const float gn = w > 0.f ? -v : 0.f;
+    const float zf = w > 0.f ? -v : 0.f;
     const float go = a.grad[pix];
-    a.grad[pix] = gn;
+    a.grad[pix] = go + zf;
     const double s = (double)st->lam * (double)a.d[pix];
-    const double z = (double)gn - (double)go;
+    const double z = (double)zf;
     const float fp = a.f[pix];
     const double D = (double)(w * fminf((float)st->L2, fmaxf((float)st->L1, fp)));
     if (D > 0) {
@@ -200,7 +209,7 @@ __global__ __launch_bounds__(kRP * FftPlan<L>::TF) void row_kernel(Args a) {
   constexpr int NS = row_nslots(OP);
   __shared__ float2 buf[kRP][L];
   DevState* st = a.st;
-  if (a.iter && st->done) return;
+  if (a.iter && (st->done || st->pause)) return;
   const int tid = threadIdx.x;
   const int j = blockIdx.y;
   const int y0 = blockIdx.x * kTile;
@@ -289,7 +298,7 @@ __global__ __launch_bounds__(ColCfg<LY>::NT) void col_kernel(Args a) {
   constexpr int E = LY * C / NT;  // units per thread
   __shared__ float2 buf[C][LY];
   DevState* st = a.st;
-  if (a.iter && st->done) return;
+  if (a.iter && (st->done || st->pause)) return;
   const int NXh = a.NX / 2;
   const int kx0 = blockIdx.x * C;
   const int tid = threadIdx.x;

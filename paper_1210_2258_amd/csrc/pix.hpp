@@ -27,7 +27,7 @@ template <int OP>
 __global__ __launch_bounds__(kPixThreads) void pix_kernel(Args a) {
   constexpr int NS = pix_nslots(OP);
   DevState* st = a.st;
-  if (a.iter && st->done) return;
+  if (a.iter && (st->done || st->pause)) return;
   if constexpr (OP == PIX_ARMIJO_MORE) {
     if (!st->need_more) return;
   }
@@ -133,6 +133,14 @@ __global__ __launch_bounds__(kPixThreads) void pix_kernel(Args a) {
         fin_armijo(st, tot, 2, st->max_backtracks - 1);
       }
     }
+  }
+}
+
+// Starts a stepping call of n iterations.
+__global__ void resume_kernel(DevState* st, int n) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    st->pause = 0;
+    st->k_stop = st->k + n;
   }
 }
 

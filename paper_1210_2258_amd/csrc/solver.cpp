@@ -1,10 +1,11 @@
-// Host side of the library: argument validation, per-shape workspace plans,
-// the setup sequence and the iteration loops of RL and SGP, and the C ABI.
+// Host side of the library: argument validation, per-shape workspaces, the
+// setup sequence, the iteration loops of RL and SGP (captured as HIP graphs),
+// and the C ABI.
 //
 // Each iteration is a fixed sequence of kernel launches with no host round
 // trip; the scalar decisions (Armijo, Barzilai-Borwein, stopping) are taken
 // on the device by the finalising workgroup of each reduction.  The host
-// reads the device "done" flag once every block of iterations.
+// reads the device state once per replayed block of iterations.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -16,9 +17,11 @@
 #include <mutex>
 #include <string>
 #include <tuple>
+#include <vector>
 
 #include "../../include/sgpdeconv.h"
 #include "common.hpp"
+#include "finalize.hpp"
 #include "launch.hpp"
 
 namespace sgp {
@@ -36,7 +39,7 @@ static int fail(int code, const std::string& msg) {
     if (e_ != hipSuccess) return fail(SGP_E_HIP, std::string(#x) + ": " + hipGetErrorString(e_)); \
   } while (0)
 
-enum Kind { KIND_RL = 0, KIND_SGP = 1, KIND_OP = 2 };
+enum Kind { KIND_RL = SGP_KIND_RL, KIND_SGP = SGP_KIND_SGP, KIND_OP = 2 };
 
 struct PlanKey {
   int kind, p, NY, NX, ny, nx, oy, ox, boundary, dev;
@@ -46,6 +49,7 @@ struct PlanKey {
   }
 };
 
+// Device workspace of one problem shape.
 struct Plan {
   PlanKey key{};
   float* grad = nullptr;
@@ -90,13 +94,8 @@ static int dalloc(T** p, size_t n) {
   return 0;
 }
 
-static int get_plan(const PlanKey& key, hipStream_t s, Plan** out) {
-  auto it = g_plans.find(key);
-  if (it != g_plans.end()) {
-    *out = it->second.get();
-    return 0;
-  }
-  auto pl = std::make_unique<Plan>();
+static int make_plan(const PlanKey& key, hipStream_t s, std::unique_ptr<Plan>& pl) {
+  pl = std::make_unique<Plan>();
   pl->key = key;
   const size_t nF = (size_t)key.NY * key.NX;
   const size_t nS = (size_t)key.ny * key.nx;
@@ -125,6 +124,18 @@ static int get_plan(const PlanKey& key, hipStream_t s, Plan** out) {
   launch_twiddle(pl->tw_row, key.NX, s);
   launch_twiddle(pl->tw_col, key.NY, s);
   SGP_HIP(hipGetLastError());
+  return 0;
+}
+
+static int cached_plan(const PlanKey& key, hipStream_t s, Plan** out) {
+  auto it = g_plans.find(key);
+  if (it != g_plans.end()) {
+    *out = it->second.get();
+    return 0;
+  }
+  std::unique_ptr<Plan> pl;
+  int rc = make_plan(key, s, pl);
+  if (rc) return rc;
   *out = pl.get();
   g_plans[key] = std::move(pl);
   return 0;
@@ -217,69 +228,73 @@ static int current_device(int* dev) {
   return 0;
 }
 
+// Launch helper; optionally brackets every launch with HIP events.
 struct Launcher {
   Args base;
-  hipStream_t s;
-  int NY, NX;
-  void row(int op, int jc, int iter, int flag = 0) {
+  hipStream_t s = nullptr;
+  int NY = 0, NX = 0;
+  bool timing = false;
+  struct Mark { hipEvent_t a, b; int cls; };
+  std::vector<Mark> marks;
+  std::vector<hipEvent_t> pool;
+  size_t used = 0;
+
+  hipEvent_t ev() {
+    if (used == pool.size()) {
+      hipEvent_t e;
+      (void)hipEventCreate(&e);
+      pool.push_back(e);
+    }
+    return pool[used++];
+  }
+  void begin(int cls, hipEvent_t& a) {
+    if (timing && cls >= 0) {
+      a = ev();
+      (void)hipEventRecord(a, s);
+    }
+  }
+  void end(int cls, hipEvent_t a) {
+    if (timing && cls >= 0) {
+      hipEvent_t b = ev();
+      (void)hipEventRecord(b, s);
+      marks.push_back({a, b, cls});
+    }
+  }
+  void row(int op, int jc, int iter, int flag = 0, int cls = -1) {
     Args a = base;
     a.nblk = (NY / kTile) * jc;
     a.iter = iter;
     a.flag = flag;
+    hipEvent_t e0 = nullptr;
+    begin(cls, e0);
     launch_row(NX, op, dim3(NY / kTile, jc), a, s);
+    end(cls, e0);
   }
-  void col(int mode, int conj, int jc, int iter) {
+  void col(int mode, int conj, int jc, int iter, int cls = -1) {
     Args a = base;
     const int C = col_width(NY);
     a.iter = iter;
+    hipEvent_t e0 = nullptr;
+    begin(cls, e0);
     launch_col(NY, mode, conj, dim3((NX / 2 + C - 1) / C, jc), a, s);
+    end(cls, e0);
   }
-  void pix(int op, long long n, int iter, int jsel = 0) {
+  void pix(int op, long long n, int iter, int jsel = 0, int cls = -1) {
     Args a = base;
     long long nb = (n + kPixThreads - 1) / kPixThreads;
     nb = std::max<long long>(1, std::min<long long>(nb, kMaxPixBlocks));
     a.nblk = (int)nb;
     a.iter = iter;
     a.jsel = jsel;
+    hipEvent_t e0 = nullptr;
+    begin(cls, e0);
     launch_pix(op, dim3((unsigned)nb), a, s);
+    end(cls, e0);
+  }
+  ~Launcher() {
+    for (hipEvent_t e : pool) (void)hipEventDestroy(e);
   }
 };
-
-static int read_state(Plan* pl, hipStream_t s) {
-  SGP_HIP(hipMemcpyAsync(pl->host_st, pl->st, sizeof(DevState), hipMemcpyDeviceToHost, s));
-  SGP_HIP(hipStreamSynchronize(s));
-  return 0;
-}
-
-// Setup shared by every solver: validation of data and PSFs, transfer
-// functions, boundary weights.  On return the state's flags are checked.
-static int setup_common(Plan* pl, Launcher& L, const Problem& pb) {
-  const long long nS = (long long)pb.ny * pb.nx, nF = (long long)pb.NY * pb.NX;
-  L.pix(PIX_VALIDATE, pb.p * nS, 0);
-  for (int j = 0; j < pb.p; ++j) L.pix(PIX_PSFSUM, nF, 0, j);
-  SGP_HIP(hipGetLastError());
-  int rc;
-  if ((rc = read_state(pl, L.s))) return rc;
-  const int fl = pl->host_st->flags;
-  if (fl & FLAG_BAD_PSF) return fail(SGP_E_BAD_PSF, "PSF has negative or non-finite entries or a non-positive sum");
-  if (fl & FLAG_BAD_DATA) return fail(SGP_E_BAD_DATA, "g must be finite and >= 0");
-  if (fl & FLAG_BAD_BG) return fail(SGP_E_BAD_DATA, "background map must be finite and >= 0");
-  // transfer functions K_j / (NY NX): shifted PSF -> row FFT -> column FFT
-  L.row(ROW_PSF, pb.p, 0);
-  L.col(COL_FWD, 0, pb.p, 0);
-  if (pb.boundary) {
-    // alpha_j = K_j correlated with M_S, then R and M_R / alpha
-    L.row(ROW_MASKS, 1, 0);
-    L.col(COL_CONV, 1, 1, 0);
-    L.row(ROW_STORE, pb.p, 0);
-    Args save = L.base;
-    L.base.d = pl->invw;
-    L.pix(PIX_INVW, nF, 0);
-    L.base = save;
-  }
-  SGP_HIP(hipGetLastError());
-  return 0;
-}
 
 static void fill_state(DevState& h, const sgp_params& p, const Problem& pb, double* trace) {
   std::memset(&h, 0, sizeof(h));
@@ -312,18 +327,194 @@ static void fill_state(DevState& h, const sgp_params& p, const Problem& pb, doub
   h.lam = 1.0;
   h.L1 = p.L1;
   h.L2 = p.L2;
+  h.k_stop = 0;
 }
 
-static int finish(Plan* pl, Launcher& L, const sgp_params& prm, const Problem& pb, sgp_report* rep,
-                  std::chrono::steady_clock::time_point t0, int kind) {
-  int rc;
-  if ((rc = read_state(pl, L.s))) return rc;
-  const DevState& h = *pl->host_st;
-  if (prm.trace && pl->trace) {
-    SGP_HIP(hipMemcpy(prm.trace, pl->trace, sizeof(double) * kTraceCols * (size_t)(prm.max_iter + 1),
-                      hipMemcpyDeviceToHost));
+}  // namespace sgp
+
+// A solver: workspace, problem, parameters, launch state and graph.
+struct sgp_solver {
+  int kind = 0;
+  sgp::Problem pb;
+  sgp_params prm{};
+  float* f = nullptr;
+  hipStream_t user = nullptr;
+  hipStream_t s = nullptr;  // internal stream (capturable)
+  sgp::Plan* pl = nullptr;
+  std::unique_ptr<sgp::Plan> owned;
+  sgp::Launcher L;
+  hipGraphExec_t graph = nullptr;
+  hipGraph_t graph_def = nullptr;
+  int graph_block = 0;
+  bool done = false;
+  std::chrono::steady_clock::time_point t0;
+  double ms[SGP_KCLASS_COUNT] = {0};
+  long long cnt[SGP_KCLASS_COUNT] = {0};
+
+  ~sgp_solver() {
+    if (graph) (void)hipGraphExecDestroy(graph);
+    if (graph_def) (void)hipGraphDestroy(graph_def);
+    if (s) (void)hipStreamDestroy(s);
   }
-  const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+};
+
+namespace sgp {
+
+static int read_state(sgp_solver* S) {
+  SGP_HIP(hipMemcpyAsync(S->pl->host_st, S->pl->st, sizeof(DevState), hipMemcpyDeviceToHost, S->s));
+  SGP_HIP(hipStreamSynchronize(S->s));
+  return 0;
+}
+
+// one iteration of the solver's loop
+static void enqueue_iteration(sgp_solver* S) {
+  Launcher& L = S->L;
+  const int p = S->pb.p;
+  const long long nS = (long long)S->pb.ny * S->pb.nx;
+  if (S->kind == KIND_SGP) {
+    L.row(ROW_DIR, 1, 1, 0, SGP_KCLASS_ROW_DIR);
+    L.col(COL_CONV, 0, 1, 1, SGP_KCLASS_COL_CONV);
+    L.row(ROW_AD, p, 1, 0, SGP_KCLASS_ROW_AD);
+    L.pix(PIX_ARMIJO_MORE, p * nS, 1, 0, SGP_KCLASS_ARMIJO_MORE);
+    L.row(ROW_UPD, p, 1, 0, SGP_KCLASS_ROW_UPD);
+    L.col(COL_CORRSUM, 1, 1, 1, SGP_KCLASS_COL_CORR);
+    L.row(ROW_GRAD, 1, 1, 0, SGP_KCLASS_ROW_GRAD);
+  } else {
+    L.col(COL_CONV, 0, 1, 1, SGP_KCLASS_COL_CONV);
+    L.row(ROW_RATIO, p, 1, 0, SGP_KCLASS_ROW_RATIO);
+    L.col(COL_CORRSUM, 1, 1, 1, SGP_KCLASS_COL_CORR);
+    L.row(ROW_RLUPD, 1, 1, 0, SGP_KCLASS_ROW_RLUPD);
+  }
+}
+
+// Setup: validation of data and PSFs, transfer functions, boundary weights,
+// start image, and for SGP one RL step giving A_j f0, J(f0), grad J(f0) and
+// (L1, L2).
+static int setup(sgp_solver* S) {
+  Launcher& L = S->L;
+  const Problem& pb = S->pb;
+  const long long nS = (long long)pb.ny * pb.nx, nF = (long long)pb.NY * pb.NX;
+  L.pix(PIX_VALIDATE, pb.p * nS, 0);
+  for (int j = 0; j < pb.p; ++j) L.pix(PIX_PSFSUM, nF, 0, j);
+  SGP_HIP(hipGetLastError());
+  int rc;
+  if ((rc = read_state(S))) return rc;
+  const int fl = S->pl->host_st->flags;
+  if (fl & FLAG_BAD_PSF) return fail(SGP_E_BAD_PSF, "PSF has negative or non-finite entries or a non-positive sum");
+  if (fl & FLAG_BAD_DATA) return fail(SGP_E_BAD_DATA, "g must be finite and >= 0");
+  if (fl & FLAG_BAD_BG) return fail(SGP_E_BAD_DATA, "background map must be finite and >= 0");
+  // transfer functions K_j / (NY NX): shifted PSF -> row FFT -> column FFT
+  L.row(ROW_PSF, pb.p, 0);
+  L.col(COL_FWD, 0, pb.p, 0);
+  if (pb.boundary) {
+    // alpha_j = K_j correlated with M_S, then R and M_R / alpha
+    L.row(ROW_MASKS, 1, 0);
+    L.col(COL_CONV, 1, 1, 0);
+    L.row(ROW_STORE, pb.p, 0);
+    Args save = L.base;
+    L.base.d = S->pl->invw;
+    L.pix(PIX_INVW, nF, 0);
+    L.base = save;
+  }
+  if (S->prm.init == SGP_INIT_FLAT) L.pix(PIX_FLATSUM, pb.p * nS, 0);
+  L.pix(PIX_INITF, nF, 0);
+  L.base.src = S->f;
+  L.row(ROW_FIELD, 1, 0);
+  if (S->kind == KIND_SGP) {
+    L.col(COL_CONV, 0, 1, 0);
+    L.row(ROW_RATIO, pb.p, 0, 1);
+    L.col(COL_CORRSUM, 1, 1, 0);
+    L.row(ROW_SETUPGRAD, 1, 0);
+  }
+  SGP_HIP(hipGetLastError());
+  if ((rc = read_state(S))) return rc;
+  S->done = S->pl->host_st->done != 0;
+  return 0;
+}
+
+static int capture_graph(sgp_solver* S, int block) {
+  if (S->graph) {
+    (void)hipGraphExecDestroy(S->graph);
+    S->graph = nullptr;
+  }
+  if (S->graph_def) {
+    (void)hipGraphDestroy(S->graph_def);
+    S->graph_def = nullptr;
+  }
+  SGP_HIP(hipStreamBeginCapture(S->s, hipStreamCaptureModeThreadLocal));
+  for (int b = 0; b < block; ++b) enqueue_iteration(S);
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamEndCapture(S->s, &g);
+  if (e != hipSuccess) return fail(SGP_E_HIP, std::string("graph capture: ") + hipGetErrorString(e));
+  S->graph_def = g;
+  SGP_HIP(hipGraphInstantiate(&S->graph, g, nullptr, nullptr, 0));
+  S->graph_block = block;
+  return 0;
+}
+
+static int step(sgp_solver* S, int n, int* done_out) {
+  if (n < 0) return fail(SGP_E_INVALID_ARG, "n must be >= 0");
+  int rc;
+  if (S->done || n == 0) {
+    if (done_out) *done_out = S->done ? 1 : 0;
+    return 0;
+  }
+  launch_resume(S->pl->st, n, S->s);
+  if (S->kind == KIND_RL) {
+    // the spectrum of f is rebuilt so a resumed RL call starts from f
+    Args a = S->L.base;
+    S->L.base.src = S->f;
+    S->L.row(ROW_FIELD, 1, 0);
+    S->L.base = a;
+  }
+  const bool early = (S->prm.stop & (SGP_STOP_CONV | SGP_STOP_DISCREPANCY)) != 0;
+  const int iters = (S->kind == KIND_RL) ? n + 1 : n;  // RL evaluates J once more before pausing
+  if (S->L.timing) {
+    for (int it = 0; it < iters; ++it) {
+      enqueue_iteration(S);
+      if (early && (it % 16) == 15) {
+        if ((rc = read_state(S))) return rc;
+        if (S->pl->host_st->done) break;
+      }
+    }
+    SGP_HIP(hipGetLastError());
+    SGP_HIP(hipStreamSynchronize(S->s));
+    for (auto& m : S->L.marks) {
+      float t = 0;
+      SGP_HIP(hipEventElapsedTime(&t, m.a, m.b));
+      S->ms[m.cls] += t;
+      S->cnt[m.cls] += 1;
+    }
+    S->L.marks.clear();
+    S->L.used = 0;
+  } else {
+    const int block = std::min(iters, 32);
+    if (!S->graph || S->graph_block != block) {
+      if ((rc = capture_graph(S, block))) return rc;
+    }
+    const int reps = (iters + block - 1) / block;
+    for (int r = 0; r < reps; ++r) {
+      SGP_HIP(hipGraphLaunch(S->graph, S->s));
+      if (early && r + 1 < reps && (r % 2) == 1) {
+        if ((rc = read_state(S))) return rc;
+        if (S->pl->host_st->done) break;
+      }
+    }
+  }
+  if ((rc = read_state(S))) return rc;
+  S->done = S->pl->host_st->done != 0;
+  if (done_out) *done_out = S->done ? 1 : 0;
+  return 0;
+}
+
+static int report(sgp_solver* S, sgp_report* rep) {
+  int rc;
+  if ((rc = read_state(S))) return rc;
+  const DevState& h = *S->pl->host_st;
+  if (S->prm.trace && S->pl->trace) {
+    SGP_HIP(hipMemcpy(S->prm.trace, S->pl->trace,
+                      sizeof(double) * kTraceCols * (size_t)(S->prm.max_iter + 1), hipMemcpyDeviceToHost));
+  }
   if (rep) {
     rep->iters = h.k;
     rep->stop_reason = h.reason;
@@ -334,37 +525,55 @@ static int finish(Plan* pl, Launcher& L, const sgp_params& prm, const Problem& p
     rep->flux = std::nan("");
     rep->L1 = h.L1;
     rep->L2 = h.L2;
-    rep->seconds = secs;
+    rep->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - S->t0).count();
   }
-  (void)kind;
+  if (!h.done) return SGP_OK;
   switch (h.reason) {
     case REASON_NUMERIC: return fail(SGP_E_NUMERIC, "non-finite value during the iteration");
     case REASON_ARMIJO: return SGP_W_ARMIJO_EXHAUSTED;
     case REASON_STATIONARY: return SGP_W_STATIONARY;
-    case REASON_MAXITER: return (prm.stop & (SGP_STOP_CONV | SGP_STOP_DISCREPANCY)) ? SGP_W_MAXITER : SGP_OK;
+    case REASON_MAXITER:
+      return (S->prm.stop & (SGP_STOP_CONV | SGP_STOP_DISCREPANCY)) ? SGP_W_MAXITER : SGP_OK;
     default: return SGP_OK;
   }
 }
 
-static int solve(int kind, const Problem& pb, const sgp_params* prm_in, float* f, sgp_report* rep,
-                 void* stream) {
-  const auto t0 = std::chrono::steady_clock::now();
-  sgp_params prm;
-  if (prm_in) prm = *prm_in;
-  else defaults(&prm);
+// Builds a solver; with `cached` the workspace comes from the per-shape cache
+// (one-shot calls, serialised by the caller), otherwise the solver owns it.
+static int create(int kind, const Problem& pb, const sgp_params* prm_in, float* f, void* stream, bool cached,
+                  std::unique_ptr<sgp_solver>& out) {
+  auto S = std::make_unique<sgp_solver>();
+  S->t0 = std::chrono::steady_clock::now();
+  if (prm_in) S->prm = *prm_in;
+  else defaults(&S->prm);
   int rc;
   if (!f) return fail(SGP_E_INVALID_ARG, "f must be non-null");
+  if (kind != KIND_RL && kind != KIND_SGP) return fail(SGP_E_INVALID_ARG, "unknown solver kind");
   if ((rc = check_problem(pb))) return rc;
-  if ((rc = check_params(prm, kind))) return rc;
+  if ((rc = check_params(S->prm, kind))) return rc;
   int dev;
   if ((rc = current_device(&dev))) return rc;
-  std::lock_guard<std::mutex> lock(g_mutex);
-  hipStream_t s = (hipStream_t)stream;
+  S->kind = kind;
+  S->pb = pb;
+  S->f = f;
+  S->user = (hipStream_t)stream;
+  SGP_HIP(hipStreamCreateWithFlags(&S->s, hipStreamNonBlocking));
+  // order the internal stream after the caller's stream
+  hipEvent_t e;
+  SGP_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  SGP_HIP(hipEventRecord(e, S->user));
+  SGP_HIP(hipStreamWaitEvent(S->s, e, 0));
+  SGP_HIP(hipEventDestroy(e));
   PlanKey key{kind, pb.p, pb.NY, pb.NX, pb.ny, pb.nx, pb.oy, pb.ox, pb.boundary ? 1 : 0, dev};
-  Plan* pl;
-  if ((rc = get_plan(key, s, &pl))) return rc;
-  if (prm.trace) {
-    const int rows = prm.max_iter + 1;
+  if (cached) {
+    if ((rc = cached_plan(key, S->s, &S->pl))) return rc;
+  } else {
+    if ((rc = make_plan(key, S->s, S->owned))) return rc;
+    S->pl = S->owned.get();
+  }
+  Plan* pl = S->pl;
+  if (S->prm.trace) {
+    const int rows = S->prm.max_iter + 1;
     if (pl->trace_rows < rows) {
       if (pl->trace) (void)hipFree(pl->trace);
       pl->trace = nullptr;
@@ -372,12 +581,12 @@ static int solve(int kind, const Problem& pb, const sgp_params* prm_in, float* f
       if ((rc = dalloc(&pl->trace, (size_t)rows * kTraceCols))) return rc;
       pl->trace_rows = rows;
     }
-    SGP_HIP(hipMemsetAsync(pl->trace, 0, sizeof(double) * kTraceCols * rows, s));
+    SGP_HIP(hipMemsetAsync(pl->trace, 0, sizeof(double) * kTraceCols * rows, S->s));
   }
-  fill_state(*pl->host_st, prm, pb, prm.trace ? pl->trace : nullptr);
-  SGP_HIP(hipMemcpyAsync(pl->st, pl->host_st, sizeof(DevState), hipMemcpyHostToDevice, s));
+  fill_state(*pl->host_st, S->prm, pb, S->prm.trace ? pl->trace : nullptr);
+  SGP_HIP(hipMemcpyAsync(pl->st, pl->host_st, sizeof(DevState), hipMemcpyHostToDevice, S->s));
 
-  Launcher L;
+  Launcher& L = S->L;
   std::memset(&L.base, 0, sizeof(L.base));
   Args& a = L.base;
   a.NY = pb.NY; a.NX = pb.NX; a.ny = pb.ny; a.nx = pb.nx; a.oy = pb.oy; a.ox = pb.ox; a.p = pb.p;
@@ -387,65 +596,30 @@ static int solve(int kind, const Problem& pb, const sgp_params* prm_in, float* f
   a.invw = pb.boundary ? pl->invw : nullptr;
   a.invw_s = 1.0f / (float)pb.p;
   a.Af = pl->Af; a.Ad = pl->Ad; a.spec = pl->spec; a.khat = pl->khat; a.knyq = pl->knyq;
-  a.psf = pb.psf; a.aux = pl->aux; a.src = prm.f0;
+  a.psf = pb.psf; a.aux = pl->aux; a.src = S->prm.f0;
   a.tw_row = pl->tw_row; a.tw_col = pl->tw_col;
   a.part = pl->part; a.counter = pl->counter; a.st = pl->st;
-  L.s = s; L.NY = pb.NY; L.NX = pb.NX;
+  L.s = S->s; L.NY = pb.NY; L.NX = pb.NX;
+  if ((rc = setup(S.get()))) return rc;
+  out = std::move(S);
+  return 0;
+}
 
-  if ((rc = setup_common(pl, L, pb))) return rc;
-  const long long nS = (long long)pb.ny * pb.nx, nF = (long long)pb.NY * pb.NX;
-  if (prm.init == SGP_INIT_FLAT) L.pix(PIX_FLATSUM, pb.p * nS, 0);
-  L.pix(PIX_INITF, nF, 0);
-  // spectrum of f^(0)
-  a.src = f;
-  L.row(ROW_FIELD, 1, 0);
-  SGP_HIP(hipGetLastError());
-
-  const int block = 8;  // iterations between host checks of the done flag
-  if (kind == KIND_SGP) {
-    // one RL step from f^(0): A_j f^(0), J(f^(0)), grad J(f^(0)), (L1, L2)
-    L.col(COL_CONV, 0, 1, 0);
-    L.row(ROW_RATIO, pb.p, 0, 1);
-    L.col(COL_CORRSUM, 1, 1, 0);
-    L.row(ROW_SETUPGRAD, 1, 0);
-    SGP_HIP(hipGetLastError());
-    for (int it = 0; it < prm.max_iter; it += block) {
-      const int nb = std::min(block, prm.max_iter - it);
-      for (int b = 0; b < nb; ++b) {
-        L.row(ROW_DIR, 1, 1);
-        L.col(COL_CONV, 0, 1, 1);
-        L.row(ROW_AD, pb.p, 1);
-        L.pix(PIX_ARMIJO_MORE, pb.p * nS, 1);
-        L.row(ROW_UPD, pb.p, 1);
-        L.col(COL_CORRSUM, 1, 1, 1);
-        L.row(ROW_GRAD, 1, 1);
-      }
-      SGP_HIP(hipGetLastError());
-      if ((rc = read_state(pl, s))) return rc;
-      if (pl->host_st->done) break;
-    }
-  } else {
-    for (int it = 0; it <= prm.max_iter; it += block) {
-      const int nb = std::min(block, prm.max_iter + 1 - it);
-      for (int b = 0; b < nb; ++b) {
-        L.col(COL_CONV, 0, 1, 1);
-        L.row(ROW_RATIO, pb.p, 1, 0);
-        L.col(COL_CORRSUM, 1, 1, 1);
-        L.row(ROW_RLUPD, 1, 1);
-      }
-      SGP_HIP(hipGetLastError());
-      if ((rc = read_state(pl, s))) return rc;
-      if (pl->host_st->done) break;
-    }
-  }
-  return finish(pl, L, prm, pb, rep, t0, kind);
+static int one_shot(int kind, const Problem& pb, const sgp_params* prm, float* f, sgp_report* rep, void* stream) {
+  std::lock_guard<std::mutex> lock(g_mutex);
+  std::unique_ptr<sgp_solver> S;
+  int rc = create(kind, pb, prm, f, stream, true, S);
+  if (rc) return rc;
+  const int n = S->prm.max_iter;
+  if ((rc = step(S.get(), n, nullptr))) return rc;
+  return report(S.get(), rep);
 }
 
 static int apply_operator(const float* psf, const float* x, int ny, int nx, int adjoint, float* out,
                           void* stream) {
   if (!psf || !x || !out) return fail(SGP_E_INVALID_ARG, "null pointer");
   Problem pb;
-  pb.g = x;  // validated like data only for finiteness of the PSF; x may be signed
+  pb.g = x;
   pb.psf = psf;
   pb.p = 1; pb.ny = pb.NY = ny; pb.nx = pb.NX = nx;
   int rc;
@@ -456,7 +630,7 @@ static int apply_operator(const float* psf, const float* x, int ny, int nx, int 
   hipStream_t s = (hipStream_t)stream;
   PlanKey key{KIND_OP, 1, ny, nx, ny, nx, 0, 0, 0, dev};
   Plan* pl;
-  if ((rc = get_plan(key, s, &pl))) return rc;
+  if ((rc = cached_plan(key, s, &pl))) return rc;
   sgp_params prm;
   defaults(&prm);
   fill_state(*pl->host_st, prm, pb, nullptr);
@@ -470,7 +644,8 @@ static int apply_operator(const float* psf, const float* x, int ny, int nx, int 
   a.invw_s = 1.f;
   L.s = s; L.NY = ny; L.NX = nx;
   L.pix(PIX_PSFSUM, (long long)ny * nx, 0, 0);
-  if ((rc = read_state(pl, s))) return rc;
+  SGP_HIP(hipMemcpyAsync(pl->host_st, pl->st, sizeof(DevState), hipMemcpyDeviceToHost, s));
+  SGP_HIP(hipStreamSynchronize(s));
   if (pl->host_st->flags & FLAG_BAD_PSF) return fail(SGP_E_BAD_PSF, "PSF has negative or non-finite entries or a non-positive sum");
   L.row(ROW_PSF, 1, 0);
   L.col(COL_FWD, 0, 1, 0);
@@ -484,13 +659,25 @@ static int apply_operator(const float* psf, const float* x, int ny, int nx, int 
   return 0;
 }
 
+static int to_problem(const sgp_problem* pr, Problem& pb) {
+  if (!pr) return fail(SGP_E_INVALID_ARG, "null problem");
+  if (pr->p < 1 || pr->p > kMaxP) return fail(SGP_E_INVALID_ARG, "p must be in 1..8");
+  if (!pr->b_map && !pr->b_const) return fail(SGP_E_INVALID_ARG, "need b_map or b_const");
+  pb.g = pr->g; pb.psf = pr->psf; pb.bmap = pr->b_map;
+  for (int j = 0; j < pr->p; ++j) pb.b[j] = pr->b_const ? pr->b_const[j] : 0.f;
+  pb.p = pr->p; pb.ny = pr->ny; pb.nx = pr->nx;
+  pb.boundary = pr->boundary != 0;
+  if (pb.boundary) {
+    pb.NY = pr->NY; pb.NX = pr->NX; pb.oy = pr->oy; pb.ox = pr->ox;
+  } else {
+    pb.NY = pr->ny; pb.NX = pr->nx; pb.oy = pb.ox = 0;
+  }
+  return 0;
+}
+
 }  // namespace sgp
 
 using namespace sgp;
-
-static void fill_b(Problem& pb, const float* b_const, int p) {
-  for (int j = 0; j < p && j < kMaxP; ++j) pb.b[j] = b_const ? b_const[j] : 0.f;
-}
 
 extern "C" {
 
@@ -500,80 +687,147 @@ int sgp_params_init(sgp_params* p) {
   return SGP_OK;
 }
 
+#define SGP_GUARD(expr)                                      \
+  try {                                                      \
+    return (expr);                                           \
+  } catch (...) {                                            \
+    return fail(SGP_E_HIP, "internal error");                \
+  }
+
 static int single(int kind, const float* g, const float* psf, const float* b_map, float b_const, int ny,
                   int nx, const sgp_params* prm, float* f, sgp_report* rep, void* stream) {
   Problem pb;
   pb.g = g; pb.psf = psf; pb.bmap = b_map; pb.b[0] = b_const;
   pb.p = 1; pb.ny = pb.NY = ny; pb.nx = pb.NX = nx;
-  return solve(kind, pb, prm, f, rep, stream);
+  return one_shot(kind, pb, prm, f, rep, stream);
 }
 
 int rl_deconv(const float* g, const float* psf, const float* b_map, float b_const, int ny, int nx,
               const sgp_params* prm, float* f, sgp_report* rep, void* hip_stream) {
-  try { return single(KIND_RL, g, psf, b_map, b_const, ny, nx, prm, f, rep, hip_stream); }
-  catch (...) { return fail(SGP_E_HIP, "internal error"); }
+  SGP_GUARD(single(KIND_RL, g, psf, b_map, b_const, ny, nx, prm, f, rep, hip_stream));
 }
 
 int sgp_deconv(const float* g, const float* psf, const float* b_map, float b_const, int ny, int nx,
                const sgp_params* prm, float* f, sgp_report* rep, void* hip_stream) {
-  try { return single(KIND_SGP, g, psf, b_map, b_const, ny, nx, prm, f, rep, hip_stream); }
-  catch (...) { return fail(SGP_E_HIP, "internal error"); }
+  SGP_GUARD(single(KIND_SGP, g, psf, b_map, b_const, ny, nx, prm, f, rep, hip_stream));
 }
 
-static int multi(int kind, const float* g, const float* psf, const float* b_map, const float* b_const, int p,
-                 int ny, int nx, const sgp_params* prm, float* f, sgp_report* rep, void* stream) {
-  if (!b_map && !b_const) return fail(SGP_E_INVALID_ARG, "need b_map or b_const");
-  if (p < 1 || p > kMaxP) return fail(SGP_E_INVALID_ARG, "p must be in 1..8");
+static int stack(int kind, const float* g, const float* psf, const float* b_map, const float* b_const, int p,
+                 int ny, int nx, int NY, int NX, int oy, int ox, int boundary, const sgp_params* prm, float* f,
+                 sgp_report* rep, void* stream) {
+  sgp_problem pr{g, psf, b_map, b_const, p, ny, nx, NY, NX, oy, ox, boundary};
   Problem pb;
-  pb.g = g; pb.psf = psf; pb.bmap = b_map;
-  fill_b(pb, b_const, p);
-  pb.p = p; pb.ny = pb.NY = ny; pb.nx = pb.NX = nx;
-  return solve(kind, pb, prm, f, rep, stream);
+  int rc = to_problem(&pr, pb);
+  if (rc) return rc;
+  return one_shot(kind, pb, prm, f, rep, stream);
 }
 
 int sgp_multi_deconv(const float* g, const float* psf, const float* b_map, const float* b_const, int p,
                      int ny, int nx, const sgp_params* prm, float* f, sgp_report* rep, void* hip_stream) {
-  try { return multi(KIND_SGP, g, psf, b_map, b_const, p, ny, nx, prm, f, rep, hip_stream); }
-  catch (...) { return fail(SGP_E_HIP, "internal error"); }
+  SGP_GUARD(stack(KIND_SGP, g, psf, b_map, b_const, p, ny, nx, ny, nx, 0, 0, 0, prm, f, rep, hip_stream));
 }
 
 int rl_multi_deconv(const float* g, const float* psf, const float* b_map, const float* b_const, int p,
                     int ny, int nx, const sgp_params* prm, float* f, sgp_report* rep, void* hip_stream) {
-  try { return multi(KIND_RL, g, psf, b_map, b_const, p, ny, nx, prm, f, rep, hip_stream); }
-  catch (...) { return fail(SGP_E_HIP, "internal error"); }
-}
-
-static int bnd(int kind, const float* g, const float* psf, const float* b_map, const float* b_const, int p,
-               int ny, int nx, int NY, int NX, int oy, int ox, const sgp_params* prm, float* f,
-               sgp_report* rep, void* stream) {
-  if (!b_map && !b_const) return fail(SGP_E_INVALID_ARG, "need b_map or b_const");
-  if (p < 1 || p > kMaxP) return fail(SGP_E_INVALID_ARG, "p must be in 1..8");
-  Problem pb;
-  pb.g = g; pb.psf = psf; pb.bmap = b_map;
-  fill_b(pb, b_const, p);
-  pb.p = p; pb.ny = ny; pb.nx = nx; pb.NY = NY; pb.NX = NX; pb.oy = oy; pb.ox = ox;
-  pb.boundary = true;
-  return solve(kind, pb, prm, f, rep, stream);
+  SGP_GUARD(stack(KIND_RL, g, psf, b_map, b_const, p, ny, nx, ny, nx, 0, 0, 0, prm, f, rep, hip_stream));
 }
 
 int sgp_boundary_deconv(const float* g, const float* psf, const float* b_map, const float* b_const, int p,
                         int ny, int nx, int NY, int NX, int oy, int ox, const sgp_params* prm, float* f,
                         sgp_report* rep, void* hip_stream) {
-  try { return bnd(KIND_SGP, g, psf, b_map, b_const, p, ny, nx, NY, NX, oy, ox, prm, f, rep, hip_stream); }
-  catch (...) { return fail(SGP_E_HIP, "internal error"); }
+  SGP_GUARD(stack(KIND_SGP, g, psf, b_map, b_const, p, ny, nx, NY, NX, oy, ox, 1, prm, f, rep, hip_stream));
 }
 
 int rl_boundary_deconv(const float* g, const float* psf, const float* b_map, const float* b_const, int p,
                        int ny, int nx, int NY, int NX, int oy, int ox, const sgp_params* prm, float* f,
                        sgp_report* rep, void* hip_stream) {
-  try { return bnd(KIND_RL, g, psf, b_map, b_const, p, ny, nx, NY, NX, oy, ox, prm, f, rep, hip_stream); }
-  catch (...) { return fail(SGP_E_HIP, "internal error"); }
+  SGP_GUARD(stack(KIND_RL, g, psf, b_map, b_const, p, ny, nx, NY, NX, oy, ox, 1, prm, f, rep, hip_stream));
 }
 
 int sgp_apply_operator(const float* psf, const float* x, int ny, int nx, int adjoint, float* out,
                        void* hip_stream) {
-  try { return apply_operator(psf, x, ny, nx, adjoint, out, hip_stream); }
-  catch (...) { return fail(SGP_E_HIP, "internal error"); }
+  SGP_GUARD(apply_operator(psf, x, ny, nx, adjoint, out, hip_stream));
+}
+
+static int solver_create(int kind, const sgp_problem* prob, const sgp_params* prm, float* f, void* stream,
+                         sgp_solver** out) {
+  if (!out) return fail(SGP_E_INVALID_ARG, "null output pointer");
+  *out = nullptr;
+  Problem pb;
+  int rc = to_problem(prob, pb);
+  if (rc) return rc;
+  std::unique_ptr<sgp_solver> S;
+  if ((rc = create(kind, pb, prm, f, stream, false, S))) return rc;
+  *out = S.release();
+  return 0;
+}
+
+int sgp_solver_create(int kind, const sgp_problem* prob, const sgp_params* prm, float* f, void* hip_stream,
+                      sgp_solver** out) {
+  SGP_GUARD(solver_create(kind, prob, prm, f, hip_stream, out));
+}
+
+int sgp_solver_step(sgp_solver* s, int n, int* done) {
+  if (!s) return fail(SGP_E_INVALID_ARG, "null solver");
+  SGP_GUARD(step(s, n, done));
+}
+
+int sgp_solver_report(sgp_solver* s, sgp_report* rep) {
+  if (!s) return fail(SGP_E_INVALID_ARG, "null solver");
+  SGP_GUARD(report(s, rep));
+}
+
+int sgp_solver_set_timing(sgp_solver* s, int enable) {
+  if (!s) return fail(SGP_E_INVALID_ARG, "null solver");
+  s->L.timing = enable != 0;
+  for (int i = 0; i < SGP_KCLASS_COUNT; ++i) {
+    s->ms[i] = 0;
+    s->cnt[i] = 0;
+  }
+  return 0;
+}
+
+int sgp_solver_timing(sgp_solver* s, double* ms, long long* counts, int ncls) {
+  if (!s || !ms || !counts) return fail(SGP_E_INVALID_ARG, "null pointer");
+  for (int i = 0; i < ncls && i < SGP_KCLASS_COUNT; ++i) {
+    ms[i] = s->ms[i];
+    counts[i] = s->cnt[i];
+  }
+  return 0;
+}
+
+int sgp_solver_destroy(sgp_solver* s) {
+  if (!s) return 0;
+  (void)hipStreamSynchronize(s->s);
+  delete s;
+  return 0;
+}
+
+int sgp_steplength_rule(const sgp_params* prm, int k, double alpha, double tau, const double* Q, int nQ,
+                        double a, double c1, double c2, double e, double* out) {
+  if (!prm || !out || nQ < 0 || nQ > 8 || (nQ > 0 && !Q)) return fail(SGP_E_INVALID_ARG, "bad arguments");
+  DevState st;
+  std::memset(&st, 0, sizeof(st));
+  st.m_alpha = prm->m_alpha;
+  st.n_bb2_only = prm->n_bb2_only;
+  st.alpha_min = prm->alpha_min;
+  st.alpha_max = prm->alpha_max;
+  st.alpha = alpha;
+  st.tau = tau;
+  st.k = k + 1;          // iterations completed
+  st.nQ = std::min(nQ, prm->m_alpha);
+  for (int i = 0; i < st.nQ; ++i) st.Q[i] = Q[nQ - st.nQ + i];
+  const BBInfo r = bb_rule(&st, a, c1, c2, e);
+  out[0] = r.a1;
+  out[1] = r.a2;
+  out[2] = r.next;
+  out[3] = st.tau;
+  out[4] = r.alt;
+  out[5] = r.br1;
+  out[6] = r.br2;
+  out[7] = st.nQ;
+  for (int i = 0; i < 8; ++i) out[8 + i] = i < st.nQ ? st.Q[i] : 0.0;
+  return 0;
 }
 
 int sgp_release_cache(void) {

@@ -93,3 +93,29 @@ def test_rejects_bad_background_and_window(lib):
 def test_strerror(lib):
     assert lib.sgp_strerror(-2) == b"unsupported FFT size"
     assert lib.sgp_strerror(0) == b"success"
+
+
+def test_device_steplength_rule_matches_hand_table(lib):
+    """The steplength rule the GPU runs (same source, compiled for the host)
+    against the hand-computed table of Sect. 2.1 decisions."""
+    import numpy as np
+    from paper_1210_2258_amd import steplength_rule
+    path = os.path.join(ROOT, "tests", "golden", "steplength_rules.txt")
+    rows = []
+    for line in open(path):
+        line = line.split("#")[0].strip()
+        if line:
+            rows.append(line.split("|"))
+    assert len(rows) >= 8
+    for r in rows:
+        k, alpha, tau = int(r[0]), float(r[1]), float(r[2])
+        Q = [float(v) for v in r[3].split()] if r[3].strip() else []
+        a, c1, c2, e = (float(v) for v in r[4].split())
+        ea1, ea2, enext, etau, ealt = (float(v) for v in r[5].split())
+        out = steplength_rule(k, alpha, tau, Q, a, c1, c2, e)
+        assert np.isclose(out["a1"], ea1, rtol=1e-15), r
+        assert np.isclose(out["a2"], ea2, rtol=1e-15), r
+        assert np.isclose(out["alpha_next"], enext, rtol=1e-15), r
+        assert np.isclose(out["tau"], etau, rtol=1e-15), r
+        assert out["alt"] == int(ealt), r
+        assert len(out["Q"]) <= 3 and out["Q"][-1] == out["a2"]

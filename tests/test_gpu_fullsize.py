@@ -1,0 +1,73 @@
+"""Parity at the benchmark workloads' full sizes, in the launch
+configuration bench.py times: 2048x2048 single image, 3 x 1024x1024
+multi-image, boundary correction on 1280x1280 with a 1024x1024 window."""
+import numpy as np
+import pytest
+
+from oracle import sgp as O
+from synth import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+K = 10
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1210_2258_amd as m
+    m.load()
+    return torch
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(np.asarray(a, np.float64) - b) / np.linalg.norm(b))
+
+
+@pytest.mark.parametrize("cfg", ["c1_2048", "c2_multi_3x1024", "c3_boundary_1280"])
+def test_full_size_sgp_parity(torch_dev, cfg):
+    import paper_1210_2258_amd as m
+    torch = torch_dev
+    w = {"c1_2048": W.config1, "c2_multi_3x1024": W.config2, "c3_boundary_1280": W.config3}[cfg]()
+    g = torch.from_numpy(np.ascontiguousarray(w.g)).cuda()
+    psf = torch.from_numpy(np.ascontiguousarray(w.psf)).cuda()
+    if w.domain is not None:
+        f, rep = m.sgp_boundary_deconv(g, psf, w.b, w.domain, max_iter=K, trace=True)
+    elif w.p > 1:
+        f, rep = m.sgp_multi_deconv(g, psf, w.b, max_iter=K, trace=True)
+    else:
+        f, rep = m.sgp_deconv(g[0], psf[0], float(w.b[0]), max_iter=K, trace=True)
+    P = O.Problem(w.g, w.psf, w.b, domain=w.domain)
+    fo, io = P.sgp(P.start("flat"), O.Params(max_iter=K))
+    for k in range(K):
+        assert int(rep["trace"]["backtracks"][k]) == io["log"][k]["backtracks"], k
+    assert _rel(f.cpu().numpy(), fo) <= 1e-4, _rel(f.cpu().numpy(), fo)
+    assert abs(rep["kl"] - io["kl"]) <= 1e-6 * io["kl"], (rep["kl"], io["kl"])
+
+
+def test_full_size_operator_sampled(torch_dev):
+    """A and A^T at 2048x2048 against the direct definition of the periodic
+    convolution at sampled output pixels (each a full O(N) sum)."""
+    import paper_1210_2258_amd as m
+    torch = torch_dev
+    w = W.config1()
+    psf = w.psf[0].astype(np.float64)
+    K = psf / psf.sum()
+    ny, nx = K.shape
+    rng = np.random.default_rng(5)
+    x = rng.random((ny, nx)).astype(np.float32)
+    A = m.apply_operator(torch.from_numpy(w.psf[0]).cuda(), torch.from_numpy(x).cuda()).cpu().numpy()
+    AT = m.apply_operator(torch.from_numpy(w.psf[0]).cuda(), torch.from_numpy(x).cuda(), adjoint=True).cpu().numpy()
+    xd = x.astype(np.float64)
+    yy = np.arange(ny)[:, None]
+    xx = np.arange(nx)[None, :]
+    for (my, mx) in rng.integers(0, 2048, (6, 2)):
+        # (A x)[m] = sum_n K[(m - n) + c] x[n]  (periodic, centre c = (ny//2, nx//2))
+        kk = K[(my - yy + ny // 2) % ny, (mx - xx + nx // 2) % nx]
+        ref = np.sum(kk * xd)
+        assert abs(A[my, mx] - ref) <= 2e-6 * abs(ref)
+        kt = K[(yy - my + ny // 2) % ny, (xx - mx + nx // 2) % nx]
+        ref_t = np.sum(kt * xd)
+        assert abs(AT[my, mx] - ref_t) <= 2e-6 * abs(ref_t)
