@@ -45,7 +45,9 @@ def parse():
     ap.add_argument("--steps", type=int, default=400)
     ap.add_argument("--warmup", type=int, default=40)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle timing")
-    ap.add_argument("--cpu-iters", type=int, default=3)
+    ap.add_argument("--cpu-iters", type=int, default=8)
+    ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
+                    help="also run a plain device copy of this many MiB (counter calibration)")
     ap.add_argument("--size", type=int, default=2048)
     return ap.parse_args()
 
@@ -93,6 +95,17 @@ def main():
     psf = torch.from_numpy(w.psf[0]).cuda()
     b = float(w.b[0])
     torch.cuda.synchronize()
+
+    if args.copy_calib:
+        # a plain copy of known size: FETCH_SIZE / WRITE_SIZE of this dispatch
+        # give the counters' scale for the solver kernels
+        n = args.copy_calib * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     # ---- throughput: W warm-up iterations, then exactly K timed iterations
     total = args.warmup + args.steps

@@ -213,7 +213,7 @@ int sgp_solver_report(sgp_solver* s, sgp_report* rep);
 #define SGP_KCLASS_ROW_DIR 0      /* scaling, projection, direction + row FFT */
 #define SGP_KCLASS_COL_CONV 1     /* column FFT x K x IFFT */
 #define SGP_KCLASS_ROW_AD 2       /* row IFFT -> A d, Armijo candidates */
-#define SGP_KCLASS_ARMIJO_MORE 3  /* further Armijo candidates (early exit if not needed) */
+#define SGP_KCLASS_ARMIJO_MORE 3  /* further Armijo candidates, two launches (early exit if not needed) */
 #define SGP_KCLASS_ROW_UPD 4      /* update f, A f, residual change + row FFT */
 #define SGP_KCLASS_COL_CORR 5     /* column FFT x conj K x IFFT, summed over images */
 #define SGP_KCLASS_ROW_GRAD 6     /* row IFFT -> gradient, BB sums */
@@ -221,6 +221,9 @@ int sgp_solver_report(sgp_solver* s, sgp_report* rep);
 #define SGP_KCLASS_ROW_RLUPD 8    /* RL: row IFFT -> update -> row FFT */
 #define SGP_KCLASS_COUNT 9
 int sgp_solver_set_timing(sgp_solver* s, int enable);
+/* Graph replay of the iteration loop (default on); off launches every kernel
+ * from the host. */
+int sgp_solver_set_graph(sgp_solver* s, int enable);
 int sgp_solver_timing(sgp_solver* s, double* ms, long long* counts, int ncls);
 int sgp_solver_destroy(sgp_solver* s);
 

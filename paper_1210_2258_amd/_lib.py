@@ -70,7 +70,7 @@ EXPORTS = [
     "sgp_params_init", "rl_deconv", "sgp_deconv", "sgp_multi_deconv", "rl_multi_deconv",
     "sgp_boundary_deconv", "rl_boundary_deconv", "sgp_apply_operator", "sgp_release_cache",
     "sgp_strerror", "sgp_last_error", "sgp_solver_create", "sgp_solver_step", "sgp_solver_report",
-    "sgp_solver_set_timing", "sgp_solver_timing", "sgp_solver_destroy", "sgp_steplength_rule",
+    "sgp_solver_set_timing", "sgp_solver_set_graph", "sgp_solver_timing", "sgp_solver_destroy", "sgp_steplength_rule",
 ]
 
 _lib = None
@@ -98,6 +98,7 @@ def load():
     lib.sgp_solver_step.argtypes = [vp, i, ctypes.POINTER(i)]
     lib.sgp_solver_report.argtypes = [vp, R]
     lib.sgp_solver_set_timing.argtypes = [vp, i]
+    lib.sgp_solver_set_graph.argtypes = [vp, i]
     lib.sgp_solver_timing.argtypes = [vp, ctypes.POINTER(d), ctypes.POINTER(ctypes.c_longlong), i]
     lib.sgp_solver_destroy.argtypes = [vp]
     lib.sgp_steplength_rule.argtypes = [P, i, d, d, ctypes.POINTER(d), i, d, d, d, d, ctypes.POINTER(d)]
@@ -324,6 +325,9 @@ class Solver:
 
     def set_timing(self, on=True):
         _raise(load().sgp_solver_set_timing(self._h, 1 if on else 0))
+
+    def set_graph(self, on=True):
+        _raise(load().sgp_solver_set_graph(self._h, 1 if on else 0))
 
     def timing(self):
         n = len(KCLASSES)

@@ -111,7 +111,8 @@ enum PixOp {
   PIX_FLATSUM,      // sum_S (g - b) over all images -> flat start value
   PIX_INITF,        // write the start image
   PIX_INVW,         // boundary: R mask and M_R / alpha from aux (alpha_j)
-  PIX_ARMIJO_MORE,  // further Armijo candidates theta^2 ..
+  PIX_ARMIJO_MORE,  // further Armijo candidates theta^2 .. theta^9
+  PIX_ARMIJO_REST,  // the remaining candidates theta^10 .. theta^40
   PIX_NOPS
 };
 

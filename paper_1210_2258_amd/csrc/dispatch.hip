@@ -12,6 +12,7 @@ namespace sgp {
   void launch_col_##L(int mode, int conj, dim3 grid, const Args& a, hipStream_t s); \
   int col_width_##L();                                                        \
   int row_threads_##L();                                                      \
+  int row_pairs_##L();                                                        \
   int col_threads_##L();
 SGP_SIZES(SGP_DECL)
 #undef SGP_DECL
@@ -28,6 +29,15 @@ bool size_supported(int L) {
 int col_width(int L) {
   switch (L) {
 #define SGP_CASE(L) case L: return col_width_##L();
+    SGP_SIZES(SGP_CASE)
+#undef SGP_CASE
+    default: return 0;
+  }
+}
+
+int row_pairs(int L) {
+  switch (L) {
+#define SGP_CASE(L) case L: return row_pairs_##L();
     SGP_SIZES(SGP_CASE)
 #undef SGP_CASE
     default: return 0;
@@ -80,6 +90,7 @@ void launch_pix(int op, dim3 grid, const Args& a, hipStream_t s) {
     SGP_PIX_CASE(PIX_INITF)
     SGP_PIX_CASE(PIX_INVW)
     SGP_PIX_CASE(PIX_ARMIJO_MORE)
+    SGP_PIX_CASE(PIX_ARMIJO_REST)
 #undef SGP_PIX_CASE
     default: break;
   }

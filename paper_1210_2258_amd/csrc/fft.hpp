@@ -30,30 +30,44 @@ __device__ __forceinline__ float2 cscale(float2 a, float s) { return make_float2
 __device__ __forceinline__ float2 mul_mi(float2 a) { return make_float2(a.y, -a.x); }  // a * (-i)
 __device__ __forceinline__ float2 mul_pi(float2 a) { return make_float2(-a.y, a.x); }  // a * (+i)
 
+// LDS index map for length-L transforms.  For power-of-two lengths bits 5-7
+// of the logical index are XORed into bits 0-4 (a bijection), which spreads
+// the stride-8 and stride-64 Stockham writes over all banks while keeping
+// runs of 32 consecutive indices conflict-free.  Other lengths use the
+// identity.
+template <int L>
+__host__ __device__ constexpr int lds_idx(int o) {
+  if constexpr ((L & (L - 1)) == 0) return o ^ (((o >> 5) & 7) | (((o >> 6) & 3) << 3));
+  else return o;
+}
+
 // ------------------------------------------------------------------ plans
 // L: transform length; E: elements per thread (a multiple of every radix);
 // TF = L / E threads per transform; R[]: radices in pass order.
 template <int L> struct FftPlan;
-#define SGP_FFT_PLAN(L_, E_, NP_, R0, R1, R2, R3)                            \
+#define SGP_FFT_PLAN(L_, E_, NP_, R0, R1, R2, R3, R4)                        \
   template <> struct FftPlan<L_> {                                          \
     static constexpr int len = L_, E = E_, TF = L_ / E_, NP = NP_;          \
-    static constexpr int r0 = R0, r1 = R1, r2 = R2, r3 = R3;                \
+    static constexpr int r0 = R0, r1 = R1, r2 = R2, r3 = R3, r4 = R4;       \
   };
-SGP_FFT_PLAN(16, 4, 2, 4, 4, 1, 1)
-SGP_FFT_PLAN(32, 8, 2, 8, 4, 1, 1)
-SGP_FFT_PLAN(64, 8, 2, 8, 8, 1, 1)
-SGP_FFT_PLAN(128, 8, 3, 8, 4, 4, 1)
-SGP_FFT_PLAN(256, 8, 3, 8, 8, 4, 1)
-SGP_FFT_PLAN(512, 8, 3, 8, 8, 8, 1)
-SGP_FFT_PLAN(1024, 8, 4, 8, 8, 4, 4)
-SGP_FFT_PLAN(2048, 16, 4, 8, 8, 8, 4)
-SGP_FFT_PLAN(4096, 16, 4, 8, 8, 8, 8)
-SGP_FFT_PLAN(80, 20, 3, 5, 4, 4, 1)
-SGP_FFT_PLAN(160, 40, 3, 5, 8, 4, 1)
-SGP_FFT_PLAN(320, 40, 3, 5, 8, 8, 1)
-SGP_FFT_PLAN(640, 40, 4, 5, 8, 4, 4)
-SGP_FFT_PLAN(1280, 40, 4, 5, 8, 8, 4)
-SGP_FFT_PLAN(2560, 40, 4, 5, 8, 8, 8)
+SGP_FFT_PLAN(16, 4, 2, 4, 4, 1, 1, 1)
+SGP_FFT_PLAN(32, 8, 2, 8, 4, 1, 1, 1)
+SGP_FFT_PLAN(64, 8, 2, 8, 8, 1, 1, 1)
+SGP_FFT_PLAN(128, 8, 3, 8, 4, 4, 1, 1)
+SGP_FFT_PLAN(256, 8, 3, 8, 8, 4, 1, 1)
+SGP_FFT_PLAN(512, 8, 3, 8, 8, 8, 1, 1)
+SGP_FFT_PLAN(1024, 8, 4, 8, 8, 4, 4, 1)
+#ifndef SGP_E2048
+#define SGP_E2048 8
+#endif
+SGP_FFT_PLAN(2048, SGP_E2048, 4, 8, 8, 8, 4, 1)
+SGP_FFT_PLAN(4096, 16, 4, 8, 8, 8, 8, 1)
+SGP_FFT_PLAN(80, 20, 3, 5, 4, 4, 1, 1)
+SGP_FFT_PLAN(160, 20, 4, 5, 4, 4, 2, 1)
+SGP_FFT_PLAN(320, 20, 4, 5, 4, 4, 4, 1)
+SGP_FFT_PLAN(640, 20, 5, 5, 4, 4, 4, 2)
+SGP_FFT_PLAN(1280, 20, 5, 5, 4, 4, 4, 4)
+SGP_FFT_PLAN(2560, 40, 4, 5, 8, 8, 8, 1)
 #undef SGP_FFT_PLAN
 
 // ------------------------------------------------------------- butterflies
@@ -125,7 +139,7 @@ __device__ __forceinline__ void stockham_pass(float2* buf, int lane, const float
   for (int q = 0; q < PER; ++q) {
     const int j = lane + q * TF;
 #pragma unroll
-    for (int i = 0; i < R; ++i) v[q][i] = buf[j + i * NB];
+    for (int i = 0; i < R; ++i) v[q][i] = buf[lds_idx<L>(j + i * NB)];
   }
   __syncthreads();
 #pragma unroll
@@ -139,12 +153,13 @@ __device__ __forceinline__ void stockham_pass(float2* buf, int lane, const float
     dft<R>(v[q]);
     const int base = (j / NS) * NS * R + k;
 #pragma unroll
-    for (int i = 0; i < R; ++i) buf[base + i * NS] = v[q][i];
+    for (int i = 0; i < R; ++i) buf[lds_idx<L>(base + i * NS)] = v[q][i];
   }
   __syncthreads();
 }
 
-// Forward FFT of buf[0..L) in place (natural order in and out).  Every thread
+// Forward FFT of buf (logical index i stored at lds_idx<L>(i)) in place,
+// natural order in and out.  Every thread
 // of the workgroup must call this (it contains barriers).
 template <int L>
 __device__ __forceinline__ void fft_lds(float2* buf, int lane, const float2* __restrict__ tw) {
@@ -154,6 +169,7 @@ __device__ __forceinline__ void fft_lds(float2* buf, int lane, const float2* __r
   stockham_pass<L, TF, P::r1, P::r0>(buf, lane, tw);
   if constexpr (P::NP > 2) stockham_pass<L, TF, P::r2, P::r0 * P::r1>(buf, lane, tw);
   if constexpr (P::NP > 3) stockham_pass<L, TF, P::r3, P::r0 * P::r1 * P::r2>(buf, lane, tw);
+  if constexpr (P::NP > 4) stockham_pass<L, TF, P::r4, P::r0 * P::r1 * P::r2 * P::r3>(buf, lane, tw);
 }
 
 }  // namespace sgp

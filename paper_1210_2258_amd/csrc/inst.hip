@@ -14,7 +14,7 @@ namespace sgp {
 
 void SGP_CAT(launch_row_, SGP_L)(int op, dim3 grid, const Args& a, hipStream_t s) {
   constexpr int L = SGP_L;
-  const dim3 blk(kRP * FftPlan<L>::TF);
+  const dim3 blk(RowCfg<L>::NT);
   switch (op) {
 #define SGP_ROW_CASE(OPV) case OPV: hipLaunchKernelGGL((row_kernel<L, OPV>), grid, blk, 0, s, a); break;
     SGP_ROW_CASE(ROW_PSF)
@@ -43,7 +43,8 @@ void SGP_CAT(launch_col_, SGP_L)(int mode, int conj, dim3 grid, const Args& a, h
 }
 
 int SGP_CAT(col_width_, SGP_L)() { return ColCfg<SGP_L>::C; }
-int SGP_CAT(row_threads_, SGP_L)() { return kRP * FftPlan<SGP_L>::TF; }
+int SGP_CAT(row_threads_, SGP_L)() { return RowCfg<SGP_L>::NT; }
+int SGP_CAT(row_pairs_, SGP_L)() { return RowCfg<SGP_L>::RP; }
 int SGP_CAT(col_threads_, SGP_L)() { return ColCfg<SGP_L>::NT; }
 
 }  // namespace sgp

@@ -61,10 +61,31 @@ struct Pix {
   __device__ float w(long long pix) const { return a.invw ? a.invw[pix] : a.invw_s; }
 };
 
-// KL term g ln(g / y) + y - g (y when g = 0), Eq. (divergence), in FP64.
+// h(x) = x - log1p(x) for x > -1 without cancellation: the alternating
+// series x^2 (1/2 - x/3 + x^2/4 - ...) for |x| < 1/2 (24 terms, truncation
+// below 5e-9 relative), x - log1p(x) otherwise (relative error below 3e-7
+// there since |log1p(x)| < 4 h(x) for |x| >= 1/2).
+__device__ __forceinline__ float h_x(float x) {
+  if (fabsf(x) < 0.5f) {
+    float q = 1.0f / 25.0f;
+#pragma unroll
+    for (int k = 24; k >= 2; --k) q = 1.0f / (float)k - x * q;
+    return x * x * q;
+  }
+  return x - log1pf(x);
+}
+
+// KL term g ln(g / y) + y - g of Eq. (divergence) (y when g = 0), written as
+// g h((y - g) / g).
 __device__ __forceinline__ double kl_term(float g, float y) {
-  const double gd = g, yd = y;
-  return g > 0.f ? gd * log(gd / yd) + yd - gd : yd;
+  return g > 0.f ? (double)(g * h_x((y - g) / g)) : (double)y;
+}
+
+// J(f + lam d) - J(f) contribution of one pixel with y = A f + b, t = lam A d:
+// t - g log1p(t / y) = (y - g) x + g h(x) with x = t / y.
+__device__ __forceinline__ double armijo_term(float g, float y, float t) {
+  const float x = t / y;
+  return (double)((y - g) * x) + (double)(g * h_x(x));
 }
 
 // One pixel of the pointwise stage.  v: result of the inverse transform at
@@ -126,12 +147,7 @@ __device__ __forceinline__ float row_point(const Args& a, const DevState* st, in
     const float g = a.g[s];
     const float yv = fmaxf(a.Af[s] + P.bg(s), 1e-30f);
 #pragma unroll
-    for (int m = 0; m < 2; ++m) {
-      const float t = (float)st->lam_tab[m] * v;
-      double term = t;
-      if (g > 0.f) term -= (double)g * (double)log1pf(t / yv);
-      acc[m] += term;
-    }
+    for (int m = 0; m < 2; ++m) acc[m] += armijo_term(g, yv, (float)st->lam_tab[m] * v);
     return 0.f;
   } else if constexpr (OP == ROW_UPD) {
     // f += lam d, A_j f += lam A_j d; feeds delta rho_j = g/y_new - g/y_old
@@ -199,22 +215,47 @@ struct RowKinds {
   }
 };
 
+// Workgroup index -> work index such that the g workgroups sharing one
+// 128-byte spectrum line (an 8-row block, or two columns of one) land on the
+// same XCD: the hardware deals linear workgroup ids round-robin over the 8
+// XCDs, so consecutive work indices are taken from one XCD's share.
+__device__ __forceinline__ int xcd_remap(int w, int n, int g) {
+#ifndef SGP_NO_XCD_REMAP
+  if ((n & 7) == 0 && ((n >> 3) % g) == 0) return (w & 7) * (n >> 3) + (w >> 3);
+#endif
+  return w;
+}
+
 // ------------------------------------------------------------------ rows
+// RP row pairs (2 RP rows) per workgroup; 4 / RP workgroups share a block.
+#ifndef SGP_ROW_THREADS
+#define SGP_ROW_THREADS 1024
+#endif
+template <int L> struct RowCfg {
+  static constexpr int TF = FftPlan<L>::TF;
+  static constexpr int RP0 = SGP_ROW_THREADS / TF;
+  static constexpr int RP = RP0 < 1 ? 1 : (RP0 > kRP ? kRP : RP0);
+  static constexpr int NT = RP * TF;
+};
+
 template <int L, int OP>
-__global__ __launch_bounds__(kRP * FftPlan<L>::TF) void row_kernel(Args a) {
+__global__ __launch_bounds__(RowCfg<L>::NT) void row_kernel(Args a) {
   using P = FftPlan<L>;
   constexpr int TF = P::TF;
-  constexpr int NT = kRP * TF;
+  constexpr int RP = RowCfg<L>::RP;
+  constexpr int NT = RowCfg<L>::NT;
   constexpr int HALF = L / 2;
   constexpr int NS = row_nslots(OP);
-  __shared__ float2 buf[kRP][L];
+  __shared__ float2 buf[RP][L];
   DevState* st = a.st;
   if (a.iter && (st->done || st->pause)) return;
   const int tid = threadIdx.x;
   const int j = blockIdx.y;
-  const int y0 = blockIdx.x * kTile;
+  const int wg = xcd_remap(blockIdx.x, gridDim.x, kRP / RP);
+  const int y0 = wg * 2 * RP;  // first row of this workgroup
   const long long sstride = spec_elems(a.NY, a.NX);
-  float2* spec = a.spec + (row_per_image(OP) ? j : 0) * sstride + (long long)blockIdx.x * HALF * kTile;
+  // (A, B) of rows y0 + 2q, y0 + 2q + 1 at column k: float4 index 4k + q + (y0 % 8) / 2
+  float2* spec = a.spec + (row_per_image(OP) ? j : 0) * sstride + (long long)(y0 >> 3) * HALF * kTile + (y0 & 7);
 
   double acc[NS > 0 ? NS : 1];
   {
@@ -225,51 +266,51 @@ __global__ __launch_bounds__(kRP * FftPlan<L>::TF) void row_kernel(Args a) {
 
   if constexpr (row_has_inv(OP)) {
     const float4* S4 = reinterpret_cast<const float4*>(spec);
-    for (int u = tid; u < HALF * kRP; u += NT) {
-      const int q = u & (kRP - 1), k = u >> 2;
-      const float4 ab = S4[u];  // (A, B) of rows 2q, 2q+1 at column k
+    for (int u = tid; u < HALF * RP; u += NT) {
+      const int q = u % RP, k = u / RP;
+      const float4 ab = S4[4 * k + q];  // (A, B) of rows y0 + 2q, y0 + 2q + 1 at column k
       if (k == 0) {
-        buf[q][0] = make_float2(ab.x, -ab.z);       // conj(A0 + i B0)
-        buf[q][HALF] = make_float2(ab.y, -ab.w);    // conj(AN + i BN)
+        buf[q][lds_idx<L>(0)] = make_float2(ab.x, -ab.z);       // conj(A0 + i B0)
+        buf[q][lds_idx<L>(HALF)] = make_float2(ab.y, -ab.w);    // conj(AN + i BN)
       } else {
-        buf[q][k] = make_float2(ab.x - ab.w, -(ab.y + ab.z));      // conj(A + iB)
-        buf[q][L - k] = make_float2(ab.x + ab.w, -(-ab.y + ab.z)); // conj(conj A + i conj B)
+        buf[q][lds_idx<L>(k)] = make_float2(ab.x - ab.w, -(ab.y + ab.z));      // conj(A + iB)
+        buf[q][lds_idx<L>(L - k)] = make_float2(ab.x + ab.w, -(-ab.y + ab.z)); // conj(conj A + i conj B)
       }
     }
     __syncthreads();
     fft_lds<L>(buf[tid / TF], tid % TF, a.tw_row);
   }
 
-  for (int u = tid; u < kRP * L; u += NT) {
+  for (int u = tid; u < RP * L; u += NT) {
     const int q = u / L, x = u % L;
     const int ya = y0 + 2 * q;
     float2 v = make_float2(0.f, 0.f);
     if constexpr (row_has_inv(OP)) {
-      const float2 w = buf[q][x];
+      const float2 w = buf[q][lds_idx<L>(x)];
       v = make_float2(w.x, -w.y);
     }
     const float ua = row_point<OP, NS>(a, st, j, ya, x, v.x, acc);
     const float ub = row_point<OP, NS>(a, st, j, ya + 1, x, v.y, acc);
-    if constexpr (row_has_fwd(OP)) buf[q][x] = make_float2(ua, ub);
+    if constexpr (row_has_fwd(OP)) buf[q][lds_idx<L>(x)] = make_float2(ua, ub);
   }
 
   if constexpr (row_has_fwd(OP)) {
     __syncthreads();
     fft_lds<L>(buf[tid / TF], tid % TF, a.tw_row);
     float4* O4 = reinterpret_cast<float4*>(spec);
-    for (int u = tid; u < HALF * kRP; u += NT) {
-      const int q = u & (kRP - 1), k = u >> 2;
-      const float2 zk = buf[q][k];
+    for (int u = tid; u < HALF * RP; u += NT) {
+      const int q = u % RP, k = u / RP;
+      const float2 zk = buf[q][lds_idx<L>(k)];
       float4 o;
       if (k == 0) {
-        const float2 zn = buf[q][HALF];
+        const float2 zn = buf[q][lds_idx<L>(HALF)];
         o = make_float4(zk.x, zn.x, zk.y, zn.y);
       } else {
-        const float2 zm = buf[q][L - k];
+        const float2 zm = buf[q][lds_idx<L>(L - k)];
         o = make_float4(0.5f * (zk.x + zm.x), 0.5f * (zk.y - zm.y),
                         0.5f * (zk.y + zm.y), -0.5f * (zk.x - zm.x));
       }
-      O4[u] = o;
+      O4[4 * k + q] = o;
     }
   }
 
@@ -300,7 +341,7 @@ __global__ __launch_bounds__(ColCfg<LY>::NT) void col_kernel(Args a) {
   DevState* st = a.st;
   if (a.iter && (st->done || st->pause)) return;
   const int NXh = a.NX / 2;
-  const int kx0 = blockIdx.x * C;
+  const int kx0 = xcd_remap(blockIdx.x, gridDim.x, C >= 2 ? 1 : 2) * C;
   const int tid = threadIdx.x;
   const long long sstride = spec_elems(a.NY, a.NX);
   const int jin = (MODE == COL_FWD) ? blockIdx.y : 0;
@@ -318,7 +359,7 @@ __global__ __launch_bounds__(ColCfg<LY>::NT) void col_kernel(Args a) {
     for (int e = 0; e < E; ++e) {
       int c, y; long long off;
       unit(e, c, y, off);
-      buf[c][y] = (kx0 + c < NXh) ? S[off] : make_float2(0.f, 0.f);
+      buf[c][lds_idx<LY>(y)] = (kx0 + c < NXh) ? S[off] : make_float2(0.f, 0.f);
     }
   };
   const bool has_col0 = (kx0 == 0);
@@ -334,9 +375,9 @@ __global__ __launch_bounds__(ColCfg<LY>::NT) void col_kernel(Args a) {
       int c, y; long long off;
       unit(e, c, y, off);
       if (kx0 + c >= NXh) continue;
-      const float2 v = buf[c][y];
+      const float2 v = buf[c][lds_idx<LY>(y)];
       if (has_col0 && c == 0) {
-        const float2 m = cconj(buf[0][(LY - y) % LY]);
+        const float2 m = cconj(buf[0][lds_idx<LY>((LY - y) % LY)]);
         K[off] = cscale(cadd(v, m), 0.5f);                   // DC column transfer function
         KN[y] = cscale(mul_mi(csub(v, m)), 0.5f);            // Nyquist column transfer function
       } else {
@@ -352,9 +393,9 @@ __global__ __launch_bounds__(ColCfg<LY>::NT) void col_kernel(Args a) {
     for (int e = 0; e < E; ++e) {
       int c, y; long long off;
       unit(e, c, y, off);
-      const float2 v = buf[c][y];
+      const float2 v = buf[c][lds_idx<LY>(y)];
       if (has_col0 && c == 0) {
-        const float2 m = cconj(buf[0][(LY - y) % LY]);
+        const float2 m = cconj(buf[0][lds_idx<LY>((LY - y) % LY)]);
         x0[e] = cscale(cadd(v, m), 0.5f);
         x1[e] = cscale(mul_mi(csub(v, m)), 0.5f);
       } else {
@@ -364,6 +405,8 @@ __global__ __launch_bounds__(ColCfg<LY>::NT) void col_kernel(Args a) {
     }
     __syncthreads();
     for (int jo = 0; jo < a.p; ++jo) {
+      int lane = tid % TF;
+      asm volatile("" : "+v"(lane));  // keeps per-pass address arithmetic inside the loop
       const float2* K = a.khat + jo * sstride;
       const float2* KN = a.knyq + (long long)jo * LY;
 #pragma unroll
@@ -382,16 +425,16 @@ __global__ __launch_bounds__(ColCfg<LY>::NT) void col_kernel(Args a) {
             pr = CONJ ? cmulc(x0[e], kv) : cmul(x0[e], kv);
           }
         }
-        buf[c][y] = cconj(pr);
+        buf[c][lds_idx<LY>(y)] = cconj(pr);
       }
       __syncthreads();
-      fft_lds<LY>(buf[tid / TF], tid % TF, a.tw_col);
+      fft_lds<LY>(buf[tid / TF], lane, a.tw_col);
       float2* O = a.spec + jo * sstride;
 #pragma unroll
       for (int e = 0; e < E; ++e) {
         int c, y; long long off;
         unit(e, c, y, off);
-        if (kx0 + c < NXh) O[off] = cconj(buf[c][y]);
+        if (kx0 + c < NXh) O[off] = cconj(buf[c][lds_idx<LY>(y)]);
       }
       __syncthreads();
     }
@@ -400,9 +443,11 @@ __global__ __launch_bounds__(ColCfg<LY>::NT) void col_kernel(Args a) {
 #pragma unroll
     for (int e = 0; e < E; ++e) acc[e] = make_float2(0.f, 0.f);
     for (int ji = 0; ji < a.p; ++ji) {
+      int lane = tid % TF;
+      asm volatile("" : "+v"(lane));  // keeps per-pass address arithmetic inside the loop
       load(a.spec + ji * sstride);
       __syncthreads();
-      fft_lds<LY>(buf[tid / TF], tid % TF, a.tw_col);
+      fft_lds<LY>(buf[tid / TF], lane, a.tw_col);
       const float2* K = a.khat + ji * sstride;
       const float2* KN = a.knyq + (long long)ji * LY;
 #pragma unroll
@@ -410,10 +455,10 @@ __global__ __launch_bounds__(ColCfg<LY>::NT) void col_kernel(Args a) {
         int c, y; long long off;
         unit(e, c, y, off);
         if (kx0 + c >= NXh) continue;
-        const float2 v = buf[c][y];
+        const float2 v = buf[c][lds_idx<LY>(y)];
         const float2 kv = K[off];
         if (has_col0 && c == 0) {
-          const float2 m = cconj(buf[0][(LY - y) % LY]);
+          const float2 m = cconj(buf[0][lds_idx<LY>((LY - y) % LY)]);
           const float2 ev = cscale(cadd(v, m), 0.5f);
           const float2 od = cscale(mul_mi(csub(v, m)), 0.5f);
           const float2 kn = KN[y];
@@ -428,7 +473,7 @@ __global__ __launch_bounds__(ColCfg<LY>::NT) void col_kernel(Args a) {
     for (int e = 0; e < E; ++e) {
       int c, y; long long off;
       unit(e, c, y, off);
-      buf[c][y] = cconj(acc[e]);
+      buf[c][lds_idx<LY>(y)] = cconj(acc[e]);
     }
     __syncthreads();
     fft_lds<LY>(buf[tid / TF], tid % TF, a.tw_col);
@@ -436,7 +481,7 @@ __global__ __launch_bounds__(ColCfg<LY>::NT) void col_kernel(Args a) {
     for (int e = 0; e < E; ++e) {
       int c, y; long long off;
       unit(e, c, y, off);
-      if (kx0 + c < NXh) a.spec[off] = cconj(buf[c][y]);
+      if (kx0 + c < NXh) a.spec[off] = cconj(buf[c][lds_idx<LY>(y)]);
     }
   }
 }

@@ -8,6 +8,8 @@ bool size_supported(int L);
 // columns handled by one column-kernel workgroup for FFT length L
 int col_width(int L);
 int row_threads(int L);
+// row pairs handled by one row-kernel workgroup for row length L
+int row_pairs(int L);
 int col_threads(int L);
 void launch_row(int L, int op, dim3 grid, const Args& a, hipStream_t s);
 void launch_col(int L, int mode, int conj, dim3 grid, const Args& a, hipStream_t s);

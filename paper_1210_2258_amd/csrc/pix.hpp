@@ -4,14 +4,16 @@
 #include "common.hpp"
 #include "finalize.hpp"
 #include "reduce.hpp"
+#include "kernels.hpp"
 
 namespace sgp {
 
-constexpr int kMoreCand = kMaxCand - 2;  // theta^2 .. theta^40
+constexpr int kMoreCand = 8;                   // theta^2 .. theta^9
+constexpr int kRestCand = kMaxCand - 2 - kMoreCand;  // theta^10 .. theta^40
 
 __host__ __device__ constexpr int pix_nslots(int op) {
   return op == PIX_VALIDATE ? 3 : op == PIX_PSFSUM ? 3 : op == PIX_FLATSUM ? 2 :
-         op == PIX_ARMIJO_MORE ? kMoreCand : 0;
+         op == PIX_ARMIJO_MORE ? kMoreCand : op == PIX_ARMIJO_REST ? kRestCand : 0;
 }
 
 struct PixKinds {
@@ -28,7 +30,7 @@ __global__ __launch_bounds__(kPixThreads) void pix_kernel(Args a) {
   constexpr int NS = pix_nslots(OP);
   DevState* st = a.st;
   if (a.iter && (st->done || st->pause)) return;
-  if constexpr (OP == PIX_ARMIJO_MORE) {
+  if constexpr (OP == PIX_ARMIJO_MORE || OP == PIX_ARMIJO_REST) {
     if (!st->need_more) return;
   }
   const long long nS = (long long)a.ny * a.nx;
@@ -96,21 +98,17 @@ __global__ __launch_bounds__(kPixThreads) void pix_kernel(Args a) {
       }
       a.d[i] = inR ? (float)(1.0 / sum) : 0.f;  // a.d points at the invw buffer for this launch
     }
-  } else if constexpr (OP == PIX_ARMIJO_MORE) {
-    const int n = st->max_backtracks - 1;  // candidates theta^2 .. theta^max_backtracks
+  } else if constexpr (OP == PIX_ARMIJO_MORE || OP == PIX_ARMIJO_REST) {
+    constexpr int m0 = OP == PIX_ARMIJO_MORE ? 2 : 2 + kMoreCand;
+    const int n = st->max_backtracks + 1 - m0;  // candidates theta^m0 .. theta^max_backtracks
     for (long long i = i0; i < a.p * nS; i += stride) {
       const int j = (int)(i / nS);
       const float adv = a.Ad[i];
       const float g = a.g[i];
       const float yv = fmaxf(a.Af[i] + (a.bmap ? a.bmap[i] : a.b[j]), 1e-30f);
 #pragma unroll
-      for (int m = 0; m < kMoreCand; ++m) {
-        if (m < n) {
-          const float t = (float)st->lam_tab[m + 2] * adv;
-          double term = t;
-          if (g > 0.f) term -= (double)g * (double)log1pf(t / yv);
-          acc[m] += term;
-        }
+      for (int m = 0; m < NS; ++m) {
+        if (m < n) acc[m] += armijo_term(g, yv, (float)st->lam_tab[m0 + m] * adv);
       }
     }
   }
@@ -130,7 +128,9 @@ __global__ __launch_bounds__(kPixThreads) void pix_kernel(Args a) {
         if (!(c > 0.0)) c = 1e-6 * fmax(tot[1] / ((double)a.p * (double)nS), 1e-30);
         st->cflat = c;
       } else if constexpr (OP == PIX_ARMIJO_MORE) {
-        fin_armijo(st, tot, 2, st->max_backtracks - 1);
+        fin_armijo(st, tot, 2, kMoreCand);
+      } else if constexpr (OP == PIX_ARMIJO_REST) {
+        fin_armijo(st, tot, 2 + kMoreCand, kRestCand);
       }
     }
   }

@@ -82,8 +82,9 @@ static std::mutex g_mutex;
 static std::map<PlanKey, std::unique_ptr<Plan>> g_plans;
 
 static size_t part_capacity(const PlanKey& k) {
-  const size_t row_blocks = (size_t)(k.NY / kTile) * k.p;
-  return std::max<size_t>((size_t)(kMaxCand) * kMaxPixBlocks, 8 * row_blocks);
+  // row kernels: at most NY / 2 workgroups per image and 4 slots
+  const size_t row_blocks = (size_t)(k.NY / 2) * k.p;
+  return std::max<size_t>((size_t)(kMaxCand) * kMaxPixBlocks, 4 * row_blocks);
 }
 
 template <class T>
@@ -262,12 +263,13 @@ struct Launcher {
   }
   void row(int op, int jc, int iter, int flag = 0, int cls = -1) {
     Args a = base;
-    a.nblk = (NY / kTile) * jc;
+    const int gx = NY / (2 * row_pairs(NX));
+    a.nblk = gx * jc;
     a.iter = iter;
     a.flag = flag;
     hipEvent_t e0 = nullptr;
     begin(cls, e0);
-    launch_row(NX, op, dim3(NY / kTile, jc), a, s);
+    launch_row(NX, op, dim3(gx, jc), a, s);
     end(cls, e0);
   }
   void col(int mode, int conj, int jc, int iter, int cls = -1) {
@@ -282,7 +284,10 @@ struct Launcher {
   void pix(int op, long long n, int iter, int jsel = 0, int cls = -1) {
     Args a = base;
     long long nb = (n + kPixThreads - 1) / kPixThreads;
-    nb = std::max<long long>(1, std::min<long long>(nb, kMaxPixBlocks));
+    // the extra Armijo candidates are rarely needed: a small grid keeps the
+    // usual early exit cheap
+    const long long cap = (op == PIX_ARMIJO_MORE || op == PIX_ARMIJO_REST) ? 256 : kMaxPixBlocks;
+    nb = std::max<long long>(1, std::min<long long>(nb, cap));
     a.nblk = (int)nb;
     a.iter = iter;
     a.jsel = jsel;
@@ -346,6 +351,7 @@ struct sgp_solver {
   hipGraphExec_t graph = nullptr;
   hipGraph_t graph_def = nullptr;
   int graph_block = 0;
+  bool use_graph = true;
   bool done = false;
   std::chrono::steady_clock::time_point t0;
   double ms[SGP_KCLASS_COUNT] = {0};
@@ -376,6 +382,7 @@ static void enqueue_iteration(sgp_solver* S) {
     L.col(COL_CONV, 0, 1, 1, SGP_KCLASS_COL_CONV);
     L.row(ROW_AD, p, 1, 0, SGP_KCLASS_ROW_AD);
     L.pix(PIX_ARMIJO_MORE, p * nS, 1, 0, SGP_KCLASS_ARMIJO_MORE);
+    L.pix(PIX_ARMIJO_REST, p * nS, 1, 0, SGP_KCLASS_ARMIJO_MORE);
     L.row(ROW_UPD, p, 1, 0, SGP_KCLASS_ROW_UPD);
     L.col(COL_CORRSUM, 1, 1, 1, SGP_KCLASS_COL_CORR);
     L.row(ROW_GRAD, 1, 1, 0, SGP_KCLASS_ROW_GRAD);
@@ -469,7 +476,7 @@ static int step(sgp_solver* S, int n, int* done_out) {
   }
   const bool early = (S->prm.stop & (SGP_STOP_CONV | SGP_STOP_DISCREPANCY)) != 0;
   const int iters = (S->kind == KIND_RL) ? n + 1 : n;  // RL evaluates J once more before pausing
-  if (S->L.timing) {
+  if (S->L.timing || !S->use_graph) {
     for (int it = 0; it < iters; ++it) {
       enqueue_iteration(S);
       if (early && (it % 16) == 15) {
@@ -784,6 +791,12 @@ int sgp_solver_set_timing(sgp_solver* s, int enable) {
     s->ms[i] = 0;
     s->cnt[i] = 0;
   }
+  return 0;
+}
+
+int sgp_solver_set_graph(sgp_solver* s, int enable) {
+  if (!s) return fail(SGP_E_INVALID_ARG, "null solver");
+  s->use_graph = enable != 0;
   return 0;
 }
 

@@ -102,17 +102,21 @@ def test_rl_fixed_iterations(torch_dev, case):
     assert abs(rep["kl"] - io["kl"]) <= KL_TOL * io["kl"], (rep["kl"], io["kl"])
 
 
-# SGP trajectories from FP32 fields drift from the FP64 oracle's at a rate
-# set by the BB steplengths (about a factor 10 every ~12 iterations from a
-# ~1e-7 start on these data), so fixed-count parity is checked at 20
-# iterations, where both bars hold with margin.
-SGP_K = 20
+# SGP iterates carried in FP32 drift from the FP64 oracle's.  Two sources:
+# FP32 storage of f and d (rounding them inside the oracle itself moves the
+# KL by ~2e-6 after 20 iterations on the 64x80 case, tests/test_oracle_fp32_floor.py)
+# and the ~1e-7 relative error of FP32 FFTs, which on the 64x80 case already
+# puts ~1e-6 into the BB inner products at k = 3 and grows the KL gap past
+# 1e-6 by k = 8.  Fixed-count parity is checked where both bars hold: 6
+# iterations on the 64x80-class cases, 20 on the 256x256 field, 10 at full
+# size (tests/test_gpu_fullsize.py).
+SGP_K = {"single_64x80": 6, "single_c0_256": 20, "multi_3x64": 6, "boundary_64x48_in_80x64": 6}
 
 
 @pytest.mark.parametrize("case", list(CASES))
 def test_sgp_fixed_iterations(torch_dev, case):
     w = CASES[case]()
-    n = SGP_K
+    n = SGP_K[case]
     fn = "sgp_deconv" if (w.domain is None and w.p == 1) else (
         "sgp_multi_deconv" if w.domain is None else "sgp_boundary_deconv")
     f, rep = _run_gpu(torch_dev, fn, w, max_iter=n)
@@ -127,14 +131,14 @@ def test_sgp_fixed_iterations(torch_dev, case):
 
 @pytest.mark.parametrize("case", ["single_64x80", "multi_3x64"])
 def test_sgp_alternation_branch(torch_dev, case):
-    """n_bb2_only = 4 makes the alternation of Eq. (alphadef) act within the
+    """n_bb2_only = 2 makes the alternation of Eq. (alphadef) act within the
     parity window."""
     w = CASES[case]()
-    n = 16
+    n = 7
     fn = "sgp_deconv" if w.p == 1 else "sgp_multi_deconv"
-    f, rep = _run_gpu(torch_dev, fn, w, max_iter=n, n_bb2_only=4)
+    f, rep = _run_gpu(torch_dev, fn, w, max_iter=n, n_bb2_only=2)
     P = _oracle(w)
-    fo, io = P.sgp(P.start("flat"), O.Params(max_iter=n, n_bb2_only=4))
+    fo, io = P.sgp(P.start("flat"), O.Params(max_iter=n, n_bb2_only=2))
     alts = {L["alt"] for L in io["log"][:n - 1]}
     assert alts & {1, 2}
     _check_log(rep["trace"], io["log"], n)
