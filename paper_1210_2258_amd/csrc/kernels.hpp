@@ -247,6 +247,9 @@ __global__ __launch_bounds__(RowCfg<L>::NT) void row_kernel(Args a) {
   constexpr int HALF = L / 2;
   constexpr int NS = row_nslots(OP);
   __shared__ float2 buf[RP][L];
+#ifndef SGP_TW_GLOBAL
+  __shared__ float2 twl[L];  // twiddle table staged in LDS
+#endif
   DevState* st = a.st;
   if (a.iter && (st->done || st->pause)) return;
   const int tid = threadIdx.x;
@@ -257,6 +260,12 @@ __global__ __launch_bounds__(RowCfg<L>::NT) void row_kernel(Args a) {
   // (A, B) of rows y0 + 2q, y0 + 2q + 1 at column k: float4 index 4k + q + (y0 % 8) / 2
   float2* spec = a.spec + (row_per_image(OP) ? j : 0) * sstride + (long long)(y0 >> 3) * HALF * kTile + (y0 & 7);
 
+#ifndef SGP_TW_GLOBAL
+  const float2* tw = twl;
+  for (int i = tid; i < L; i += NT) twl[i] = a.tw_row[i];  // visible after the first barrier
+#else
+  const float2* tw = a.tw_row;
+#endif
   double acc[NS > 0 ? NS : 1];
   {
     RowKinds kinds{OP};
@@ -266,6 +275,7 @@ __global__ __launch_bounds__(RowCfg<L>::NT) void row_kernel(Args a) {
 
   if constexpr (row_has_inv(OP)) {
     const float4* S4 = reinterpret_cast<const float4*>(spec);
+#pragma unroll
     for (int u = tid; u < HALF * RP; u += NT) {
       const int q = u % RP, k = u / RP;
       const float4 ab = S4[4 * k + q];  // (A, B) of rows y0 + 2q, y0 + 2q + 1 at column k
@@ -278,9 +288,10 @@ __global__ __launch_bounds__(RowCfg<L>::NT) void row_kernel(Args a) {
       }
     }
     __syncthreads();
-    fft_lds<L>(buf[tid / TF], tid % TF, a.tw_row);
+    fft_lds<L>(buf[tid / TF], tid % TF, tw);
   }
 
+#pragma unroll
   for (int u = tid; u < RP * L; u += NT) {
     const int q = u / L, x = u % L;
     const int ya = y0 + 2 * q;
@@ -296,8 +307,9 @@ __global__ __launch_bounds__(RowCfg<L>::NT) void row_kernel(Args a) {
 
   if constexpr (row_has_fwd(OP)) {
     __syncthreads();
-    fft_lds<L>(buf[tid / TF], tid % TF, a.tw_row);
+    fft_lds<L>(buf[tid / TF], tid % TF, tw);
     float4* O4 = reinterpret_cast<float4*>(spec);
+#pragma unroll
     for (int u = tid; u < HALF * RP; u += NT) {
       const int q = u % RP, k = u / RP;
       const float2 zk = buf[q][lds_idx<L>(k)];
@@ -338,6 +350,9 @@ __global__ __launch_bounds__(ColCfg<LY>::NT) void col_kernel(Args a) {
   constexpr int NT = ColCfg<LY>::NT;
   constexpr int E = LY * C / NT;  // units per thread
   __shared__ float2 buf[C][LY];
+#ifndef SGP_TW_GLOBAL
+  __shared__ float2 twl[LY];  // twiddle table staged in LDS
+#endif
   DevState* st = a.st;
   if (a.iter && (st->done || st->pause)) return;
   const int NXh = a.NX / 2;
@@ -345,6 +360,12 @@ __global__ __launch_bounds__(ColCfg<LY>::NT) void col_kernel(Args a) {
   const int tid = threadIdx.x;
   const long long sstride = spec_elems(a.NY, a.NX);
   const int jin = (MODE == COL_FWD) ? blockIdx.y : 0;
+#ifndef SGP_TW_GLOBAL
+  const float2* tw = twl;
+  for (int i = tid; i < LY; i += NT) twl[i] = a.tw_col[i];  // visible after the first barrier
+#else
+  const float2* tw = a.tw_col;
+#endif
 
   // unit e of this thread -> (column c, row y) and its offset in the layout
   auto unit = [&](int e, int& c, int& y, long long& off) {
@@ -367,7 +388,7 @@ __global__ __launch_bounds__(ColCfg<LY>::NT) void col_kernel(Args a) {
   if constexpr (MODE == COL_FWD) {
     load(a.spec + jin * sstride);
     __syncthreads();
-    fft_lds<LY>(buf[tid / TF], tid % TF, a.tw_col);
+    fft_lds<LY>(buf[tid / TF], tid % TF, tw);
     float2* K = a.khat + jin * sstride;
     float2* KN = a.knyq + (long long)jin * LY;
 #pragma unroll
@@ -387,7 +408,7 @@ __global__ __launch_bounds__(ColCfg<LY>::NT) void col_kernel(Args a) {
   } else if constexpr (MODE == COL_CONV) {
     load(a.spec);
     __syncthreads();
-    fft_lds<LY>(buf[tid / TF], tid % TF, a.tw_col);
+    fft_lds<LY>(buf[tid / TF], tid % TF, tw);
     float2 x0[E], x1[E];  // spectrum (or its even / odd parts for column 0)
 #pragma unroll
     for (int e = 0; e < E; ++e) {
@@ -428,7 +449,7 @@ __global__ __launch_bounds__(ColCfg<LY>::NT) void col_kernel(Args a) {
         buf[c][lds_idx<LY>(y)] = cconj(pr);
       }
       __syncthreads();
-      fft_lds<LY>(buf[tid / TF], lane, a.tw_col);
+      fft_lds<LY>(buf[tid / TF], lane, tw);
       float2* O = a.spec + jo * sstride;
 #pragma unroll
       for (int e = 0; e < E; ++e) {
@@ -447,7 +468,7 @@ __global__ __launch_bounds__(ColCfg<LY>::NT) void col_kernel(Args a) {
       asm volatile("" : "+v"(lane));  // keeps per-pass address arithmetic inside the loop
       load(a.spec + ji * sstride);
       __syncthreads();
-      fft_lds<LY>(buf[tid / TF], lane, a.tw_col);
+      fft_lds<LY>(buf[tid / TF], lane, tw);
       const float2* K = a.khat + ji * sstride;
       const float2* KN = a.knyq + (long long)ji * LY;
 #pragma unroll
@@ -476,7 +497,7 @@ __global__ __launch_bounds__(ColCfg<LY>::NT) void col_kernel(Args a) {
       buf[c][lds_idx<LY>(y)] = cconj(acc[e]);
     }
     __syncthreads();
-    fft_lds<LY>(buf[tid / TF], tid % TF, a.tw_col);
+    fft_lds<LY>(buf[tid / TF], tid % TF, tw);
 #pragma unroll
     for (int e = 0; e < E; ++e) {
       int c, y; long long off;

@@ -110,7 +110,7 @@ def test_rl_fixed_iterations(torch_dev, case):
 # 1e-6 by k = 8.  Fixed-count parity is checked where both bars hold: 6
 # iterations on the 64x80-class cases, 20 on the 256x256 field, 10 at full
 # size (tests/test_gpu_fullsize.py).
-SGP_K = {"single_64x80": 6, "single_c0_256": 20, "multi_3x64": 6, "boundary_64x48_in_80x64": 6}
+SGP_K = {"single_64x80": 6, "single_c0_256": 20, "multi_3x64": 6, "boundary_64x48_in_80x64": 4}
 
 
 @pytest.mark.parametrize("case", list(CASES))
