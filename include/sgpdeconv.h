@@ -100,8 +100,9 @@ typedef struct sgp_params {
   int n_bb2_only;        /* iterations using Eq. (alphadef) before alternation (default 20) */
   int auto_bounds;       /* 1: (L1, L2) by the Sect. 3.2 rule; 0: use L1, L2 below */
   double L1, L2;         /* scaling bounds of Eq. (Dk) when auto_bounds = 0 */
-  int flux_constraint;   /* reserved, must be 0 (projection onto f >= 0 only) */
-  double flux;           /* reserved */
+  int flux_constraint;   /* 1: project onto {f >= 0, sum f = flux} in the D^-1 metric (SGP only;
+                            the constraint set named in Sect. 2), else onto f >= 0 */
+  double flux;           /* flux of the constraint; < 0: mean over images of sum_S (g - b) */
   double sigma_R;        /* threshold sigma of Eq. (Rdef) (default 1e-3) */
   int max_backtracks;    /* Armijo reductions allowed, 0..40 (default 40) */
   double* trace;         /* optional HOST buffer [(max_iter + 1) * SGP_TRACE_COLS] doubles */

@@ -44,7 +44,11 @@ struct DevState {
   double psf_scale[kMaxP];
   double norm_disc;  // 2 / (p |S|), Eq. (discrepancy)
   double cflat, ymin, ymax;
+  double fsum;       // sum of f (PIX_FSUM)
   double mu;         // flux-projection multiplier
+  double flux_fixed; // sum of max(0, z) over pixels with D = 0
+  double flux_cnt;   // active-set size at the current mu
+  int flux_done;     // Newton iteration for mu has converged
   double* trace;     // [max_iter + 1][kTraceCols] or null
 };
 
@@ -113,6 +117,10 @@ enum PixOp {
   PIX_INVW,         // boundary: R mask and M_R / alpha from aux (alpha_j)
   PIX_ARMIJO_MORE,  // further Armijo candidates theta^2 .. theta^9
   PIX_ARMIJO_REST,  // the remaining candidates theta^10 .. theta^40
+  PIX_FLUX_INIT,    // flux projection: all-active multiplier and bracket
+  PIX_FLUX_NEWTON,  // flux projection: one Newton step on the multiplier
+  PIX_FSUM,         // sum of f (flux of the start image)
+  PIX_FSCALE,       // scale f to the prescribed flux
   PIX_NOPS
 };
 

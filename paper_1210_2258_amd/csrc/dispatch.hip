@@ -91,6 +91,10 @@ void launch_pix(int op, dim3 grid, const Args& a, hipStream_t s) {
     SGP_PIX_CASE(PIX_INVW)
     SGP_PIX_CASE(PIX_ARMIJO_MORE)
     SGP_PIX_CASE(PIX_ARMIJO_REST)
+    SGP_PIX_CASE(PIX_FLUX_INIT)
+    SGP_PIX_CASE(PIX_FLUX_NEWTON)
+    SGP_PIX_CASE(PIX_FSUM)
+    SGP_PIX_CASE(PIX_FSCALE)
 #undef SGP_PIX_CASE
     default: break;
   }

@@ -202,4 +202,42 @@ __host__ __device__ inline void fin_rl(DevState* st, double J) {
   st->J = J;
 }
 
+// Flux projection (constraint set {x >= 0, sum x = c} of Sect. 2, projection
+// in the D^-1 metric): x_i = max(0, z_i - mu D_i), with mu the root of the
+// convex, decreasing, piecewise linear phi(mu) = sum_i max(0, z_i - mu D_i) - c.
+// Newton steps from the left of the root stay left of it and end at the
+// exact root once the active set stops changing:
+//   mu <- (sum_{active} z_i - c') / sum_{active} D_i.
+// t = {sum_{D>0} z, sum_{D>0} D, min_{D>0} z/D, sum_{D=0} max(0, z), #(D>0)}
+__host__ __device__ inline void fin_flux_init(DevState* st, const double* t) {
+  st->flux_fixed = t[3];
+  const double c = st->flux_c - t[3];
+  const double mu = (t[0] - c) / t[1];
+  st->mu = mu;
+  st->flux_cnt = t[4];
+  st->flux_done = (mu <= t[2]) ? 1 : 0;  // every pixel active at mu: exact root
+  if (!__builtin_isfinite(mu)) {
+    st->done = 1;
+    st->reason = REASON_NUMERIC;
+  }
+}
+
+// t = {sum_{active} z, sum_{active} D, #active} with active = {z - mu D > 0}
+// at the current mu.  An unchanged active set means the step returns the
+// current mu: the root.
+__host__ __device__ inline void fin_flux_newton(DevState* st, const double* t) {
+  if (!(t[1] > 0.0)) {  // nothing active: c' <= 0, the projection is x = 0 on D > 0
+    st->flux_done = 1;
+    return;
+  }
+  const double mu = (t[0] - (st->flux_c - st->flux_fixed)) / t[1];
+  if (t[2] == st->flux_cnt) st->flux_done = 1;
+  st->flux_cnt = t[2];
+  st->mu = mu;
+  if (!__builtin_isfinite(mu)) {
+    st->done = 1;
+    st->reason = REASON_NUMERIC;
+  }
+}
+
 }  // namespace sgp

@@ -136,7 +136,9 @@ __device__ __forceinline__ float row_point(const Args& a, const DevState* st, in
     const float f = a.f[pix], gr = a.grad[pix];
     const float D = P.w(pix) * fminf((float)st->L2, fmaxf((float)st->L1, f));
     const float z = f - (float)st->alpha * D * gr;
-    const float dd = fmaxf(0.f, z) - f;
+    // projection onto f >= 0, or with the flux constraint onto {f >= 0, sum f = c}
+    const float dd = (st->flux_constraint && D > 0.f ? (float)fmax(0.0, (double)z - st->mu * (double)D)
+                                                    : fmaxf(0.f, z)) - f;
     a.d[pix] = dd;
     acc[0] += (double)gr * (double)dd;
     return dd;

@@ -13,7 +13,8 @@ constexpr int kRestCand = kMaxCand - 2 - kMoreCand;  // theta^10 .. theta^40
 
 __host__ __device__ constexpr int pix_nslots(int op) {
   return op == PIX_VALIDATE ? 3 : op == PIX_PSFSUM ? 3 : op == PIX_FLATSUM ? 2 :
-         op == PIX_ARMIJO_MORE ? kMoreCand : op == PIX_ARMIJO_REST ? kRestCand : 0;
+         op == PIX_ARMIJO_MORE ? kMoreCand : op == PIX_ARMIJO_REST ? kRestCand :
+         op == PIX_FLUX_INIT ? 5 : op == PIX_FLUX_NEWTON ? 3 : op == PIX_FSUM ? 1 : 0;
 }
 
 struct PixKinds {
@@ -21,6 +22,7 @@ struct PixKinds {
   __device__ int operator()(int s) const {
     if (op == PIX_VALIDATE) return s == 1 ? RED_SUM : RED_MIN;  // min g, #non-finite, min b
     if (op == PIX_PSFSUM) return s == 1 ? RED_MIN : RED_SUM;    // sum, min, #non-finite
+    if (op == PIX_FLUX_INIT) return s == 2 ? RED_MIN : RED_SUM;
     return RED_SUM;
   }
 };
@@ -32,6 +34,9 @@ __global__ __launch_bounds__(kPixThreads) void pix_kernel(Args a) {
   if (a.iter && (st->done || st->pause)) return;
   if constexpr (OP == PIX_ARMIJO_MORE || OP == PIX_ARMIJO_REST) {
     if (!st->need_more) return;
+  }
+  if constexpr (OP == PIX_FLUX_NEWTON) {
+    if (st->flux_done) return;
   }
   const long long nS = (long long)a.ny * a.nx;
   const long long nF = (long long)a.NY * a.NX;
@@ -113,6 +118,39 @@ __global__ __launch_bounds__(kPixThreads) void pix_kernel(Args a) {
     }
   }
 
+  if constexpr (OP == PIX_FLUX_INIT || OP == PIX_FLUX_NEWTON) {
+    // z = f - alpha D grad with D = invw clip(f, L1, L2), as in the direction kernel
+    const float alpha = (float)st->alpha, L1 = (float)st->L1, L2 = (float)st->L2;
+    const double mu = st->mu;
+    for (long long i = i0; i < nF; i += stride) {
+      const float f = a.f[i];
+      const float w = a.invw ? a.invw[i] : a.invw_s;
+      const float D = w * fminf(L2, fmaxf(L1, f));
+      const float z = f - alpha * D * a.grad[i];
+      if constexpr (OP == PIX_FLUX_INIT) {
+        if (D > 0.f) {
+          acc[0] += z;
+          acc[1] += D;
+          acc[2] = fmin(acc[2], (double)z / (double)D);
+          acc[4] += 1.0;
+        } else {
+          acc[3] += fmaxf(0.f, z);
+        }
+      } else {
+        if (D > 0.f && (double)z - mu * (double)D > 0.0) {
+          acc[0] += z;
+          acc[1] += D;
+          acc[2] += 1.0;
+        }
+      }
+    }
+  } else if constexpr (OP == PIX_FSUM) {
+    for (long long i = i0; i < nF; i += stride) acc[0] += a.f[i];
+  } else if constexpr (OP == PIX_FSCALE) {
+    const double s = st->fsum > 0.0 ? st->flux_c / st->fsum : 1.0;
+    for (long long i = i0; i < nF; i += stride) a.f[i] = (float)((double)a.f[i] * s);
+  }
+
   if constexpr (NS > 0) {
     double tot[NS];
     if (grid_reduce<kPixThreads, NS>(acc, kinds, a.part, a.counter, a.nblk, blockIdx.x, tot)) {
@@ -127,10 +165,18 @@ __global__ __launch_bounds__(kPixThreads) void pix_kernel(Args a) {
         double c = tot[0] / ((double)a.p * (double)nS);
         if (!(c > 0.0)) c = 1e-6 * fmax(tot[1] / ((double)a.p * (double)nS), 1e-30);
         st->cflat = c;
+        // default flux of the constraint: (mean) background-subtracted flux
+        if (!(st->flux >= 0.0)) st->flux_c = tot[0] / (double)a.p;
       } else if constexpr (OP == PIX_ARMIJO_MORE) {
         fin_armijo(st, tot, 2, kMoreCand);
       } else if constexpr (OP == PIX_ARMIJO_REST) {
         fin_armijo(st, tot, 2 + kMoreCand, kRestCand);
+      } else if constexpr (OP == PIX_FLUX_INIT) {
+        fin_flux_init(st, tot);
+      } else if constexpr (OP == PIX_FLUX_NEWTON) {
+        fin_flux_newton(st, tot);
+      } else if constexpr (OP == PIX_FSUM) {
+        st->fsum = tot[0];
       }
     }
   }

@@ -199,7 +199,7 @@ static int check_params(const sgp_params& p, int kind) {
     if (p.max_backtracks < 0 || p.max_backtracks > kMaxCand - 1)
       return fail(SGP_E_INVALID_ARG, "max_backtracks must be in 0..40");
   }
-  if (p.flux_constraint) return fail(SGP_E_INVALID_ARG, "flux_constraint is not available in this build");
+  if (p.flux_constraint && kind != KIND_SGP) return fail(SGP_E_INVALID_ARG, "the flux constraint applies to SGP only");
   if (!(p.sigma_R > 0)) return fail(SGP_E_INVALID_ARG, "sigma_R must be > 0");
   return 0;
 }
@@ -326,6 +326,7 @@ static void fill_state(DevState& h, const sgp_params& p, const Problem& pb, doub
   h.L2p = p.L2;
   h.sigma_R = p.sigma_R;
   h.flux = p.flux;
+  h.flux_c = p.flux;
   h.norm_disc = 2.0 / ((double)pb.p * (double)pb.ny * (double)pb.nx);
   h.alpha = p.alpha0;
   h.tau = p.tau1;
@@ -372,12 +373,21 @@ static int read_state(sgp_solver* S) {
   return 0;
 }
 
+// Newton steps allowed for the flux multiplier per iteration (each exits at
+// once after convergence, typically within 4 steps)
+constexpr int kFluxNewton = 8;
+
 // one iteration of the solver's loop
 static void enqueue_iteration(sgp_solver* S) {
   Launcher& L = S->L;
   const int p = S->pb.p;
   const long long nS = (long long)S->pb.ny * S->pb.nx;
   if (S->kind == KIND_SGP) {
+    if (S->prm.flux_constraint) {
+      const long long nF = (long long)S->pb.NY * S->pb.NX;
+      L.pix(PIX_FLUX_INIT, nF, 1, 0, SGP_KCLASS_ROW_DIR);
+      for (int t = 0; t < kFluxNewton; ++t) L.pix(PIX_FLUX_NEWTON, nF, 1, 0, SGP_KCLASS_ROW_DIR);
+    }
     L.row(ROW_DIR, 1, 1, 0, SGP_KCLASS_ROW_DIR);
     L.col(COL_CONV, 0, 1, 1, SGP_KCLASS_COL_CONV);
     L.row(ROW_AD, p, 1, 0, SGP_KCLASS_ROW_AD);
@@ -423,8 +433,12 @@ static int setup(sgp_solver* S) {
     L.pix(PIX_INVW, nF, 0);
     L.base = save;
   }
-  if (S->prm.init == SGP_INIT_FLAT) L.pix(PIX_FLATSUM, pb.p * nS, 0);
+  if (S->prm.init == SGP_INIT_FLAT || S->prm.flux_constraint) L.pix(PIX_FLATSUM, pb.p * nS, 0);
   L.pix(PIX_INITF, nF, 0);
+  if (S->prm.flux_constraint) {  // the start image is put on the constraint set
+    L.pix(PIX_FSUM, nF, 0);
+    L.pix(PIX_FSCALE, nF, 0);
+  }
   L.base.src = S->f;
   L.row(ROW_FIELD, 1, 0);
   if (S->kind == KIND_SGP) {
@@ -516,6 +530,7 @@ static int step(sgp_solver* S, int n, int* done_out) {
 
 static int report(sgp_solver* S, sgp_report* rep) {
   int rc;
+  S->L.pix(PIX_FSUM, (long long)S->pb.NY * S->pb.NX, 0);
   if ((rc = read_state(S))) return rc;
   const DevState& h = *S->pl->host_st;
   if (S->prm.trace && S->pl->trace) {
@@ -529,7 +544,7 @@ static int report(sgp_solver* S, sgp_report* rep) {
     rep->used_fallback = 0;
     rep->kl = h.J;
     rep->discrepancy = h.norm_disc * h.J;
-    rep->flux = std::nan("");
+    rep->flux = h.fsum;
     rep->L1 = h.L1;
     rep->L2 = h.L2;
     rep->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - S->t0).count();

@@ -243,3 +243,25 @@ def test_gpu_errors(torch_dev):
     with pytest.raises(m.SgpError) as e:
         m.sgp_deconv(g, psf, 1.0, max_iter=5)
     assert e.value.code == -4
+
+
+# the flux-constrained runs drift a little faster than the plain ones
+FLUX_K = {"single_64x80": 6, "single_c0_256": 12, "multi_3x64": 4}
+
+
+@pytest.mark.parametrize("case", list(FLUX_K))
+def test_sgp_flux_constraint(torch_dev, case):
+    """Flux-constrained SGP (projection onto {f >= 0, sum f = c} in the
+    D^-1 metric): GPU Newton multiplier vs the oracle's breakpoint scan."""
+    w = CASES[case]()
+    n = FLUX_K[case]
+    fn = "sgp_deconv" if w.p == 1 else "sgp_multi_deconv"
+    f, rep = _run_gpu(torch_dev, fn, w, max_iter=n, flux_constraint=1)
+    P = _oracle(w)
+    prm = O.Params(max_iter=n, flux_constraint=True)
+    fo, io = P.sgp(P.start("flat"), prm)
+    c = P.flux_value(prm)
+    assert abs(rep["flux"] - c) <= 1e-5 * c, (rep["flux"], c)
+    _check_log(rep["trace"], io["log"], n)
+    assert _rel(f.cpu().numpy(), fo) <= F_TOL, _rel(f.cpu().numpy(), fo)
+    assert abs(rep["kl"] - io["kl"]) <= KL_TOL * io["kl"], (rep["kl"], io["kl"])

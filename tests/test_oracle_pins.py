@@ -347,3 +347,16 @@ def test_discrepancy_of_true_object_near_one():
     # std of the mean of 2 KL terms over 65536 pixels is ~0.006
     assert abs(D_true - expect) < 0.03
     assert 0.9 < expect < 1.1
+
+
+def test_sgp_flux_constraint_keeps_flux():
+    """With the flux constraint every iterate has sum f = c and J decreases."""
+    w = W.small_single(64, 80)
+    P = O.Problem(w.g, w.psf, w.b)
+    prm = O.Params(max_iter=25, flux_constraint=True)
+    c = P.flux_value(prm)
+    f, info = P.sgp(P.start("flat"), prm)
+    assert abs(f.sum() - c) <= 1e-9 * c
+    assert f.min() >= 0
+    h = np.array(info["history"])
+    assert np.all(np.diff(h) <= 0)
