@@ -75,6 +75,8 @@ extern "C" {
 #define SGP_INIT_ZERO 1   /* not valid for RL, whose iterates stay at 0 */
 #define SGP_INIT_DATA 2   /* g (g_1 for several images), embedded on R */
 #define SGP_INIT_USER 3   /* f0 below (device pointer, [NY][NX]); negative values clipped */
+#define SGP_INIT_WARM 4   /* f0 (e.g. a learned warm start), replaced by the flat start when its
+                             KL is larger; sgp_report.used_fallback tells which was used */
 
 /* per-iteration trace columns (one row of SGP_TRACE_COLS doubles per iteration) */
 #define SGP_TRACE_COLS 20
@@ -112,7 +114,7 @@ typedef struct sgp_report {
   int iters;             /* iterations performed */
   int stop_reason;       /* SGP_REASON_* */
   int backtracks;        /* total Armijo reductions */
-  int used_fallback;     /* reserved (warm start) */
+  int used_fallback;     /* SGP_INIT_WARM: 1 if the flat start replaced f0 */
   double kl;             /* J_0 at the returned f */
   double discrepancy;    /* 2 J_0 / (p ny nx) */
   double flux;           /* sum of f */
@@ -227,6 +229,17 @@ int sgp_solver_set_timing(sgp_solver* s, int enable);
 int sgp_solver_set_graph(sgp_solver* s, int enable);
 int sgp_solver_timing(sgp_solver* s, double* ms, long long* counts, int ncls);
 int sgp_solver_destroy(sgp_solver* s);
+
+/* Many single-image periodic problems in one run (images of uneven sizes).
+ * probs[i]: p = 1, boundary = 0, b_map = NULL (constant background
+ * b_const[0]); f[i]: device [ny][nx] iterate of problem i; f0: NULL or
+ * per-problem starts for SGP_INIT_USER / SGP_INIT_WARM.  Problems of one
+ * shape form one batched solver (every launch covers all of them); all
+ * shapes advance together in one HIP graph of parallel branches, replayed
+ * until every problem has met its own stop rule.  reps: n reports (optional).
+ * Returns the most severe per-problem code.  kind: SGP_KIND_SGP or _RL. */
+int sgp_batch_deconv(int kind, const sgp_problem* probs, int n, float* const* f, const float* const* f0,
+                     const sgp_params* prm, sgp_report* reps, void* hip_stream);
 
 /* The steplength rule of Sect. 2.1 exactly as the device runs it, callable on
  * the host for validation.  k: index of the iteration just completed;

@@ -21,7 +21,7 @@ TRACE_FIELDS = ["k", "alpha", "gd", "backtracks", "lam", "J", "a", "c1", "c2", "
                 "a1", "a2", "br1", "br2", "alt", "tau", "alpha_next", "flux_mu"]
 
 STOP_FIXED, STOP_CONV, STOP_DISCREPANCY = 1, 2, 4
-INIT_FLAT, INIT_ZERO, INIT_DATA, INIT_USER = 0, 1, 2, 3
+INIT_FLAT, INIT_ZERO, INIT_DATA, INIT_USER, INIT_WARM = 0, 1, 2, 3, 4
 REASONS = {0: "maxiter", 1: "convergence", 2: "discrepancy", 4: "stationary", 5: "armijo", 6: "numeric"}
 
 
@@ -70,7 +70,7 @@ EXPORTS = [
     "sgp_params_init", "rl_deconv", "sgp_deconv", "sgp_multi_deconv", "rl_multi_deconv",
     "sgp_boundary_deconv", "rl_boundary_deconv", "sgp_apply_operator", "sgp_release_cache",
     "sgp_strerror", "sgp_last_error", "sgp_solver_create", "sgp_solver_step", "sgp_solver_report",
-    "sgp_solver_set_timing", "sgp_solver_set_graph", "sgp_solver_timing", "sgp_solver_destroy", "sgp_steplength_rule",
+    "sgp_solver_set_timing", "sgp_solver_set_graph", "sgp_solver_timing", "sgp_solver_destroy", "sgp_steplength_rule", "sgp_batch_deconv",
 ]
 
 _lib = None
@@ -101,6 +101,8 @@ def load():
     lib.sgp_solver_set_graph.argtypes = [vp, i]
     lib.sgp_solver_timing.argtypes = [vp, ctypes.POINTER(d), ctypes.POINTER(ctypes.c_longlong), i]
     lib.sgp_solver_destroy.argtypes = [vp]
+    lib.sgp_batch_deconv.argtypes = [i, ctypes.POINTER(_Problem), i, ctypes.POINTER(vp), ctypes.POINTER(vp), P,
+                                     ctypes.POINTER(_Report), vp]
     lib.sgp_steplength_rule.argtypes = [P, i, d, d, ctypes.POINTER(d), i, d, d, d, d, ctypes.POINTER(d)]
     lib.sgp_strerror.restype = ctypes.c_char_p
     lib.sgp_strerror.argtypes = [i]
@@ -359,3 +361,41 @@ def steplength_rule(k, alpha, tau, Q, a, c1, c2, e, **params):
     nq = int(out[7])
     return dict(a1=out[0], a2=out[1], alpha_next=out[2], tau=out[3], alt=int(out[4]),
                 br1=int(out[5]), br2=int(out[6]), Q=[out[8 + i] for i in range(nq)])
+
+
+def batch_deconv(gs, psfs, bs, *, kind=KIND_SGP, f0s=None, fs=None, stream=None, **params):
+    """Many single-image problems (uneven sizes) in one batched run.
+    gs, psfs: lists of 2D CUDA tensors; bs: constant backgrounds; f0s: optional
+    starts (init=INIT_USER or INIT_WARM).  Returns (list of f, list of reports)."""
+    import torch
+    lib = load()
+    n = len(gs)
+    if fs is None:
+        fs = [torch.empty_like(g) for g in gs]
+    probs = (_Problem * n)()
+    keep = [gs, psfs, fs, f0s]
+    bcs = []
+    for i in range(n):
+        _check_dev(gs[i], "g")
+        _check_dev(psfs[i], "psf")
+        _check_dev(fs[i], "f")
+        ny, nx = gs[i].shape
+        bc = (ctypes.c_float * 1)(float(bs[i]))
+        bcs.append(bc)
+        probs[i] = _Problem(gs[i].data_ptr(), psfs[i].data_ptr(), None, ctypes.cast(bc, ctypes.c_void_p),
+                            1, ny, nx, ny, nx, 0, 0, 0)
+    fp = (ctypes.c_void_p * n)(*[f.data_ptr() for f in fs])
+    f0p = None
+    if f0s is not None:
+        for t in f0s:
+            _check_dev(t, "f0")
+        f0p = (ctypes.c_void_p * n)(*[t.data_ptr() for t in f0s])
+        if "init" not in params:
+            params["init"] = INIT_USER
+    prm, _, _ = _make_params(params, None)
+    if f0s is not None:
+        prm.f0 = f0s[0].data_ptr()
+    reps = (_Report * n)()
+    rc = lib.sgp_batch_deconv(kind, probs, n, fp, f0p, ctypes.byref(prm), reps, _stream(stream))
+    _raise(rc)
+    return fs, [_report(reps[i], rc, None) for i in range(n)]

@@ -19,7 +19,7 @@ enum { STOP_FIXED = 1, STOP_CONV = 2, STOP_DISCREPANCY = 4, STOP_RMSE = 8 };
 enum { REASON_MAXITER = 0, REASON_CONV = 1, REASON_DISCREPANCY = 2, REASON_RMSE = 3,
        REASON_STATIONARY = 4, REASON_ARMIJO = 5, REASON_NUMERIC = 6 };
 // start options (Sect. 3.1)
-enum { INIT_FLAT = 0, INIT_ZERO = 1, INIT_DATA = 2, INIT_USER = 3 };
+enum { INIT_FLAT = 0, INIT_ZERO = 1, INIT_DATA = 2, INIT_USER = 3, INIT_WARM = 4 };
 // data validation flags
 enum { FLAG_BAD_DATA = 1, FLAG_BAD_PSF = 2, FLAG_BAD_BG = 4 };
 
@@ -45,6 +45,8 @@ struct DevState {
   double norm_disc;  // 2 / (p |S|), Eq. (discrepancy)
   double cflat, ymin, ymax;
   double fsum;       // sum of f (PIX_FSUM)
+  double J_alt;      // KL of the flat start when a given start is judged against it
+  int used_fallback; // the given start was replaced by the flat one
   double mu;         // flux-projection multiplier
   double flux_fixed; // sum of max(0, z) over pixels with D = 0
   double flux_cnt;   // active-set size at the current mu
@@ -82,6 +84,19 @@ struct Args {
   double* part;          // reduction partials [slot][nblk]
   unsigned* counter;     // arrival counter of the reduction
   DevState* st;
+  // batched launches (nbatch > 0): item blockIdx.z takes its data through the
+  // pointer tables and offsets below (see batch_view)
+  int nbatch;
+  const float* const* gtab;   // [nbatch] observed image of each item
+  float* const* ftab;         // [nbatch] iterate of each item
+  const float* const* psftab; // [nbatch] PSF of each item
+  const float* const* srctab; // [nbatch] user start of each item, or null
+  const float* btab;          // [nbatch] constant background of each item
+  long long item_field;       // NY*NX: grad, d
+  long long item_obs;         // p*ny*nx: Af, Ad
+  long long item_spec;        // p*NY*NX/2: spec, khat
+  long long item_nyq;         // p*NY: knyq
+  long long item_part;        // partials per item
 };
 
 // Row-kernel operations: pointwise work fused into the row FFT passes.
@@ -121,6 +136,7 @@ enum PixOp {
   PIX_FLUX_NEWTON,  // flux projection: one Newton step on the multiplier
   PIX_FSUM,         // sum of f (flux of the start image)
   PIX_FSCALE,       // scale f to the prescribed flux
+  PIX_CHOOSE,       // keep the given start or fall back to the flat one (lower KL wins)
   PIX_NOPS
 };
 

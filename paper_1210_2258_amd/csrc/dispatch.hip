@@ -95,13 +95,14 @@ void launch_pix(int op, dim3 grid, const Args& a, hipStream_t s) {
     SGP_PIX_CASE(PIX_FLUX_NEWTON)
     SGP_PIX_CASE(PIX_FSUM)
     SGP_PIX_CASE(PIX_FSCALE)
+    SGP_PIX_CASE(PIX_CHOOSE)
 #undef SGP_PIX_CASE
     default: break;
   }
 }
 
-void launch_resume(DevState* st, int n, hipStream_t s) {
-  hipLaunchKernelGGL(resume_kernel, dim3(1), dim3(64), 0, s, st, n);
+void launch_resume(DevState* st, int n, int nitems, hipStream_t s) {
+  hipLaunchKernelGGL(resume_kernel, dim3((nitems + 63) / 64), dim3(64), 0, s, st, n, nitems);
 }
 
 void launch_twiddle(float2* tw, int L, hipStream_t s) {

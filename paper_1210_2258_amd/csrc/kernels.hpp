@@ -29,6 +29,30 @@ __device__ __forceinline__ long long sidx(int y, int kx, int NXh) {
   return ((long long)(y >> 3) * NXh + kx) * 8 + (y & 7);
 }
 
+// View of the arguments for item blockIdx.z of a batched launch.
+__device__ __forceinline__ Args batch_view(const Args& in) {
+  Args a = in;
+  if (in.nbatch > 0) {
+    const int b = blockIdx.z;
+    a.g = in.gtab[b];
+    a.f = in.ftab[b];
+    a.psf = in.psftab[b];
+    a.src = in.srctab ? in.srctab[b] : in.src;
+    a.b[0] = in.btab[b];
+    a.grad += b * in.item_field;
+    a.d += b * in.item_field;
+    a.Af += b * in.item_obs;
+    if (a.Ad) a.Ad += b * in.item_obs;
+    a.spec += b * in.item_spec;
+    a.khat += b * in.item_spec;
+    a.knyq += b * in.item_nyq;
+    a.part += b * in.item_part;
+    a.counter += b;
+    a.st += b;
+  }
+  return a;
+}
+
 // ------------------------------------------------------------- op traits
 __host__ __device__ constexpr bool row_has_inv(int op) {
   return op == ROW_STORE || op == ROW_RATIO || op == ROW_RLUPD || op == ROW_SETUPGRAD ||
@@ -110,7 +134,7 @@ __device__ __forceinline__ float row_point(const Args& a, const DevState* st, in
   } else if constexpr (OP == ROW_RATIO) {
     if (!P.inS(y, x)) return 0.f;
     const long long s = P.s_of(y, x);
-    if (a.flag) a.Af[s] = v;
+    if (a.flag & 1) a.Af[s] = v;
     const float g = a.g[s];
     const float yv = fmaxf(v + P.bg(s), 1e-30f);
     acc[0] += kl_term(g, yv);
@@ -195,6 +219,7 @@ template <int OP>
 __device__ __forceinline__ void row_finalize(DevState* st, const Args& a, const double* t) {
   if constexpr (OP == ROW_RATIO) {
     if (a.iter) fin_rl(st, t[0]);
+    else if (a.flag & 2) st->J_alt = t[0];
     else st->J = t[0];
   } else if constexpr (OP == ROW_SETUPGRAD) {
     fin_bounds(st, t[0], t[1]);
@@ -241,7 +266,8 @@ template <int L> struct RowCfg {
 };
 
 template <int L, int OP>
-__global__ __launch_bounds__(RowCfg<L>::NT) void row_kernel(Args a) {
+__global__ __launch_bounds__(RowCfg<L>::NT) void row_kernel(Args a_in) {
+  const Args a = batch_view(a_in);
   using P = FftPlan<L>;
   constexpr int TF = P::TF;
   constexpr int RP = RowCfg<L>::RP;
@@ -346,7 +372,8 @@ template <int LY> struct ColCfg {
 };
 
 template <int LY, int MODE, int CONJ>
-__global__ __launch_bounds__(ColCfg<LY>::NT) void col_kernel(Args a) {
+__global__ __launch_bounds__(ColCfg<LY>::NT) void col_kernel(Args a_in) {
+  const Args a = batch_view(a_in);
   constexpr int TF = FftPlan<LY>::TF;
   constexpr int C = ColCfg<LY>::C;
   constexpr int NT = ColCfg<LY>::NT;

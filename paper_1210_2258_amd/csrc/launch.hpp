@@ -15,6 +15,6 @@ void launch_row(int L, int op, dim3 grid, const Args& a, hipStream_t s);
 void launch_col(int L, int mode, int conj, dim3 grid, const Args& a, hipStream_t s);
 void launch_pix(int op, dim3 grid, const Args& a, hipStream_t s);
 void launch_twiddle(float2* tw, int L, hipStream_t s);
-void launch_resume(DevState* st, int n, hipStream_t s);
+void launch_resume(DevState* st, int n, int nitems, hipStream_t s);
 
 }  // namespace sgp

@@ -28,7 +28,8 @@ struct PixKinds {
 };
 
 template <int OP>
-__global__ __launch_bounds__(kPixThreads) void pix_kernel(Args a) {
+__global__ __launch_bounds__(kPixThreads) void pix_kernel(Args a_in) {
+  const Args a = batch_view(a_in);
   constexpr int NS = pix_nslots(OP);
   DevState* st = a.st;
   if (a.iter && (st->done || st->pause)) return;
@@ -80,16 +81,27 @@ __global__ __launch_bounds__(kPixThreads) void pix_kernel(Args a) {
       const float w = a.invw ? a.invw[i] : a.invw_s;
       const float mr = w > 0.f ? 1.f : 0.f;
       float v = 0.f;
-      if (st->init == INIT_FLAT) {
+      const int mode = a.jsel;  // start option chosen by the host for this launch
+      if (mode == INIT_FLAT) {
         v = mr * (float)st->cflat;
-      } else if (st->init == INIT_DATA) {
+      } else if (mode == INIT_DATA) {
         const int y = (int)(i / a.NX), x = (int)(i % a.NX);
         const bool in = (unsigned)(y - a.oy) < (unsigned)a.ny && (unsigned)(x - a.ox) < (unsigned)a.nx;
         v = in ? mr * a.g[(long long)(y - a.oy) * a.nx + (x - a.ox)] : 0.f;
-      } else if (st->init == INIT_USER) {
+      } else if (mode == INIT_USER) {
         v = fmaxf(0.f, a.src[i]);
       }
       a.f[i] = v;
+    }
+  } else if constexpr (OP == PIX_CHOOSE) {
+    // Sect. 3.1 start "provided by the user", kept only if its KL is not
+    // larger than that of the flat start
+    if (st->J > st->J_alt) {
+      for (long long i = i0; i < nF; i += stride) {
+        const float w = a.invw ? a.invw[i] : a.invw_s;
+        a.f[i] = w > 0.f ? (float)st->cflat : 0.f;
+      }
+      if (blockIdx.x == 0 && threadIdx.x == 0) st->used_fallback = 1;
     }
   } else if constexpr (OP == PIX_INVW) {
     // Eq. (Rdef): R = {alpha_j >= sigma for all j}; invw = M_R / sum_j alpha_j
@@ -183,10 +195,11 @@ __global__ __launch_bounds__(kPixThreads) void pix_kernel(Args a) {
 }
 
 // Starts a stepping call of n iterations.
-__global__ void resume_kernel(DevState* st, int n) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) {
-    st->pause = 0;
-    st->k_stop = st->k + n;
+__global__ void resume_kernel(DevState* st, int n, int nitems) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < nitems) {
+    st[i].pause = 0;
+    st[i].k_stop = st[i].k + n;
   }
 }
 

@@ -43,9 +43,10 @@ enum Kind { KIND_RL = SGP_KIND_RL, KIND_SGP = SGP_KIND_SGP, KIND_OP = 2 };
 
 struct PlanKey {
   int kind, p, NY, NX, ny, nx, oy, ox, boundary, dev;
+  int nitems = 1;  // batched problems of this shape
   bool operator<(const PlanKey& o) const {
-    return std::tie(kind, p, NY, NX, ny, nx, oy, ox, boundary, dev) <
-           std::tie(o.kind, o.p, o.NY, o.NX, o.ny, o.nx, o.oy, o.ox, o.boundary, o.dev);
+    return std::tie(kind, p, NY, NX, ny, nx, oy, ox, boundary, dev, nitems) <
+           std::tie(o.kind, o.p, o.NY, o.NX, o.ny, o.nx, o.oy, o.ox, o.boundary, o.dev, o.nitems);
   }
 };
 
@@ -66,12 +67,19 @@ struct Plan {
   double* part = nullptr;
   unsigned* counter = nullptr;
   DevState* st = nullptr;
-  DevState* host_st = nullptr;  // pinned
+  DevState* host_st = nullptr;  // pinned, one per item
   double* trace = nullptr;
   int trace_rows = 0;
+  // batched items: device pointer tables
+  const float** gtab = nullptr;
+  float** ftab = nullptr;
+  const float** psftab = nullptr;
+  const float** srctab = nullptr;
+  float* btab = nullptr;
 
   ~Plan() {
-    void* ptrs[] = {grad, d, invw, Af, Ad, aux, spec, khat, knyq, tw_row, tw_col, part, counter, st, trace};
+    void* ptrs[] = {grad, d, invw, Af, Ad, aux, spec, khat, knyq, tw_row, tw_col, part, counter, st, trace,
+                    (void*)gtab, (void*)ftab, (void*)psftab, (void*)srctab, btab};
     for (void* q : ptrs)
       if (q) (void)hipFree(q);
     if (host_st) (void)hipHostFree(host_st);
@@ -98,9 +106,10 @@ static int dalloc(T** p, size_t n) {
 static int make_plan(const PlanKey& key, hipStream_t s, std::unique_ptr<Plan>& pl) {
   pl = std::make_unique<Plan>();
   pl->key = key;
-  const size_t nF = (size_t)key.NY * key.NX;
-  const size_t nS = (size_t)key.ny * key.nx;
-  const size_t nSpec = (size_t)spec_elems(key.NY, key.NX);
+  const size_t n = (size_t)key.nitems;
+  const size_t nF = (size_t)key.NY * key.NX * n;
+  const size_t nS = (size_t)key.ny * key.nx * n;
+  const size_t nSpec = (size_t)spec_elems(key.NY, key.NX) * n;
   int rc;
   if ((rc = dalloc(&pl->grad, nF))) return rc;
   if ((rc = dalloc(&pl->d, nF))) return rc;
@@ -114,14 +123,21 @@ static int make_plan(const PlanKey& key, hipStream_t s, std::unique_ptr<Plan>& p
   if (key.kind == KIND_SGP && (rc = dalloc(&pl->Ad, nS * key.p))) return rc;
   if ((rc = dalloc(&pl->spec, nSpec * key.p))) return rc;
   if ((rc = dalloc(&pl->khat, nSpec * key.p))) return rc;
-  if ((rc = dalloc(&pl->knyq, (size_t)key.NY * key.p))) return rc;
+  if ((rc = dalloc(&pl->knyq, (size_t)key.NY * key.p * n))) return rc;
   if ((rc = dalloc(&pl->tw_row, (size_t)key.NX))) return rc;
   if ((rc = dalloc(&pl->tw_col, (size_t)key.NY))) return rc;
-  if ((rc = dalloc(&pl->part, part_capacity(key)))) return rc;
-  if ((rc = dalloc(&pl->counter, 1))) return rc;
-  if ((rc = dalloc(&pl->st, 1))) return rc;
-  SGP_HIP(hipHostMalloc((void**)&pl->host_st, sizeof(DevState), hipHostMallocDefault));
-  SGP_HIP(hipMemsetAsync(pl->counter, 0, sizeof(unsigned), s));
+  if ((rc = dalloc(&pl->part, part_capacity(key) * n))) return rc;
+  if ((rc = dalloc(&pl->counter, n))) return rc;
+  if ((rc = dalloc(&pl->st, n))) return rc;
+  if (n > 1) {
+    if ((rc = dalloc(&pl->gtab, n))) return rc;
+    if ((rc = dalloc(&pl->ftab, n))) return rc;
+    if ((rc = dalloc(&pl->psftab, n))) return rc;
+    if ((rc = dalloc(&pl->srctab, n))) return rc;
+    if ((rc = dalloc(&pl->btab, n))) return rc;
+  }
+  SGP_HIP(hipHostMalloc((void**)&pl->host_st, sizeof(DevState) * n, hipHostMallocDefault));
+  SGP_HIP(hipMemsetAsync(pl->counter, 0, sizeof(unsigned) * n, s));
   launch_twiddle(pl->tw_row, key.NX, s);
   launch_twiddle(pl->tw_col, key.NY, s);
   SGP_HIP(hipGetLastError());
@@ -183,8 +199,9 @@ static int check_params(const sgp_params& p, int kind) {
     return fail(SGP_E_INVALID_ARG, "unknown stop bits");
   if (!(p.tol >= 0)) return fail(SGP_E_INVALID_ARG, "tol must be >= 0");
   if (!(p.disc_target > 0)) return fail(SGP_E_INVALID_ARG, "disc_target must be > 0");
-  if (p.init < SGP_INIT_FLAT || p.init > SGP_INIT_USER) return fail(SGP_E_INVALID_ARG, "unknown init");
-  if (p.init == SGP_INIT_USER && !p.f0) return fail(SGP_E_INVALID_ARG, "SGP_INIT_USER needs f0");
+  if (p.init < SGP_INIT_FLAT || p.init > SGP_INIT_WARM) return fail(SGP_E_INVALID_ARG, "unknown init");
+  if ((p.init == SGP_INIT_USER || p.init == SGP_INIT_WARM) && !p.f0)
+    return fail(SGP_E_INVALID_ARG, "SGP_INIT_USER / SGP_INIT_WARM need f0");
   if (kind == KIND_RL && p.init == SGP_INIT_ZERO)
     return fail(SGP_E_INVALID_ARG, "RL cannot start from the zero image");
   if (kind == KIND_SGP) {
@@ -234,6 +251,7 @@ struct Launcher {
   Args base;
   hipStream_t s = nullptr;
   int NY = 0, NX = 0;
+  int nz = 1;  // batched items (grid z)
   bool timing = false;
   struct Mark { hipEvent_t a, b; int cls; };
   std::vector<Mark> marks;
@@ -269,7 +287,7 @@ struct Launcher {
     a.flag = flag;
     hipEvent_t e0 = nullptr;
     begin(cls, e0);
-    launch_row(NX, op, dim3(gx, jc), a, s);
+    launch_row(NX, op, dim3(gx, jc, nz), a, s);
     end(cls, e0);
   }
   void col(int mode, int conj, int jc, int iter, int cls = -1) {
@@ -278,7 +296,7 @@ struct Launcher {
     a.iter = iter;
     hipEvent_t e0 = nullptr;
     begin(cls, e0);
-    launch_col(NY, mode, conj, dim3((NX / 2 + C - 1) / C, jc), a, s);
+    launch_col(NY, mode, conj, dim3((NX / 2 + C - 1) / C, jc, nz), a, s);
     end(cls, e0);
   }
   void pix(int op, long long n, int iter, int jsel = 0, int cls = -1) {
@@ -293,7 +311,7 @@ struct Launcher {
     a.jsel = jsel;
     hipEvent_t e0 = nullptr;
     begin(cls, e0);
-    launch_pix(op, dim3((unsigned)nb), a, s);
+    launch_pix(op, dim3((unsigned)nb, 1, nz), a, s);
     end(cls, e0);
   }
   ~Launcher() {
@@ -354,6 +372,8 @@ struct sgp_solver {
   int graph_block = 0;
   bool use_graph = true;
   bool done = false;
+  int nitems = 1;  // batched problems (same shape), item i's iterate is fs[i]
+  std::vector<float*> fs;
   std::chrono::steady_clock::time_point t0;
   double ms[SGP_KCLASS_COUNT] = {0};
   long long cnt[SGP_KCLASS_COUNT] = {0};
@@ -368,9 +388,26 @@ struct sgp_solver {
 namespace sgp {
 
 static int read_state(sgp_solver* S) {
-  SGP_HIP(hipMemcpyAsync(S->pl->host_st, S->pl->st, sizeof(DevState), hipMemcpyDeviceToHost, S->s));
+  SGP_HIP(hipMemcpyAsync(S->pl->host_st, S->pl->st, sizeof(DevState) * S->nitems, hipMemcpyDeviceToHost, S->s));
   SGP_HIP(hipStreamSynchronize(S->s));
   return 0;
+}
+
+static bool all_done(const sgp_solver* S) {
+  for (int i = 0; i < S->nitems; ++i)
+    if (!S->pl->host_st[i].done) return false;
+  return true;
+}
+
+// Points the field input of ROW_FIELD / PIX_INITF at the iterate f (or the
+// user start) of every item.
+static void src_iterate(sgp_solver* S) {
+  if (S->nitems > 1) S->L.base.srctab = (const float* const*)S->pl->ftab;
+  else S->L.base.src = S->f;
+}
+static void src_user(sgp_solver* S) {
+  if (S->nitems > 1) S->L.base.srctab = S->pl->srctab;
+  else S->L.base.src = S->prm.f0;
 }
 
 // Newton steps allowed for the flux multiplier per iteration (each exits at
@@ -416,10 +453,13 @@ static int setup(sgp_solver* S) {
   SGP_HIP(hipGetLastError());
   int rc;
   if ((rc = read_state(S))) return rc;
-  const int fl = S->pl->host_st->flags;
-  if (fl & FLAG_BAD_PSF) return fail(SGP_E_BAD_PSF, "PSF has negative or non-finite entries or a non-positive sum");
-  if (fl & FLAG_BAD_DATA) return fail(SGP_E_BAD_DATA, "g must be finite and >= 0");
-  if (fl & FLAG_BAD_BG) return fail(SGP_E_BAD_DATA, "background map must be finite and >= 0");
+  for (int i = 0; i < S->nitems; ++i) {
+    const int fl = S->pl->host_st[i].flags;
+    const std::string who = S->nitems > 1 ? " (batch item " + std::to_string(i) + ")" : "";
+    if (fl & FLAG_BAD_PSF) return fail(SGP_E_BAD_PSF, "PSF has negative or non-finite entries or a non-positive sum" + who);
+    if (fl & FLAG_BAD_DATA) return fail(SGP_E_BAD_DATA, "g must be finite and >= 0" + who);
+    if (fl & FLAG_BAD_BG) return fail(SGP_E_BAD_DATA, "background map must be finite and >= 0" + who);
+  }
   // transfer functions K_j / (NY NX): shifted PSF -> row FFT -> column FFT
   L.row(ROW_PSF, pb.p, 0);
   L.col(COL_FWD, 0, pb.p, 0);
@@ -433,13 +473,32 @@ static int setup(sgp_solver* S) {
     L.pix(PIX_INVW, nF, 0);
     L.base = save;
   }
-  if (S->prm.init == SGP_INIT_FLAT || S->prm.flux_constraint) L.pix(PIX_FLATSUM, pb.p * nS, 0);
-  L.pix(PIX_INITF, nF, 0);
+  const int init = S->prm.init;
+  if (init == SGP_INIT_FLAT || init == SGP_INIT_WARM || S->prm.flux_constraint) L.pix(PIX_FLATSUM, pb.p * nS, 0);
+  if (init == SGP_INIT_WARM) {
+    // J of the flat start (kept aside), then J of the given start; each item
+    // keeps the given start only if its KL is not larger
+    L.pix(PIX_INITF, nF, 0, INIT_FLAT);
+    src_iterate(S);
+    L.row(ROW_FIELD, 1, 0);
+    L.col(COL_CONV, 0, 1, 0);
+    L.row(ROW_RATIO, pb.p, 0, 2);
+    src_user(S);
+    L.pix(PIX_INITF, nF, 0, INIT_USER);
+    src_iterate(S);
+    L.row(ROW_FIELD, 1, 0);
+    L.col(COL_CONV, 0, 1, 0);
+    L.row(ROW_RATIO, pb.p, 0, 0);
+    L.pix(PIX_CHOOSE, nF, 0);
+  } else {
+    src_user(S);
+    L.pix(PIX_INITF, nF, 0, init);
+  }
   if (S->prm.flux_constraint) {  // the start image is put on the constraint set
     L.pix(PIX_FSUM, nF, 0);
     L.pix(PIX_FSCALE, nF, 0);
   }
-  L.base.src = S->f;
+  src_iterate(S);
   L.row(ROW_FIELD, 1, 0);
   if (S->kind == KIND_SGP) {
     L.col(COL_CONV, 0, 1, 0);
@@ -449,7 +508,7 @@ static int setup(sgp_solver* S) {
   }
   SGP_HIP(hipGetLastError());
   if ((rc = read_state(S))) return rc;
-  S->done = S->pl->host_st->done != 0;
+  S->done = all_done(S);
   return 0;
 }
 
@@ -480,13 +539,11 @@ static int step(sgp_solver* S, int n, int* done_out) {
     if (done_out) *done_out = S->done ? 1 : 0;
     return 0;
   }
-  launch_resume(S->pl->st, n, S->s);
+  launch_resume(S->pl->st, n, S->nitems, S->s);
   if (S->kind == KIND_RL) {
     // the spectrum of f is rebuilt so a resumed RL call starts from f
-    Args a = S->L.base;
-    S->L.base.src = S->f;
+    src_iterate(S);
     S->L.row(ROW_FIELD, 1, 0);
-    S->L.base = a;
   }
   const bool early = (S->prm.stop & (SGP_STOP_CONV | SGP_STOP_DISCREPANCY)) != 0;
   const int iters = (S->kind == KIND_RL) ? n + 1 : n;  // RL evaluates J once more before pausing
@@ -495,7 +552,7 @@ static int step(sgp_solver* S, int n, int* done_out) {
       enqueue_iteration(S);
       if (early && (it % 16) == 15) {
         if ((rc = read_state(S))) return rc;
-        if (S->pl->host_st->done) break;
+        if (all_done(S)) break;
       }
     }
     SGP_HIP(hipGetLastError());
@@ -518,37 +575,17 @@ static int step(sgp_solver* S, int n, int* done_out) {
       SGP_HIP(hipGraphLaunch(S->graph, S->s));
       if (early && r + 1 < reps && (r % 2) == 1) {
         if ((rc = read_state(S))) return rc;
-        if (S->pl->host_st->done) break;
+        if (all_done(S)) break;
       }
     }
   }
   if ((rc = read_state(S))) return rc;
-  S->done = S->pl->host_st->done != 0;
+  S->done = all_done(S);
   if (done_out) *done_out = S->done ? 1 : 0;
   return 0;
 }
 
-static int report(sgp_solver* S, sgp_report* rep) {
-  int rc;
-  S->L.pix(PIX_FSUM, (long long)S->pb.NY * S->pb.NX, 0);
-  if ((rc = read_state(S))) return rc;
-  const DevState& h = *S->pl->host_st;
-  if (S->prm.trace && S->pl->trace) {
-    SGP_HIP(hipMemcpy(S->prm.trace, S->pl->trace,
-                      sizeof(double) * kTraceCols * (size_t)(S->prm.max_iter + 1), hipMemcpyDeviceToHost));
-  }
-  if (rep) {
-    rep->iters = h.k;
-    rep->stop_reason = h.reason;
-    rep->backtracks = h.total_back;
-    rep->used_fallback = 0;
-    rep->kl = h.J;
-    rep->discrepancy = h.norm_disc * h.J;
-    rep->flux = h.fsum;
-    rep->L1 = h.L1;
-    rep->L2 = h.L2;
-    rep->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - S->t0).count();
-  }
+static int item_code(const sgp_solver* S, const DevState& h) {
   if (!h.done) return SGP_OK;
   switch (h.reason) {
     case REASON_NUMERIC: return fail(SGP_E_NUMERIC, "non-finite value during the iteration");
@@ -560,24 +597,91 @@ static int report(sgp_solver* S, sgp_report* rep) {
   }
 }
 
-// Builds a solver; with `cached` the workspace comes from the per-shape cache
-// (one-shot calls, serialised by the caller), otherwise the solver owns it.
-static int create(int kind, const Problem& pb, const sgp_params* prm_in, float* f, void* stream, bool cached,
-                  std::unique_ptr<sgp_solver>& out) {
+static void fill_report(const sgp_solver* S, const DevState& h, sgp_report* rep) {
+  rep->iters = h.k;
+  rep->stop_reason = h.reason;
+  rep->backtracks = h.total_back;
+  rep->used_fallback = h.used_fallback;
+  rep->kl = h.J;
+  rep->discrepancy = h.norm_disc * h.J;
+  rep->flux = h.fsum;
+  rep->L1 = h.L1;
+  rep->L2 = h.L2;
+  rep->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - S->t0).count();
+}
+
+// Fills reps[0..nitems) and returns the most severe item code (errors first,
+// then the largest warning).
+static int report(sgp_solver* S, sgp_report* rep) {
+  int rc;
+  S->L.pix(PIX_FSUM, (long long)S->pb.NY * S->pb.NX, 0);
+  if ((rc = read_state(S))) return rc;
+  if (S->prm.trace && S->pl->trace) {
+    SGP_HIP(hipMemcpy(S->prm.trace, S->pl->trace,
+                      sizeof(double) * kTraceCols * (size_t)(S->prm.max_iter + 1), hipMemcpyDeviceToHost));
+  }
+  int worst = SGP_OK;
+  for (int i = 0; i < S->nitems; ++i) {
+    const DevState& h = S->pl->host_st[i];
+    if (rep) fill_report(S, h, rep + i);
+    const int c = item_code(S, h);
+    if (c < 0 ? (worst >= 0 || c < worst) : (worst >= 0 && c > worst)) worst = c;
+  }
+  return worst;
+}
+
+static int to_problem(const sgp_problem* pr, Problem& pb) {
+  if (!pr) return fail(SGP_E_INVALID_ARG, "null problem");
+  if (pr->p < 1 || pr->p > kMaxP) return fail(SGP_E_INVALID_ARG, "p must be in 1..8");
+  if (!pr->b_map && !pr->b_const) return fail(SGP_E_INVALID_ARG, "need b_map or b_const");
+  pb.g = pr->g; pb.psf = pr->psf; pb.bmap = pr->b_map;
+  for (int j = 0; j < pr->p; ++j) pb.b[j] = pr->b_const ? pr->b_const[j] : 0.f;
+  pb.p = pr->p; pb.ny = pr->ny; pb.nx = pr->nx;
+  pb.boundary = pr->boundary != 0;
+  if (pb.boundary) {
+    pb.NY = pr->NY; pb.NX = pr->NX; pb.oy = pr->oy; pb.ox = pr->ox;
+  } else {
+    pb.NY = pr->ny; pb.NX = pr->nx; pb.oy = pb.ox = 0;
+  }
+  return 0;
+}
+
+// Builds a solver for one problem or for a batch of problems of one shape
+// (item i: problem items[i], iterate fs[i], start f0s[i]).  With `cached` the
+// workspace comes from the per-shape cache (one-shot calls, serialised by the
+// caller), otherwise the solver owns it.
+static int create_items(int kind, const std::vector<Problem>& items, const std::vector<float*>& fs,
+                        const std::vector<const float*>& f0s, const sgp_params* prm_in, void* stream,
+                        bool cached, std::unique_ptr<sgp_solver>& out) {
   auto S = std::make_unique<sgp_solver>();
   S->t0 = std::chrono::steady_clock::now();
   if (prm_in) S->prm = *prm_in;
   else defaults(&S->prm);
   int rc;
-  if (!f) return fail(SGP_E_INVALID_ARG, "f must be non-null");
+  const int n = (int)items.size();
+  if (n < 1) return fail(SGP_E_INVALID_ARG, "no problem given");
+  for (int i = 0; i < n; ++i)
+    if (!fs[i]) return fail(SGP_E_INVALID_ARG, "f must be non-null");
   if (kind != KIND_RL && kind != KIND_SGP) return fail(SGP_E_INVALID_ARG, "unknown solver kind");
-  if ((rc = check_problem(pb))) return rc;
+  for (const Problem& q : items)
+    if ((rc = check_problem(q))) return rc;
+  if (n > 1) {
+    if ((S->prm.init == SGP_INIT_USER || S->prm.init == SGP_INIT_WARM))
+      for (int i = 0; i < n; ++i)
+        if (!f0s[i]) return fail(SGP_E_INVALID_ARG, "SGP_INIT_USER / SGP_INIT_WARM need a start for every item");
+    S->prm.trace = nullptr;  // no per-iteration trace for batches
+    if (S->prm.f0 == nullptr && (S->prm.init == SGP_INIT_USER || S->prm.init == SGP_INIT_WARM))
+      S->prm.f0 = f0s[0];
+  }
   if ((rc = check_params(S->prm, kind))) return rc;
   int dev;
   if ((rc = current_device(&dev))) return rc;
+  const Problem& pb = items[0];
   S->kind = kind;
   S->pb = pb;
-  S->f = f;
+  S->f = fs[0];
+  S->nitems = n;
+  S->fs = fs;
   S->user = (hipStream_t)stream;
   SGP_HIP(hipStreamCreateWithFlags(&S->s, hipStreamNonBlocking));
   // order the internal stream after the caller's stream
@@ -587,6 +691,7 @@ static int create(int kind, const Problem& pb, const sgp_params* prm_in, float* 
   SGP_HIP(hipStreamWaitEvent(S->s, e, 0));
   SGP_HIP(hipEventDestroy(e));
   PlanKey key{kind, pb.p, pb.NY, pb.NX, pb.ny, pb.nx, pb.oy, pb.ox, pb.boundary ? 1 : 0, dev};
+  key.nitems = n;
   if (cached) {
     if ((rc = cached_plan(key, S->s, &S->pl))) return rc;
   } else {
@@ -605,8 +710,8 @@ static int create(int kind, const Problem& pb, const sgp_params* prm_in, float* 
     }
     SGP_HIP(hipMemsetAsync(pl->trace, 0, sizeof(double) * kTraceCols * rows, S->s));
   }
-  fill_state(*pl->host_st, S->prm, pb, S->prm.trace ? pl->trace : nullptr);
-  SGP_HIP(hipMemcpyAsync(pl->st, pl->host_st, sizeof(DevState), hipMemcpyHostToDevice, S->s));
+  for (int i = 0; i < n; ++i) fill_state(pl->host_st[i], S->prm, items[i], S->prm.trace ? pl->trace : nullptr);
+  SGP_HIP(hipMemcpyAsync(pl->st, pl->host_st, sizeof(DevState) * n, hipMemcpyHostToDevice, S->s));
 
   Launcher& L = S->L;
   std::memset(&L.base, 0, sizeof(L.base));
@@ -614,17 +719,140 @@ static int create(int kind, const Problem& pb, const sgp_params* prm_in, float* 
   a.NY = pb.NY; a.NX = pb.NX; a.ny = pb.ny; a.nx = pb.nx; a.oy = pb.oy; a.ox = pb.ox; a.p = pb.p;
   a.g = pb.g; a.bmap = pb.bmap;
   for (int j = 0; j < kMaxP; ++j) a.b[j] = pb.b[j];
-  a.f = f; a.grad = pl->grad; a.d = pl->d;
+  a.f = fs[0]; a.grad = pl->grad; a.d = pl->d;
   a.invw = pb.boundary ? pl->invw : nullptr;
   a.invw_s = 1.0f / (float)pb.p;
   a.Af = pl->Af; a.Ad = pl->Ad; a.spec = pl->spec; a.khat = pl->khat; a.knyq = pl->knyq;
   a.psf = pb.psf; a.aux = pl->aux; a.src = S->prm.f0;
   a.tw_row = pl->tw_row; a.tw_col = pl->tw_col;
   a.part = pl->part; a.counter = pl->counter; a.st = pl->st;
-  L.s = S->s; L.NY = pb.NY; L.NX = pb.NX;
+  if (n > 1) {
+    std::vector<const float*> gt(n), pt(n), st0(n);
+    std::vector<float> bt(n);
+    for (int i = 0; i < n; ++i) {
+      gt[i] = items[i].g;
+      pt[i] = items[i].psf;
+      st0[i] = f0s.empty() ? nullptr : f0s[i];
+      bt[i] = items[i].b[0];
+    }
+    SGP_HIP(hipMemcpy(pl->gtab, gt.data(), sizeof(float*) * n, hipMemcpyHostToDevice));
+    SGP_HIP(hipMemcpy(pl->ftab, fs.data(), sizeof(float*) * n, hipMemcpyHostToDevice));
+    SGP_HIP(hipMemcpy(pl->psftab, pt.data(), sizeof(float*) * n, hipMemcpyHostToDevice));
+    SGP_HIP(hipMemcpy(pl->srctab, st0.data(), sizeof(float*) * n, hipMemcpyHostToDevice));
+    SGP_HIP(hipMemcpy(pl->btab, bt.data(), sizeof(float) * n, hipMemcpyHostToDevice));
+    a.nbatch = n;
+    a.gtab = pl->gtab;
+    a.ftab = pl->ftab;
+    a.psftab = pl->psftab;
+    a.srctab = pl->srctab;
+    a.btab = pl->btab;
+    PlanKey k1 = key;
+    k1.nitems = 1;
+    a.item_field = (long long)pb.NY * pb.NX;
+    a.item_obs = (long long)pb.p * pb.ny * pb.nx;
+    a.item_spec = (long long)pb.p * spec_elems(pb.NY, pb.NX);
+    a.item_nyq = (long long)pb.p * pb.NY;
+    a.item_part = (long long)part_capacity(k1);
+  }
+  L.s = S->s; L.NY = pb.NY; L.NX = pb.NX; L.nz = n;
   if ((rc = setup(S.get()))) return rc;
   out = std::move(S);
   return 0;
+}
+
+static int create(int kind, const Problem& pb, const sgp_params* prm_in, float* f, void* stream, bool cached,
+                  std::unique_ptr<sgp_solver>& out) {
+  return create_items(kind, std::vector<Problem>{pb}, std::vector<float*>{f},
+                      std::vector<const float*>{prm_in ? prm_in->f0 : nullptr}, prm_in, stream, cached, out);
+}
+
+// Many problems in one run: problems are grouped by shape, each group is one
+// batched solver (every kernel launch covers all its items, grid z = item),
+// and the groups advance together: one HIP graph holds a block of iterations
+// of every group as parallel branches and is replayed until every item has
+// met its stop rule.
+static int batch_run(int kind, const sgp_problem* probs, int n, float* const* fout, const float* const* f0s,
+                     const sgp_params* prm, sgp_report* reps, void* stream) {
+  if (!probs || n < 1 || !fout) return fail(SGP_E_INVALID_ARG, "need n >= 1 problems and outputs");
+  std::map<std::pair<int, int>, std::vector<int>> groups;
+  std::vector<Problem> all(n);
+  int rc;
+  for (int i = 0; i < n; ++i) {
+    if ((rc = to_problem(&probs[i], all[i]))) return rc;
+    if (all[i].p != 1 || all[i].boundary || all[i].bmap)
+      return fail(SGP_E_INVALID_ARG, "batched problems must be single periodic images with constant background");
+    groups[{all[i].ny, all[i].nx}].push_back(i);
+  }
+  std::lock_guard<std::mutex> lock(g_mutex);
+  std::vector<std::unique_ptr<sgp_solver>> sol;
+  std::vector<std::vector<int>> idx;
+  for (auto& kv : groups) {
+    std::vector<Problem> items;
+    std::vector<float*> fs;
+    std::vector<const float*> f0v;
+    for (int i : kv.second) {
+      items.push_back(all[i]);
+      fs.push_back(fout[i]);
+      f0v.push_back(f0s ? f0s[i] : nullptr);
+    }
+    std::unique_ptr<sgp_solver> S;
+    if ((rc = create_items(kind, items, fs, f0v, prm, stream, true, S))) return rc;
+    sol.push_back(std::move(S));
+    idx.push_back(kv.second);
+  }
+  const int max_iter = sol[0]->prm.max_iter;
+  const int iters = kind == KIND_RL ? max_iter + 1 : max_iter;
+  hipStream_t s0 = sol[0]->s;
+  for (auto& S : sol) launch_resume(S->pl->st, max_iter, S->nitems, S->s);
+  // the first group's stream carries the graph; the others fork from it
+  std::vector<hipEvent_t> ev(2 * sol.size());
+  for (auto& e : ev) SGP_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  for (size_t c = 1; c < sol.size(); ++c) {  // setup and resume of every group precede the graph
+    SGP_HIP(hipEventRecord(ev[c], sol[c]->s));
+    SGP_HIP(hipStreamWaitEvent(s0, ev[c], 0));
+  }
+  const int block = std::min(iters, 16);
+  hipGraph_t g = nullptr;
+  hipGraphExec_t ge = nullptr;
+  SGP_HIP(hipStreamBeginCapture(s0, hipStreamCaptureModeThreadLocal));
+  SGP_HIP(hipEventRecord(ev[0], s0));
+  for (size_t c = 1; c < sol.size(); ++c) SGP_HIP(hipStreamWaitEvent(sol[c]->s, ev[0], 0));
+  for (auto& S : sol)
+    for (int b = 0; b < block; ++b) enqueue_iteration(S.get());
+  for (size_t c = 1; c < sol.size(); ++c) {
+    SGP_HIP(hipEventRecord(ev[sol.size() + c], sol[c]->s));
+    SGP_HIP(hipStreamWaitEvent(s0, ev[sol.size() + c], 0));
+  }
+  hipError_t ce = hipStreamEndCapture(s0, &g);
+  if (ce != hipSuccess) return fail(SGP_E_HIP, std::string("graph capture: ") + hipGetErrorString(ce));
+  SGP_HIP(hipGraphInstantiate(&ge, g, nullptr, nullptr, 0));
+  const int reps_n = (iters + block - 1) / block;
+  for (int r = 0; r < reps_n; ++r) {
+    SGP_HIP(hipGraphLaunch(ge, s0));
+    if (r % 4 == 3 || r + 1 == reps_n) {  // stop once every item has stopped
+      SGP_HIP(hipStreamSynchronize(s0));
+      bool done = true;
+      for (auto& S : sol) {
+        if ((rc = read_state(S.get()))) return rc;
+        done = done && all_done(S.get());
+      }
+      if (done) break;
+    }
+  }
+  SGP_HIP(hipStreamSynchronize(s0));
+  (void)hipGraphExecDestroy(ge);
+  (void)hipGraphDestroy(g);
+  for (auto& e : ev) (void)hipEventDestroy(e);
+  int worst = SGP_OK;
+  std::vector<sgp_report> tmp;
+  for (size_t c = 0; c < sol.size(); ++c) {
+    tmp.resize(sol[c]->nitems);
+    const int code = report(sol[c].get(), tmp.data());
+    if (code < 0 ? (worst >= 0 || code < worst) : (worst >= 0 && code > worst)) worst = code;
+    if (reps)
+      for (int t = 0; t < sol[c]->nitems; ++t) reps[idx[c][t]] = tmp[t];
+  }
+  return worst;
 }
 
 static int one_shot(int kind, const Problem& pb, const sgp_params* prm, float* f, sgp_report* rep, void* stream) {
@@ -681,21 +909,6 @@ static int apply_operator(const float* psf, const float* x, int ny, int nx, int 
   return 0;
 }
 
-static int to_problem(const sgp_problem* pr, Problem& pb) {
-  if (!pr) return fail(SGP_E_INVALID_ARG, "null problem");
-  if (pr->p < 1 || pr->p > kMaxP) return fail(SGP_E_INVALID_ARG, "p must be in 1..8");
-  if (!pr->b_map && !pr->b_const) return fail(SGP_E_INVALID_ARG, "need b_map or b_const");
-  pb.g = pr->g; pb.psf = pr->psf; pb.bmap = pr->b_map;
-  for (int j = 0; j < pr->p; ++j) pb.b[j] = pr->b_const ? pr->b_const[j] : 0.f;
-  pb.p = pr->p; pb.ny = pr->ny; pb.nx = pr->nx;
-  pb.boundary = pr->boundary != 0;
-  if (pb.boundary) {
-    pb.NY = pr->NY; pb.NX = pr->NX; pb.oy = pr->oy; pb.ox = pr->ox;
-  } else {
-    pb.NY = pr->ny; pb.NX = pr->nx; pb.oy = pb.ox = 0;
-  }
-  return 0;
-}
 
 }  // namespace sgp
 
@@ -829,6 +1042,11 @@ int sgp_solver_destroy(sgp_solver* s) {
   (void)hipStreamSynchronize(s->s);
   delete s;
   return 0;
+}
+
+int sgp_batch_deconv(int kind, const sgp_problem* probs, int n, float* const* f, const float* const* f0,
+                     const sgp_params* prm, sgp_report* reps, void* hip_stream) {
+  SGP_GUARD(batch_run(kind, probs, n, f, f0, prm, reps, hip_stream));
 }
 
 int sgp_steplength_rule(const sgp_params* prm, int k, double alpha, double tau, const double* Q, int nQ,
