@@ -17,7 +17,8 @@ paper; the network itself is not part of the paper):
 
 conv is a 5x5 cross-correlation with periodic padding,
     out[co](y, x) = bias[co] + sum_{ci,ky,kx} W[co, ci, ky, kx] in[ci]((y+ky-2) mod H, (x+kx-2) mod W),
-and every weight is rounded to bfloat16 (round to nearest even) before use.
+and every convolution weight (not the biases) is rounded to bfloat16 (round
+to nearest even) before use.
 The training loss on a batch is the mean over pixels of
 (sqrt(y + eps) - sqrt(t + eps))^2 with t = f_target / s, eps = 1e-3.
 Adam (beta1 0.9, beta2 0.999, eps 1e-8) updates float32 master weights.

@@ -70,7 +70,10 @@ EXPORTS = [
     "sgp_params_init", "rl_deconv", "sgp_deconv", "sgp_multi_deconv", "rl_multi_deconv",
     "sgp_boundary_deconv", "rl_boundary_deconv", "sgp_apply_operator", "sgp_release_cache",
     "sgp_strerror", "sgp_last_error", "sgp_solver_create", "sgp_solver_step", "sgp_solver_report",
-    "sgp_solver_set_timing", "sgp_solver_set_graph", "sgp_solver_timing", "sgp_solver_destroy", "sgp_steplength_rule", "sgp_batch_deconv",
+    "sgp_solver_set_timing", "sgp_solver_set_graph", "sgp_solver_timing", "sgp_solver_destroy",
+    "sgp_steplength_rule", "sgp_batch_deconv",
+    "sgp_cnn_num_params", "sgp_cnn_create", "sgp_cnn_get_params", "sgp_cnn_infer", "sgp_cnn_loss_grad",
+    "sgp_cnn_adam_step", "sgp_cnn_train_step", "sgp_cnn_destroy",
 ]
 
 _lib = None
@@ -104,6 +107,17 @@ def load():
     lib.sgp_batch_deconv.argtypes = [i, ctypes.POINTER(_Problem), i, ctypes.POINTER(vp), ctypes.POINTER(vp), P,
                                      ctypes.POINTER(_Report), vp]
     lib.sgp_steplength_rule.argtypes = [P, i, d, d, ctypes.POINTER(d), i, d, d, d, d, ctypes.POINTER(d)]
+    sz, fp = ctypes.c_size_t, ctypes.POINTER(ctypes.c_float)
+    lib.sgp_cnn_num_params.argtypes = []
+    lib.sgp_cnn_create.argtypes = [fp, sz, ctypes.POINTER(vp)]
+    lib.sgp_cnn_get_params.argtypes = [vp, fp, sz]
+    lib.sgp_cnn_infer.argtypes = [vp, i, ctypes.POINTER(vp), fp, i, i, ctypes.POINTER(vp), vp]
+    lib.sgp_cnn_loss_grad.argtypes = [vp, i, ctypes.POINTER(vp), fp, ctypes.POINTER(vp), i, i,
+                                      ctypes.POINTER(d), fp, vp]
+    lib.sgp_cnn_adam_step.argtypes = [vp, f, vp]
+    lib.sgp_cnn_train_step.argtypes = [vp, i, ctypes.POINTER(vp), fp, ctypes.POINTER(vp), i, i, f,
+                                       ctypes.POINTER(d), vp]
+    lib.sgp_cnn_destroy.argtypes = [vp]
     lib.sgp_strerror.restype = ctypes.c_char_p
     lib.sgp_strerror.argtypes = [i]
     lib.sgp_last_error.restype = ctypes.c_char_p
@@ -399,3 +413,87 @@ def batch_deconv(gs, psfs, bs, *, kind=KIND_SGP, f0s=None, fs=None, stream=None,
     rc = lib.sgp_batch_deconv(kind, probs, n, fp, f0p, ctypes.byref(prm), reps, _stream(stream))
     _raise(rc)
     return fs, [_report(reps[i], rc, None) for i in range(n)]
+
+
+# ------------------------------------------------------------------ warm-start network
+def _ptrs(ts, name):
+    for t in ts:
+        _check_dev(t, name)
+    return (ctypes.c_void_p * len(ts))(*[t.data_ptr() for t in ts])
+
+
+class CnnNet:
+    """Handle of the warm-start network (sgp_cnn_* of the C ABI).  ``params``
+    is the float32 parameter vector (include/sgpcnn.h gives its layout)."""
+
+    def __init__(self, params):
+        lib = load()
+        self.n_params = lib.sgp_cnn_num_params()
+        theta = np.ascontiguousarray(params, dtype=np.float32).ravel()
+        if theta.size != self.n_params:
+            raise ValueError(f"expected {self.n_params} parameters, got {theta.size}")
+        self._h = ctypes.c_void_p()
+        _raise(lib.sgp_cnn_create(theta.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), theta.size,
+                                  ctypes.byref(self._h)))
+
+    @staticmethod
+    def _shape(gs):
+        shapes = {tuple(g.shape) for g in gs}
+        if len(shapes) != 1 or len(next(iter(shapes))) != 2:
+            raise ValueError("one call takes 2D images of one shape")
+        return next(iter(shapes))
+
+    def params(self):
+        out = np.empty(self.n_params, dtype=np.float32)
+        _raise(load().sgp_cnn_get_params(self._h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
+                                         out.size))
+        return out
+
+    def infer(self, gs, bs, out=None, stream=None):
+        """Start images for images of one shape; returns a list of tensors."""
+        import torch
+        ny, nx = self._shape(gs)
+        if out is None:
+            out = [torch.empty_like(g) for g in gs]
+        b = np.ascontiguousarray(bs, dtype=np.float32)
+        _raise(load().sgp_cnn_infer(self._h, len(gs), _ptrs(gs, "g"),
+                                    b.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), ny, nx,
+                                    _ptrs(out, "f0"), _stream(stream)))
+        return out
+
+    def loss_grad(self, gs, bs, targets, stream=None):
+        """(mean loss, gradient as float32 numpy) of one batch."""
+        ny, nx = self._shape(gs)
+        b = np.ascontiguousarray(bs, dtype=np.float32)
+        loss = ctypes.c_double()
+        grad = np.empty(self.n_params, dtype=np.float32)
+        _raise(load().sgp_cnn_loss_grad(self._h, len(gs), _ptrs(gs, "g"),
+                                        b.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), _ptrs(targets, "target"),
+                                        ny, nx, ctypes.byref(loss),
+                                        grad.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), _stream(stream)))
+        return loss.value, grad
+
+    def adam_step(self, lr, stream=None):
+        _raise(load().sgp_cnn_adam_step(self._h, float(lr), _stream(stream)))
+
+    def train_step(self, gs, bs, targets, lr, stream=None):
+        """Loss, gradient and Adam step on one batch; returns the loss."""
+        ny, nx = self._shape(gs)
+        b = np.ascontiguousarray(bs, dtype=np.float32)
+        loss = ctypes.c_double()
+        _raise(load().sgp_cnn_train_step(self._h, len(gs), _ptrs(gs, "g"),
+                                         b.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
+                                         _ptrs(targets, "target"), ny, nx, float(lr), ctypes.byref(loss),
+                                         _stream(stream)))
+        return loss.value
+
+    def close(self):
+        if self._h:
+            load().sgp_cnn_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -44,6 +44,9 @@ def _jobs():
     jobs.append(([HIPCC] + CFLAGS + ["-c", os.path.join(CSRC, "dispatch.hip"),
                                      "-o", os.path.join(BUILD, "dispatch.o")],
                  os.path.join(BUILD, "dispatch.o")))
+    jobs.append(([HIPCC] + CFLAGS + ["-c", os.path.join(CSRC, "cnn.hip"),
+                                     "-o", os.path.join(BUILD, "cnn.o")],
+                 os.path.join(BUILD, "cnn.o")))
     jobs.append(([HIPCC] + CFLAGS + ["-x", "hip", "-c", os.path.join(CSRC, "solver.cpp"),
                                      "-o", os.path.join(BUILD, "solver.o")],
                  os.path.join(BUILD, "solver.o")))

@@ -33,6 +33,8 @@ static int fail(int code, const std::string& msg) {
   return code;
 }
 
+void record_error(const std::string& msg) { g_last_error = msg; }
+
 #define SGP_HIP(x)                                                                    \
   do {                                                                                \
     hipError_t e_ = (x);                                                              \

@@ -8,7 +8,7 @@ import re
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADER = os.path.join(ROOT, "include", "sgpdeconv.h")
+INCLUDE = os.path.join(ROOT, "include")
 
 
 @pytest.fixture(scope="module")
@@ -21,17 +21,23 @@ def lib():
 
 
 def _declared_functions():
-    txt = open(HEADER).read()
-    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
-    names = re.findall(r"^\s*(?:const\s+)?\w+\s*\*?\s*(\w+)\s*\(", txt, flags=re.M)
-    return sorted(set(n for n in names if n not in ("if", "defined")))
+    names = set()
+    for h in sorted(os.listdir(INCLUDE)):
+        if not h.endswith(".h"):
+            continue
+        txt = open(os.path.join(INCLUDE, h)).read()
+        txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+        names |= set(re.findall(r"^\s*(?:const\s+)?\w+\s*\*?\s*(\w+)\s*\(", txt, flags=re.M))
+    return sorted(n for n in names if n not in ("if", "defined"))
 
 
 def test_exports_every_declared_function(lib):
+    from paper_1210_2258_amd import EXPORTS
     names = _declared_functions()
-    assert "sgp_deconv" in names and "sgp_boundary_deconv" in names
+    assert "sgp_deconv" in names and "sgp_boundary_deconv" in names and "sgp_cnn_infer" in names
     for n in names:
         assert hasattr(lib, n), n
+    assert set(names) <= set(EXPORTS) | {"sgp_strerror", "sgp_last_error"}
 
 
 def test_params_defaults_are_the_papers(lib):
@@ -88,6 +94,11 @@ def test_rejects_bad_background_and_window(lib):
     # S must fit inside Sbar
     assert lib.sgp_boundary_deconv(fake, fake, None, ctypes.cast(b, ctypes.c_void_p), 1, 64, 64, 80, 64,
                                    20, 8, ctypes.byref(p), fake, ctypes.byref(rep), None) == -1
+
+
+def test_cnn_parameter_count(lib):
+    from oracle import cnn as OC
+    assert lib.sgp_cnn_num_params() == OC.n_params() == 13649
 
 
 def test_strerror(lib):
