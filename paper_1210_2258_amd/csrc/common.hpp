@@ -92,6 +92,7 @@ struct Args {
   const float* const* psftab; // [nbatch] PSF of each item
   const float* const* srctab; // [nbatch] user start of each item, or null
   const float* btab;          // [nbatch] constant background of each item
+  const int* zmap;            // [gridDim.z] item of each grid-z slice (null: slice = item)
   long long item_field;       // NY*NX: grad, d
   long long item_obs;         // p*ny*nx: Af, Ad
   long long item_spec;        // p*NY*NX/2: spec, khat

@@ -29,11 +29,12 @@ __device__ __forceinline__ long long sidx(int y, int kx, int NXh) {
   return ((long long)(y >> 3) * NXh + kx) * 8 + (y & 7);
 }
 
-// View of the arguments for item blockIdx.z of a batched launch.
+// View of the arguments for the item of grid-z slice blockIdx.z of a batched
+// launch (the slice map lets a launch cover only the items still running).
 __device__ __forceinline__ Args batch_view(const Args& in) {
   Args a = in;
   if (in.nbatch > 0) {
-    const int b = blockIdx.z;
+    const int b = in.zmap ? in.zmap[blockIdx.z] : (int)blockIdx.z;
     a.g = in.gtab[b];
     a.f = in.ftab[b];
     a.psf = in.psftab[b];

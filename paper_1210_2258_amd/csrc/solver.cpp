@@ -78,10 +78,11 @@ struct Plan {
   const float** psftab = nullptr;
   const float** srctab = nullptr;
   float* btab = nullptr;
+  int* zmap = nullptr;
 
   ~Plan() {
     void* ptrs[] = {grad, d, invw, Af, Ad, aux, spec, khat, knyq, tw_row, tw_col, part, counter, st, trace,
-                    (void*)gtab, (void*)ftab, (void*)psftab, (void*)srctab, btab};
+                    (void*)gtab, (void*)ftab, (void*)psftab, (void*)srctab, btab, zmap};
     for (void* q : ptrs)
       if (q) (void)hipFree(q);
     if (host_st) (void)hipHostFree(host_st);
@@ -137,6 +138,7 @@ static int make_plan(const PlanKey& key, hipStream_t s, std::unique_ptr<Plan>& p
     if ((rc = dalloc(&pl->psftab, n))) return rc;
     if ((rc = dalloc(&pl->srctab, n))) return rc;
     if ((rc = dalloc(&pl->btab, n))) return rc;
+    if ((rc = dalloc(&pl->zmap, n))) return rc;
   }
   SGP_HIP(hipHostMalloc((void**)&pl->host_st, sizeof(DevState) * n, hipHostMallocDefault));
   SGP_HIP(hipMemsetAsync(pl->counter, 0, sizeof(unsigned) * n, s));
@@ -814,37 +816,77 @@ static int batch_run(int kind, const sgp_problem* probs, int n, float* const* fo
     SGP_HIP(hipStreamWaitEvent(s0, ev[c], 0));
   }
   const int block = std::min(iters, 16);
+  const size_t ng = sol.size();
+  std::vector<char> live(ng, 1);  // groups with items still running
   hipGraph_t g = nullptr;
   hipGraphExec_t ge = nullptr;
-  SGP_HIP(hipStreamBeginCapture(s0, hipStreamCaptureModeThreadLocal));
-  SGP_HIP(hipEventRecord(ev[0], s0));
-  for (size_t c = 1; c < sol.size(); ++c) SGP_HIP(hipStreamWaitEvent(sol[c]->s, ev[0], 0));
-  for (auto& S : sol)
-    for (int b = 0; b < block; ++b) enqueue_iteration(S.get());
-  for (size_t c = 1; c < sol.size(); ++c) {
-    SGP_HIP(hipEventRecord(ev[sol.size() + c], sol[c]->s));
-    SGP_HIP(hipStreamWaitEvent(s0, ev[sol.size() + c], 0));
-  }
-  hipError_t ce = hipStreamEndCapture(s0, &g);
-  if (ce != hipSuccess) return fail(SGP_E_HIP, std::string("graph capture: ") + hipGetErrorString(ce));
-  SGP_HIP(hipGraphInstantiate(&ge, g, nullptr, nullptr, 0));
+  auto drop_graph = [&]() {
+    if (ge) (void)hipGraphExecDestroy(ge);
+    if (g) (void)hipGraphDestroy(g);
+    ge = nullptr;
+    g = nullptr;
+  };
+  // one block of iterations of every live group, as parallel branches
+  auto capture = [&]() -> int {
+    drop_graph();
+    SGP_HIP(hipStreamBeginCapture(s0, hipStreamCaptureModeThreadLocal));
+    SGP_HIP(hipEventRecord(ev[0], s0));
+    for (size_t c = 1; c < ng; ++c)
+      if (live[c]) SGP_HIP(hipStreamWaitEvent(sol[c]->s, ev[0], 0));
+    for (size_t c = 0; c < ng; ++c)
+      if (live[c])
+        for (int b = 0; b < block; ++b) enqueue_iteration(sol[c].get());
+    for (size_t c = 1; c < ng; ++c)
+      if (live[c]) {
+        SGP_HIP(hipEventRecord(ev[ng + c], sol[c]->s));
+        SGP_HIP(hipStreamWaitEvent(s0, ev[ng + c], 0));
+      }
+    hipError_t ce = hipStreamEndCapture(s0, &g);
+    if (ce != hipSuccess) return fail(SGP_E_HIP, std::string("graph capture: ") + hipGetErrorString(ce));
+    SGP_HIP(hipGraphInstantiate(&ge, g, nullptr, nullptr, 0));
+    return 0;
+  };
+  if ((rc = capture())) return rc;
   const int reps_n = (iters + block - 1) / block;
+  std::vector<int> act;
   for (int r = 0; r < reps_n; ++r) {
     SGP_HIP(hipGraphLaunch(ge, s0));
     if (r % 4 == 3 || r + 1 == reps_n) {  // stop once every item has stopped
       SGP_HIP(hipStreamSynchronize(s0));
-      bool done = true;
-      for (auto& S : sol) {
-        if ((rc = read_state(S.get()))) return rc;
-        done = done && all_done(S.get());
+      bool done = true, recapture = false;
+      for (size_t c = 0; c < ng; ++c) {
+        if (!live[c]) continue;
+        sgp_solver* S = sol[c].get();
+        if ((rc = read_state(S))) return rc;
+        act.clear();
+        for (int i = 0; i < S->nitems; ++i)
+          if (!S->pl->host_st[i].done) act.push_back(i);
+        if (act.empty()) {
+          live[c] = 0;
+          recapture = true;
+          continue;
+        }
+        done = false;
+        // once half of a group's launch covers stopped items, launch over the
+        // running ones only (grid z through the slice map)
+        if (S->nitems > 1 && 2 * (int)act.size() <= S->L.nz) {
+          SGP_HIP(hipMemcpy(S->pl->zmap, act.data(), sizeof(int) * act.size(), hipMemcpyHostToDevice));
+          S->L.base.zmap = S->pl->zmap;
+          S->L.nz = (int)act.size();
+          recapture = true;
+        }
       }
       if (done) break;
+      if (recapture && r + 1 < reps_n && (rc = capture())) return rc;
     }
   }
   SGP_HIP(hipStreamSynchronize(s0));
-  (void)hipGraphExecDestroy(ge);
-  (void)hipGraphDestroy(g);
+  drop_graph();
   for (auto& e : ev) (void)hipEventDestroy(e);
+  for (auto& S : sol) {  // reports see every item again
+    S->L.base.zmap = nullptr;
+    S->L.nz = S->nitems;
+  }
   int worst = SGP_OK;
   std::vector<sgp_report> tmp;
   for (size_t c = 0; c < sol.size(); ++c) {
