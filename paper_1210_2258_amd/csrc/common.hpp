@@ -65,7 +65,7 @@ struct Args {
   int jsel;              // op-specific image index
   const float* g;        // [p][ny][nx]
   const float* bmap;     // [p][ny][nx] or null
-  float b[kMaxP];        // constant backgrounds (used when bmap is null)
+  const float* bvec;     // [p] constant backgrounds in device memory (used when bmap is null)
   float* f;              // [NY][NX] iterate
   float* grad;           // [NY][NX]
   float* d;              // [NY][NX]
@@ -91,7 +91,6 @@ struct Args {
   float* const* ftab;         // [nbatch] iterate of each item
   const float* const* psftab; // [nbatch] PSF of each item
   const float* const* srctab; // [nbatch] user start of each item, or null
-  const float* btab;          // [nbatch] constant background of each item
   const int* zmap;            // [gridDim.z] item of each grid-z slice (null: slice = item)
   long long item_field;       // NY*NX: grad, d
   long long item_obs;         // p*ny*nx: Af, Ad

@@ -39,7 +39,7 @@ __device__ __forceinline__ Args batch_view(const Args& in) {
     a.f = in.ftab[b];
     a.psf = in.psftab[b];
     a.src = in.srctab ? in.srctab[b] : in.src;
-    a.b[0] = in.btab[b];
+    a.bvec = in.bvec + b;  // one image per item
     a.grad += b * in.item_field;
     a.d += b * in.item_field;
     a.Af += b * in.item_obs;
@@ -72,6 +72,11 @@ __host__ __device__ constexpr bool row_per_image(int op) {
   return op == ROW_PSF || op == ROW_STORE || op == ROW_RATIO || op == ROW_AD || op == ROW_UPD;
 }
 
+// Constant background of image j.  The values live in device memory: an
+// array inside Args indexed by j would put the kernel's copy of Args in
+// scratch memory.
+__device__ __forceinline__ float pick_b(const Args& a, int j) { return a.bvec[j]; }
+
 struct Pix {
   const Args& a;
   int j;
@@ -82,7 +87,7 @@ struct Pix {
   __device__ long long s_of(int y, int x) const {
     return (long long)j * a.ny * a.nx + (long long)(y - a.oy) * a.nx + (x - a.ox);
   }
-  __device__ float bg(long long s) const { return a.bmap ? a.bmap[s] : a.b[j]; }
+  __device__ float bg(long long s) const { return a.bmap ? a.bmap[s] : pick_b(a, j); }
   __device__ float w(long long pix) const { return a.invw ? a.invw[pix] : a.invw_s; }
 };
 

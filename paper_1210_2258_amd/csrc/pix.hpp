@@ -72,7 +72,7 @@ __global__ __launch_bounds__(kPixThreads) void pix_kernel(Args a_in) {
   } else if constexpr (OP == PIX_FLATSUM) {
     for (long long i = i0; i < a.p * nS; i += stride) {
       const int j = (int)(i / nS);
-      const float b = a.bmap ? a.bmap[i] : a.b[j];
+      const float b = a.bmap ? a.bmap[i] : pick_b(a, j);
       acc[0] += (double)a.g[i] - (double)b;
       acc[1] += (double)a.g[i];
     }
@@ -122,7 +122,7 @@ __global__ __launch_bounds__(kPixThreads) void pix_kernel(Args a_in) {
       const int j = (int)(i / nS);
       const float adv = a.Ad[i];
       const float g = a.g[i];
-      const float yv = fmaxf(a.Af[i] + (a.bmap ? a.bmap[i] : a.b[j]), 1e-30f);
+      const float yv = fmaxf(a.Af[i] + (a.bmap ? a.bmap[i] : pick_b(a, j)), 1e-30f);
 #pragma unroll
       for (int m = 0; m < NS; ++m) {
         if (m < n) acc[m] += armijo_term(g, yv, (float)st->lam_tab[m0 + m] * adv);

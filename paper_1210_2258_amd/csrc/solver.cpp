@@ -137,9 +137,9 @@ static int make_plan(const PlanKey& key, hipStream_t s, std::unique_ptr<Plan>& p
     if ((rc = dalloc(&pl->ftab, n))) return rc;
     if ((rc = dalloc(&pl->psftab, n))) return rc;
     if ((rc = dalloc(&pl->srctab, n))) return rc;
-    if ((rc = dalloc(&pl->btab, n))) return rc;
     if ((rc = dalloc(&pl->zmap, n))) return rc;
   }
+  if ((rc = dalloc(&pl->btab, std::max<size_t>(n, kMaxP)))) return rc;
   SGP_HIP(hipHostMalloc((void**)&pl->host_st, sizeof(DevState) * n, hipHostMallocDefault));
   SGP_HIP(hipMemsetAsync(pl->counter, 0, sizeof(unsigned) * n, s));
   launch_twiddle(pl->tw_row, key.NX, s);
@@ -722,7 +722,6 @@ static int create_items(int kind, const std::vector<Problem>& items, const std::
   Args& a = L.base;
   a.NY = pb.NY; a.NX = pb.NX; a.ny = pb.ny; a.nx = pb.nx; a.oy = pb.oy; a.ox = pb.ox; a.p = pb.p;
   a.g = pb.g; a.bmap = pb.bmap;
-  for (int j = 0; j < kMaxP; ++j) a.b[j] = pb.b[j];
   a.f = fs[0]; a.grad = pl->grad; a.d = pl->d;
   a.invw = pb.boundary ? pl->invw : nullptr;
   a.invw_s = 1.0f / (float)pb.p;
@@ -730,6 +729,8 @@ static int create_items(int kind, const std::vector<Problem>& items, const std::
   a.psf = pb.psf; a.aux = pl->aux; a.src = S->prm.f0;
   a.tw_row = pl->tw_row; a.tw_col = pl->tw_col;
   a.part = pl->part; a.counter = pl->counter; a.st = pl->st;
+  a.bvec = pl->btab;
+  if (n == 1) SGP_HIP(hipMemcpy(pl->btab, pb.b, sizeof(float) * pb.p, hipMemcpyHostToDevice));
   if (n > 1) {
     std::vector<const float*> gt(n), pt(n), st0(n);
     std::vector<float> bt(n);
@@ -749,7 +750,6 @@ static int create_items(int kind, const std::vector<Problem>& items, const std::
     a.ftab = pl->ftab;
     a.psftab = pl->psftab;
     a.srctab = pl->srctab;
-    a.btab = pl->btab;
     PlanKey k1 = key;
     k1.nitems = 1;
     a.item_field = (long long)pb.NY * pb.NX;
