@@ -9,7 +9,13 @@ stop (call to return, setup included), the roofline of the dominant kernel
 (from HIP events on the solver's stream), and the FP64 oracle timed on the
 host's cores on a bounded sample.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
+The heterogeneous batch (512 star fields of 128..1024 pixels a side) is
+deconvolved three ways with one stop rule (discrepancy, relative KL change
+as a backstop): one image at a time from the flat start (plain SGP), in one
+batched run from the flat start, and in one batched run from the learned
+warm start (network inference included in its time).
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-batch]
 """
 from __future__ import annotations
 
@@ -49,7 +55,77 @@ def parse():
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
                     help="also run a plain device copy of this many MiB (counter calibration)")
     ap.add_argument("--size", type=int, default=2048)
+    ap.add_argument("--no-batch", action="store_true", help="skip the heterogeneous batch legs")
+    ap.add_argument("--batch-images", type=int, default=512)
     return ap.parse_args()
+
+
+def _c4_item(i):
+    from synth import workloads as W
+    w = W.config4(n_images=1, purpose_base=i)[0]
+    return w.g[0], w.psf[0], float(w.b[0])
+
+
+def make_batch_inputs(n):
+    """The 512-image star-field batch, generated in worker processes that
+    fork before anything touches the GPU."""
+    import multiprocessing as mp
+    from concurrent.futures import ProcessPoolExecutor
+    with ProcessPoolExecutor(max_workers=min(16, os.cpu_count() or 4), mp_context=mp.get_context("fork")) as ex:
+        return list(ex.map(_c4_item, range(n), chunksize=8))
+
+
+def batch_legs(torch, m, items):
+    """Plain (one image at a time, flat start), flat batch and warm batch,
+    each timed from call to return with the inputs resident."""
+    import numpy as np
+    from paper_1210_2258_amd import warmstart as WS
+    gs = [torch.from_numpy(g).cuda() for g, _, _ in items]
+    ps = [torch.from_numpy(p).cuda() for _, p, _ in items]
+    bs = [b for _, _, b in items]
+    kw = dict(max_iter=3000, stop=m.STOP_DISCREPANCY | m.STOP_CONV, tol=1e-7)
+    net = WS.load_net()
+    # warm-up: workspaces of every shape and group size, network buffers
+    seen = {}
+    for i, g in enumerate(gs):
+        seen.setdefault(tuple(g.shape), i)
+    for i in seen.values():
+        m.sgp_deconv(gs[i], ps[i], bs[i], max_iter=2)
+    m.batch_deconv(gs, ps, bs, max_iter=1)
+    WS.infer_many(net, gs, bs)
+    torch.cuda.synchronize()
+
+    t0 = time.perf_counter()
+    plain = [m.sgp_deconv(gs[i], ps[i], bs[i], **kw)[1] for i in range(len(gs))]
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    _, flat = m.batch_deconv(gs, ps, bs, **kw)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    _, warm = WS.warm_batch_deconv(net, gs, ps, bs, **kw)
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
+    WS.infer_many(net, gs, bs)
+    torch.cuda.synchronize()
+    t4 = time.perf_counter()
+    net.close()
+
+    def summary(reps, secs):
+        it = np.array([r["iters"] for r in reps])
+        return {"seconds": secs, "iterations": int(it.sum()), "max_iterations": int(it.max()),
+                "reached_discrepancy": int(sum(r["reason"] == "discrepancy" for r in reps)),
+                "stopped_by_kl_change": int(sum(r["reason"] == "convergence" for r in reps)),
+                "mean_kl": float(np.mean([r["kl"] for r in reps])),
+                "mean_discrepancy": float(np.mean([r["discrepancy"] for r in reps]))}
+    out = {"images": len(gs), "pixels": int(sum(g.numel() for g in gs)),
+           "stop": "discrepancy <= 1, else relative KL change <= 1e-7, else 3000 iterations",
+           "plain": summary(plain, t1 - t0), "flat_batch": summary(flat, t2 - t1),
+           "warm_batch": summary(warm, t3 - t2), "network_inference_s": t4 - t3,
+           "warm_used_flat_fallback": int(sum(r["used_fallback"] for r in warm)),
+           "kl_ratio_warm_over_plain": float(np.mean([w["kl"] / p["kl"] for w, p in zip(warm, plain)]))}
+    out["speedup_warm_batch_vs_plain"] = out["plain"]["seconds"] / out["warm_batch"]["seconds"]
+    out["speedup_warm_batch_vs_flat_batch"] = out["flat_batch"]["seconds"] / out["warm_batch"]["seconds"]
+    return out
 
 
 def cpu_baseline(w, iters):
@@ -78,6 +154,7 @@ def main():
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
               "(the multi-GPU design is described in DESIGN.md, not built)", file=sys.stderr)
         sys.exit(2)
+    batch_items = None if args.no_batch else make_batch_inputs(args.batch_images)
     import numpy as np
     import torch
 
@@ -178,6 +255,8 @@ def main():
         "rl_time_to_discrepancy_s": ttd_rl,
         "rl_iters_to_discrepancy": rrep["iters"],
     }
+    if batch_items is not None:
+        out["batch_512"] = batch_legs(torch, m, batch_items)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_iters)
     print(json.dumps(out))

@@ -8,8 +8,8 @@ cut-out), and as targets the SGP reconstructions the library itself computes
 for them from the flat start, stopped by the discrepancy rule.  Training
 runs sgp_cnn_train_step (forward, backward and Adam kernels) on minibatches.
 
-    python -m paper_1210_2258_amd.train_warmstart [--pairs 20000] [--epochs 12]
-        [--batch 32] [--lr 1e-3] [--out paper_1210_2258_amd/warmstart_weights.npy]
+    python -m paper_1210_2258_amd.train_warmstart [--pairs 20000] [--epochs 40]
+        [--batch 32] [--lr 1.5e-3] [--out paper_1210_2258_amd/warmstart_weights.npy]
 
 Writes the float32 parameter vector (.npy) and a JSON record of the run
 beside it.
@@ -115,9 +115,9 @@ def train(net, g, b, tgt, idx_train, idx_val, epochs, batch, lr0, lr_min, seed):
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--pairs", type=int, default=20000)
-    ap.add_argument("--epochs", type=int, default=12)
+    ap.add_argument("--epochs", type=int, default=40)
     ap.add_argument("--batch", type=int, default=32)
-    ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--lr", type=float, default=1.5e-3)
     ap.add_argument("--lr-min", type=float, default=5e-5)
     ap.add_argument("--val-frac", type=float, default=0.05)
     ap.add_argument("--max-iter", type=int, default=1500)
