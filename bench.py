@@ -56,6 +56,7 @@ def parse():
                     help="also run a plain device copy of this many MiB (counter calibration)")
     ap.add_argument("--size", type=int, default=2048)
     ap.add_argument("--no-batch", action="store_true", help="skip the heterogeneous batch legs")
+    ap.add_argument("--no-ttd", action="store_true", help="skip the time-to-discrepancy runs")
     ap.add_argument("--batch-images", type=int, default=512)
     return ap.parse_args()
 
@@ -128,6 +129,53 @@ def batch_legs(torch, m, items):
     return out
 
 
+def time_to_discrepancy(torch, m, g, psf, b):
+    """SGP and RL to the discrepancy stop, call to return, setup included."""
+    f_out = torch.empty_like(g)
+    m.sgp_deconv(g, psf, b, f=f_out, max_iter=10, stop=m.STOP_FIXED)  # warm the plan cache
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    f_out, drep = m.sgp_deconv(g, psf, b, f=f_out, max_iter=5000, stop=m.STOP_DISCREPANCY)
+    torch.cuda.synchronize()
+    ttd = time.perf_counter() - t2
+    t3 = time.perf_counter()
+    f_rl, rrep = m.rl_deconv(g, psf, b, max_iter=20000, stop=m.STOP_DISCREPANCY)
+    torch.cuda.synchronize()
+    ttd_rl = time.perf_counter() - t3
+    return {"time_to_discrepancy_s": ttd, "iters_to_discrepancy": drep["iters"],
+            "discrepancy_final": drep["discrepancy"], "kl_final": drep["kl"],
+            "rl_time_to_discrepancy_s": ttd_rl, "rl_iters_to_discrepancy": rrep["iters"]}
+
+
+COUNTER_FILE = os.path.join(ROOT, "profiles", "sgp_2048_hbm_counters.md")
+KERNEL_SOURCES = ("common.hpp", "fft.hpp", "reduce.hpp", "finalize.hpp", "kernels.hpp", "pix.hpp",
+                  "inst.hip", "dispatch.hip")
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_1210_2258_amd", "csrc", name), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def counter_traffic(kernel, npx):
+    """HBM bytes per launch of `kernel` from the committed counter summary
+    (FETCH_SIZE + WRITE_SIZE, calibrated on a plain copy), or None when the
+    kernel sources changed since the counters were taken."""
+    try:
+        txt = open(COUNTER_FILE).read()
+        rec = json.loads(txt.split("```json")[1].split("```")[0])
+    except (OSError, IndexError, ValueError):
+        return None
+    if rec.get("source_hash") != kernel_source_hash() or rec.get("pixels") != npx:
+        return None
+    k = rec.get("kernels", {}).get(kernel)
+    return None if k is None else k["traffic_bytes"]
+
+
 def cpu_baseline(w, iters):
     """The FP64 oracle on the host: s/iteration from SGP runs with 0 and
     `iters` iterations (setup cancels)."""
@@ -174,13 +222,14 @@ def main():
     torch.cuda.synchronize()
 
     if args.copy_calib:
-        # a plain copy of known size: FETCH_SIZE / WRITE_SIZE of this dispatch
-        # give the counters' scale for the solver kernels
+        # a plain copy of known size (an elementwise multiply by one, so the
+        # dispatch has a name of its own): FETCH_SIZE / WRITE_SIZE of this
+        # dispatch give the counters' scale for the solver kernels
         n = args.copy_calib * (1 << 20) // 4
         src = torch.ones(n, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
         for _ in range(3):
-            dst.copy_(src)
+            torch.mul(src, 1.0, out=dst)
         torch.cuda.synchronize()
         del src, dst
 
@@ -211,19 +260,11 @@ def main():
     iter_ms_events = sum(v[2] for v in kern.values()) / 8
     iter_roofline = ITER_BYTES_PER_PX * npx / (ms_per_step * 1e-3) / 1e9
 
-    # ---- time to discrepancy (call to return, setup included)
-    f_out = torch.empty_like(g)
-    m.sgp_deconv(g, psf, b, f=f_out, max_iter=10, stop=m.STOP_FIXED)  # warm the plan cache
-    torch.cuda.synchronize()
-    t2 = time.perf_counter()
-    f_out, drep = m.sgp_deconv(g, psf, b, f=f_out, max_iter=5000, stop=m.STOP_DISCREPANCY)
-    torch.cuda.synchronize()
-    ttd = time.perf_counter() - t2
-    t3 = time.perf_counter()
-    f_rl, rrep = m.rl_deconv(g, psf, b, max_iter=20000, stop=m.STOP_DISCREPANCY)
-    torch.cuda.synchronize()
-    ttd_rl = time.perf_counter() - t3
-
+    out_ttd = {}
+    if not args.no_ttd:
+        out_ttd = time_to_discrepancy(torch, m, g, psf, b)
+    traffic = counter_traffic(dom, npx)
+    
     out = {
         "metric": METRIC,
         "value": its,
@@ -242,18 +283,13 @@ def main():
                                "with RL scaling, FP64 reductions",
                    "image": [ny, nx], "images_per_step": 1, "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": dom,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": dom,
                      "avg_ms": avg_ms, "bytes_per_launch": BYTES_PER_PX[dom] * npx},
         "iteration_roofline": {"bytes_per_iter": ITER_BYTES_PER_PX * npx, "achieved_GBs": iter_roofline,
                                "frac": iter_roofline / HBM_PEAK_GBS},
         "kernels_ms": {k: v[0] for k, v in kern.items()},
         "iteration_ms_events": iter_ms_events,
-        "time_to_discrepancy_s": ttd,
-        "iters_to_discrepancy": drep["iters"],
-        "discrepancy_final": drep["discrepancy"],
-        "kl_final": drep["kl"],
-        "rl_time_to_discrepancy_s": ttd_rl,
-        "rl_iters_to_discrepancy": rrep["iters"],
+        **out_ttd,
     }
     if batch_items is not None:
         out["batch_512"] = batch_legs(torch, m, batch_items)
