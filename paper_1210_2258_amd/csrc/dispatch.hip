@@ -101,6 +101,19 @@ void launch_pix(int op, dim3 grid, const Args& a, hipStream_t s) {
   }
 }
 
+bool row_fin_deferred(int op) { return row_deferred_fin(op); }
+
+void launch_row_fin(int op, int nz, const Args& a, hipStream_t s) {
+  const dim3 grid(1, 1, nz), blk(kFinThreads);
+  switch (op) {
+    case ROW_DIR: hipLaunchKernelGGL((row_fin_kernel<ROW_DIR>), grid, blk, 0, s, a); break;
+    case ROW_AD: hipLaunchKernelGGL((row_fin_kernel<ROW_AD>), grid, blk, 0, s, a); break;
+    case ROW_UPD: hipLaunchKernelGGL((row_fin_kernel<ROW_UPD>), grid, blk, 0, s, a); break;
+    case ROW_GRAD: hipLaunchKernelGGL((row_fin_kernel<ROW_GRAD>), grid, blk, 0, s, a); break;
+    default: break;
+  }
+}
+
 void launch_resume(DevState* st, int n, int nitems, hipStream_t s) {
   hipLaunchKernelGGL(resume_kernel, dim3((nitems + 63) / 64), dim3(64), 0, s, st, n, nitems);
 }

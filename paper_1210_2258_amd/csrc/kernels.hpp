@@ -67,6 +67,13 @@ __host__ __device__ constexpr int row_nslots(int op) {
   return op == ROW_RATIO ? 1 : op == ROW_SETUPGRAD ? 2 : op == ROW_DIR ? 1 :
          op == ROW_AD ? 2 : op == ROW_UPD ? 1 : op == ROW_GRAD ? 4 : 0;
 }
+// Iteration kernels whose reduction is finished by a separate one-workgroup
+// launch (row_fin_kernel) instead of the last workgroup: the last-workgroup
+// pattern needs a device-scope release in every workgroup, which writes back
+// the whole L2 of its XCD before the workgroup may retire.
+__host__ __device__ constexpr bool row_deferred_fin(int op) {
+  return op == ROW_DIR || op == ROW_AD || op == ROW_UPD || op == ROW_GRAD;
+}
 // image index of the spectrum read / written
 __host__ __device__ constexpr bool row_per_image(int op) {
   return op == ROW_PSF || op == ROW_STORE || op == ROW_RATIO || op == ROW_AD || op == ROW_UPD;
@@ -118,44 +125,139 @@ __device__ __forceinline__ double armijo_term(float g, float y, float t) {
   return (double)((y - g) * x) + (double)(g * h_x(x));
 }
 
+// Solver scalars a row kernel uses, read once per workgroup (the kernel's
+// global stores could otherwise force them to be re-read at every pixel).
+struct RowScal {
+  float alpha, L1, L2, lam, lam0, lam1;
+  double lamd, mu, psf_scale;
+  int flux;
+};
+
+template <int OP>
+__device__ __forceinline__ RowScal row_scalars(const DevState* st, int j) {
+  RowScal c{};
+  if constexpr (OP == ROW_PSF) c.psf_scale = st->psf_scale[j];
+  if constexpr (OP == ROW_DIR || OP == ROW_GRAD) {
+    c.L1 = (float)st->L1;
+    c.L2 = (float)st->L2;
+  }
+  if constexpr (OP == ROW_DIR) {
+    c.alpha = (float)st->alpha;
+    c.flux = st->flux_constraint;
+    c.mu = st->mu;
+  }
+  if constexpr (OP == ROW_AD) {
+    c.lam0 = (float)st->lam_tab[0];
+    c.lam1 = (float)st->lam_tab[1];
+  }
+  if constexpr (OP == ROW_UPD) c.lam = (float)st->lam;
+  if constexpr (OP == ROW_GRAD) c.lamd = st->lam;
+  return c;
+}
+
+// Units per load chunk: the largest divisor of nu not above 8.
+__host__ __device__ constexpr int row_chunk(int nu) {
+  int c = nu < 8 ? nu : 8;
+  while (nu % c) --c;
+  return c;
+}
+
+// Global inputs of one pixel of the pointwise stage, loaded ahead of the
+// pixel's arithmetic and stores so that a thread has all its loads in flight
+// at once.
+struct RowIn {
+  float c[6];
+};
+
+template <int OP>
+__device__ __forceinline__ RowIn row_load(const Args& a, int j, int y, int x) {
+  Pix P(a, j);
+  const long long pix = (long long)y * a.NX + x;
+  RowIn in{};
+  if constexpr (OP == ROW_PSF) {
+    // K0 = ifftshift(K): K0[y][x] = K[(y + NY/2) % NY][(x + NX/2) % NX]
+    const int ys = (y + a.NY / 2) % a.NY, xs = (x + a.NX / 2) % a.NX;
+    in.c[0] = a.psf[(long long)j * a.NY * a.NX + (long long)ys * a.NX + xs];
+  } else if constexpr (OP == ROW_FIELD) {
+    in.c[0] = a.src[pix];
+  } else if constexpr (OP == ROW_RATIO) {
+    if (P.inS(y, x)) {
+      const long long s = P.s_of(y, x);
+      in.c[0] = a.g[s];
+      in.c[1] = P.bg(s);
+    }
+  } else if constexpr (OP == ROW_RLUPD || OP == ROW_SETUPGRAD) {
+    in.c[0] = P.w(pix);
+    in.c[1] = a.f[pix];
+  } else if constexpr (OP == ROW_DIR) {
+    in.c[0] = a.f[pix];
+    in.c[1] = a.grad[pix];
+    in.c[2] = P.w(pix);
+  } else if constexpr (OP == ROW_AD) {
+    if (P.inS(y, x)) {
+      const long long s = P.s_of(y, x);
+      in.c[0] = a.g[s];
+      in.c[1] = a.Af[s];
+      in.c[2] = P.bg(s);
+    }
+  } else if constexpr (OP == ROW_UPD) {
+    if (j == 0) {
+      in.c[0] = a.f[pix];
+      in.c[1] = a.d[pix];
+    }
+    if (P.inS(y, x)) {
+      const long long s = P.s_of(y, x);
+      in.c[2] = a.Af[s];
+      in.c[3] = a.Ad[s];
+      in.c[4] = a.g[s];
+      in.c[5] = P.bg(s);
+    }
+  } else if constexpr (OP == ROW_GRAD) {
+    in.c[0] = P.w(pix);
+    in.c[1] = a.grad[pix];
+    in.c[2] = a.d[pix];
+    in.c[3] = a.f[pix];
+  }
+  return in;
+}
+
 // One pixel of the pointwise stage.  v: result of the inverse transform at
-// this pixel (conv / corr value); returns the value fed to the forward
-// transform.  acc: per-thread FP64 accumulators.
+// this pixel (conv / corr value); in: the pixel's loaded inputs; returns the
+// value fed to the forward transform.  acc: per-thread FP64 accumulators.
 template <int OP, int NS>
-__device__ __forceinline__ float row_point(const Args& a, const DevState* st, int j, int y, int x,
-                                           float v, double (&acc)[NS > 0 ? NS : 1]) {
+__device__ __forceinline__ float row_point(const Args& a, const RowScal& sc, int j, int y, int x, float v,
+                                           const RowIn& in, double (&acc)[NS > 0 ? NS : 1]) {
   Pix P(a, j);
   const long long pix = (long long)y * a.NX + x;
   if constexpr (OP == ROW_PSF) {
-    // K0 = ifftshift(K): K0[y][x] = K[(y + NY/2) % NY][(x + NX/2) % NX], scaled by 1/(sum NY NX)
-    const int ys = (y + a.NY / 2) % a.NY, xs = (x + a.NX / 2) % a.NX;
-    return (float)((double)a.psf[(long long)j * a.NY * a.NX + (long long)ys * a.NX + xs] * st->psf_scale[j]);
+    // scaled by 1 / (sum NY NX)
+    return (float)((double)in.c[0] * sc.psf_scale);
   } else if constexpr (OP == ROW_MASKS) {
     return P.inS(y, x) ? 1.f : 0.f;
   } else if constexpr (OP == ROW_STORE) {
     a.aux[(long long)j * a.NY * a.NX + pix] = v;
     return 0.f;
   } else if constexpr (OP == ROW_FIELD) {
-    return a.src[pix];
+    return in.c[0];
   } else if constexpr (OP == ROW_RATIO) {
     if (!P.inS(y, x)) return 0.f;
     const long long s = P.s_of(y, x);
     if (a.flag & 1) a.Af[s] = v;
-    const float g = a.g[s];
-    const float yv = fmaxf(v + P.bg(s), 1e-30f);
+    const float g = in.c[0];
+    const float yv = fmaxf(v + in.c[1], 1e-30f);
     acc[0] += kl_term(g, yv);
     return (g - yv) / yv;
   } else if constexpr (OP == ROW_RLUPD) {
-    const float w = P.w(pix);
-    const float f = a.f[pix];
+    const float w = in.c[0];
+    const float f = in.c[1];
     const float fn = w > 0.f ? fmaxf(0.f, f * (1.f + w * v)) : 0.f;
     a.f[pix] = fn;
     return fn;
   } else if constexpr (OP == ROW_SETUPGRAD) {
-    const float w = P.w(pix);
+    const float w = in.c[0];
     const float mr = w > 0.f ? 1.f : 0.f;
     a.grad[pix] = -mr * v;
-    const float yr = w > 0.f ? a.f[pix] * (1.f + w * v) : 0.f;  // one RL step from f0
+    const float yr = w > 0.f ? in.c[1] * (1.f + w * v) : 0.f;  // one RL step from f0
     // bounds from the observed window S (equal to R for periodic problems)
     if (yr > 0.f && P.inS(y, x)) {
       acc[0] = fmin(acc[0], (double)yr);
@@ -163,12 +265,11 @@ __device__ __forceinline__ float row_point(const Args& a, const DevState* st, in
     }
     return 0.f;
   } else if constexpr (OP == ROW_DIR) {
-    const float f = a.f[pix], gr = a.grad[pix];
-    const float D = P.w(pix) * fminf((float)st->L2, fmaxf((float)st->L1, f));
-    const float z = f - (float)st->alpha * D * gr;
+    const float f = in.c[0], gr = in.c[1];
+    const float D = in.c[2] * fminf(sc.L2, fmaxf(sc.L1, f));
+    const float z = f - sc.alpha * D * gr;
     // projection onto f >= 0, or with the flux constraint onto {f >= 0, sum f = c}
-    const float dd = (st->flux_constraint && D > 0.f ? (float)fmax(0.0, (double)z - st->mu * (double)D)
-                                                    : fmaxf(0.f, z)) - f;
+    const float dd = (sc.flux && D > 0.f ? (float)fmax(0.0, (double)z - sc.mu * (double)D) : fmaxf(0.f, z)) - f;
     a.d[pix] = dd;
     acc[0] += (double)gr * (double)dd;
     return dd;
@@ -176,39 +277,37 @@ __device__ __forceinline__ float row_point(const Args& a, const DevState* st, in
     if (!P.inS(y, x)) return 0.f;
     const long long s = P.s_of(y, x);
     a.Ad[s] = v;
-    const float g = a.g[s];
-    const float yv = fmaxf(a.Af[s] + P.bg(s), 1e-30f);
-#pragma unroll
-    for (int m = 0; m < 2; ++m) acc[m] += armijo_term(g, yv, (float)st->lam_tab[m] * v);
+    const float g = in.c[0];
+    const float yv = fmaxf(in.c[1] + in.c[2], 1e-30f);
+    acc[0] += armijo_term(g, yv, sc.lam0 * v);
+    acc[1] += armijo_term(g, yv, sc.lam1 * v);
     return 0.f;
   } else if constexpr (OP == ROW_UPD) {
     // f += lam d, A_j f += lam A_j d; feeds delta rho_j = g/y_new - g/y_old
     // = -g lam A_j d / (y_old y_new) to the transform (no cancellation), so
     // the adjoint directly yields z = grad_new - grad_old
-    const float lam = (float)st->lam;
-    if (j == 0) a.f[pix] = a.f[pix] + lam * a.d[pix];
+    const float lam = sc.lam;
+    if (j == 0) a.f[pix] = in.c[0] + lam * in.c[1];
     if (!P.inS(y, x)) return 0.f;
     const long long s = P.s_of(y, x);
-    const float bgv = P.bg(s);
-    const float afo = a.Af[s];
-    const float step = lam * a.Ad[s];
+    const float bgv = in.c[5];
+    const float afo = in.c[2];
+    const float step = lam * in.c[3];
     const float afn = afo + step;
     a.Af[s] = afn;
-    const float g = a.g[s];
+    const float g = in.c[4];
     const float yo = fmaxf(afo + bgv, 1e-30f);
     const float yn = fmaxf(afn + bgv, 1e-30f);
     acc[0] += kl_term(g, yn);
     return g > 0.f ? -g * step / (yo * yn) : 0.f;
   } else if constexpr (OP == ROW_GRAD) {
     // v = sum_j A_j^T delta rho_j, so z = grad_new - grad_old = -M_R v
-    const float w = P.w(pix);
+    const float w = in.c[0];
     const float zf = w > 0.f ? -v : 0.f;
-    const float go = a.grad[pix];
-    a.grad[pix] = go + zf;
-    const double s = (double)st->lam * (double)a.d[pix];
+    a.grad[pix] = in.c[1] + zf;
+    const double s = sc.lamd * (double)in.c[2];
     const double z = (double)zf;
-    const float fp = a.f[pix];
-    const double D = (double)(w * fminf((float)st->L2, fmaxf((float)st->L1, fp)));
+    const double D = (double)(w * fminf(sc.L2, fmaxf(sc.L1, in.c[3])));
     if (D > 0) {
       acc[0] += s * s / (D * D);
       acc[1] += s * z / D;
@@ -325,18 +424,39 @@ __global__ __launch_bounds__(RowCfg<L>::NT) void row_kernel(Args a_in) {
     fft_lds<L>(buf[tid / TF], tid % TF, tw);
   }
 
+  // pointwise stage in chunks of CH units per thread: every load of a chunk
+  // is issued before the chunk's arithmetic and stores
+  {
+    const RowScal sc = row_scalars<OP>(st, j);
+    constexpr int NU = RP * L / NT;  // units (pixel pairs) per thread
+    static_assert(NU * NT == RP * L, "threads must tile the rows");
+    constexpr int CH = row_chunk(NU);
+    static_assert(NU % CH == 0, "chunks must tile the units");
 #pragma unroll
-  for (int u = tid; u < RP * L; u += NT) {
-    const int q = u / L, x = u % L;
-    const int ya = y0 + 2 * q;
-    float2 v = make_float2(0.f, 0.f);
-    if constexpr (row_has_inv(OP)) {
-      const float2 w = buf[q][lds_idx<L>(x)];
-      v = make_float2(w.x, -w.y);
+    for (int c0 = 0; c0 < NU; c0 += CH) {
+      RowIn in[CH][2];
+#pragma unroll
+      for (int c = 0; c < CH; ++c) {
+        const int u = tid + (c0 + c) * NT;
+        const int q = u / L, x = u % L;
+        in[c][0] = row_load<OP>(a, j, y0 + 2 * q, x);
+        in[c][1] = row_load<OP>(a, j, y0 + 2 * q + 1, x);
+      }
+#pragma unroll
+      for (int c = 0; c < CH; ++c) {
+        const int u = tid + (c0 + c) * NT;
+        const int q = u / L, x = u % L;
+        const int ya = y0 + 2 * q;
+        float2 v = make_float2(0.f, 0.f);
+        if constexpr (row_has_inv(OP)) {
+          const float2 w = buf[q][lds_idx<L>(x)];
+          v = make_float2(w.x, -w.y);
+        }
+        const float ua = row_point<OP, NS>(a, sc, j, ya, x, v.x, in[c][0], acc);
+        const float ub = row_point<OP, NS>(a, sc, j, ya + 1, x, v.y, in[c][1], acc);
+        if constexpr (row_has_fwd(OP)) buf[q][lds_idx<L>(x)] = make_float2(ua, ub);
+      }
     }
-    const float ua = row_point<OP, NS>(a, st, j, ya, x, v.x, acc);
-    const float ub = row_point<OP, NS>(a, st, j, ya + 1, x, v.y, acc);
-    if constexpr (row_has_fwd(OP)) buf[q][lds_idx<L>(x)] = make_float2(ua, ub);
   }
 
   if constexpr (row_has_fwd(OP)) {
@@ -361,10 +481,14 @@ __global__ __launch_bounds__(RowCfg<L>::NT) void row_kernel(Args a_in) {
   }
 
   if constexpr (NS > 0) {
-    double tot[NS];
     const int bid = blockIdx.y * gridDim.x + blockIdx.x;
-    if (grid_reduce<NT, NS>(acc, RowKinds{OP}, a.part, a.counter, a.nblk, bid, tot))
-      row_finalize<OP>(st, a, tot);
+    if constexpr (row_deferred_fin(OP)) {
+      block_partials<NT, NS>(acc, RowKinds{OP}, a.part, a.nblk, bid);
+    } else {
+      double tot[NS];
+      if (grid_reduce<NT, NS>(acc, RowKinds{OP}, a.part, a.counter, a.nblk, bid, tot))
+        row_finalize<OP>(st, a, tot);
+    }
   }
 }
 

@@ -194,6 +194,21 @@ __global__ __launch_bounds__(kPixThreads) void pix_kernel(Args a_in) {
   }
 }
 
+// Second stage of the reduction of a row iteration kernel (row_deferred_fin):
+// one workgroup per item sums the partials in a fixed order and runs the
+// kernel's finaliser.
+constexpr int kFinThreads = 256;
+template <int OP>
+__global__ __launch_bounds__(kFinThreads) void row_fin_kernel(Args a_in) {
+  const Args a = batch_view(a_in);
+  DevState* st = a.st;
+  if (a.iter && (st->done || st->pause)) return;
+  constexpr int NS = row_nslots(OP);
+  double tot[NS];
+  sum_partials<kFinThreads, NS>(RowKinds{OP}, a.part, a.nblk, tot);
+  if (threadIdx.x == 0) row_finalize<OP>(st, a, tot);
+}
+
 // Starts a stepping call of n iterations.
 __global__ void resume_kernel(DevState* st, int n, int nitems) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;

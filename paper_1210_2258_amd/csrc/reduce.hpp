@@ -89,4 +89,61 @@ __device__ bool grid_reduce(double (&acc)[NS], Kinds kinds, double* part, unsign
   return false;
 }
 
+// First stage only: thread 0 of each workgroup writes the workgroup's partial
+// of every slot.  No cross-workgroup synchronisation: a later launch sums the
+// partials (sum_partials), the kernel boundary making them visible.
+template <int NT, int NS, class Kinds>
+__device__ void block_partials(double (&acc)[NS], Kinds kinds, double* part, int nblk, int bid) {
+  constexpr int NW = NT < 64 ? 1 : NT / 64;
+  __shared__ double sh[NS][NW];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+#pragma unroll
+  for (int s = 0; s < NS; ++s) {
+    double v = wave_reduce<NT>(kinds(s), acc[s]);
+    if (lane == 0) sh[s][wave] = v;
+  }
+  __syncthreads();
+  if (tid == 0) {
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+      double v = sh[s][0];
+      for (int w = 1; w < NW; ++w) v = red_combine(kinds(s), v, sh[s][w]);
+      part[(size_t)s * nblk + bid] = v;
+    }
+  }
+}
+
+// Second stage in one workgroup of NT threads: the totals of nblk partials
+// per slot, summed in a fixed order.  Must be called by every thread; tot is
+// valid in thread 0.
+template <int NT, int NS, class Kinds>
+__device__ void sum_partials(Kinds kinds, const double* part, int nblk, double (&tot)[NS]) {
+  constexpr int NW = NT < 64 ? 1 : NT / 64;
+  __shared__ double sh[NS][NW];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  double loc[NS];
+#pragma unroll
+  for (int s = 0; s < NS; ++s) loc[s] = red_identity(kinds(s));
+  for (int i = tid; i < nblk; i += NT) {
+#pragma unroll
+    for (int s = 0; s < NS; ++s) loc[s] = red_combine(kinds(s), loc[s], part[(size_t)s * nblk + i]);
+  }
+#pragma unroll
+  for (int s = 0; s < NS; ++s) {
+    double v = wave_reduce<NT>(kinds(s), loc[s]);
+    if (lane == 0) sh[s][wave] = v;
+  }
+  __syncthreads();
+  if (tid == 0) {
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+      double v = sh[s][0];
+      for (int w = 1; w < NW; ++w) v = red_combine(kinds(s), v, sh[s][w]);
+      tot[s] = v;
+    }
+  }
+}
+
 }  // namespace sgp

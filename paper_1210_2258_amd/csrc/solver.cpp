@@ -292,6 +292,7 @@ struct Launcher {
     hipEvent_t e0 = nullptr;
     begin(cls, e0);
     launch_row(NX, op, dim3(gx, jc, nz), a, s);
+    if (row_fin_deferred(op)) launch_row_fin(op, nz, a, s);
     end(cls, e0);
   }
   void col(int mode, int conj, int jc, int iter, int cls = -1) {
