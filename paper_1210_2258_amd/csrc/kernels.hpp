@@ -98,16 +98,20 @@ struct Pix {
   __device__ float w(long long pix) const { return a.invw ? a.invw[pix] : a.invw_s; }
 };
 
-// h(x) = x - log1p(x) for x > -1 without cancellation: the alternating
-// series x^2 (1/2 - x/3 + x^2/4 - ...) for |x| < 1/2 (24 terms, truncation
-// below 5e-9 relative), x - log1p(x) otherwise (relative error below 3e-7
-// there since |log1p(x)| < 4 h(x) for |x| >= 1/2).
+// h(x) = x - log1p(x) for x > -1 without cancellation.  For |x| < 1/2, with
+// u = x / (2 + x): log1p(x) = 2 atanh(u) and x - 2u = x u, so
+// h(x) = x u - 2 u^3 (1/3 + u^2/5 + u^4/7 + ...); |u| <= 1/3, and the
+// series stops at u^16 / 19 (truncation below 1e-10 relative).  Elsewhere
+// x - log1p(x) (relative error below 3e-7 there since |log1p(x)| < 4 h(x)
+// for |x| >= 1/2).
 __device__ __forceinline__ float h_x(float x) {
   if (fabsf(x) < 0.5f) {
-    float q = 1.0f / 25.0f;
+    const float u = x * __builtin_amdgcn_rcpf(2.f + x);
+    const float u2 = u * u;
+    float q = 1.f / 19.f;
 #pragma unroll
-    for (int k = 24; k >= 2; --k) q = 1.0f / (float)k - x * q;
-    return x * x * q;
+    for (int k = 17; k >= 3; k -= 2) q = 1.f / (float)k + u2 * q;
+    return x * u - 2.f * u * u2 * q;
   }
   return x - log1pf(x);
 }
@@ -309,8 +313,9 @@ __device__ __forceinline__ float row_point(const Args& a, const RowScal& sc, int
     const double z = (double)zf;
     const double D = (double)(w * fminf(sc.L2, fmaxf(sc.L1, in.c[3])));
     if (D > 0) {
-      acc[0] += s * s / (D * D);
-      acc[1] += s * z / D;
+      const double sd = s / D;
+      acc[0] += sd * sd;
+      acc[1] += sd * z;
       acc[2] += s * z * D;
       acc[3] += z * z * D * D;
     }
@@ -566,6 +571,13 @@ __global__ __launch_bounds__(ColCfg<LY>::NT) void col_kernel(Args a_in) {
     }
   } else if constexpr (MODE == COL_CONV) {
     load(a.spec);
+    float2 kpre[E];  // transfer function of image 0, fetched while the spectrum is transformed
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      int c, y; long long off;
+      unit(e, c, y, off);
+      kpre[e] = (kx0 + c < NXh) ? a.khat[off] : make_float2(0.f, 0.f);
+    }
     __syncthreads();
     fft_lds<LY>(buf[tid / TF], tid % TF, tw);
     float2 x0[E], x1[E];  // spectrum (or its even / odd parts for column 0)
@@ -595,7 +607,7 @@ __global__ __launch_bounds__(ColCfg<LY>::NT) void col_kernel(Args a_in) {
         unit(e, c, y, off);
         float2 pr = make_float2(0.f, 0.f);
         if (kx0 + c < NXh) {
-          const float2 kv = K[off];
+          const float2 kv = jo == 0 ? kpre[e] : K[off];
           if (has_col0 && c == 0) {
             const float2 kn = KN[y];
             const float2 p0 = CONJ ? cmulc(x0[e], kv) : cmul(x0[e], kv);
@@ -626,17 +638,24 @@ __global__ __launch_bounds__(ColCfg<LY>::NT) void col_kernel(Args a_in) {
       int lane = tid % TF;
       asm volatile("" : "+v"(lane));  // keeps per-pass address arithmetic inside the loop
       load(a.spec + ji * sstride);
-      __syncthreads();
-      fft_lds<LY>(buf[tid / TF], lane, tw);
       const float2* K = a.khat + ji * sstride;
       const float2* KN = a.knyq + (long long)ji * LY;
+      float2 kpre[E];
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        int c, y; long long off;
+        unit(e, c, y, off);
+        kpre[e] = (kx0 + c < NXh) ? K[off] : make_float2(0.f, 0.f);
+      }
+      __syncthreads();
+      fft_lds<LY>(buf[tid / TF], lane, tw);
 #pragma unroll
       for (int e = 0; e < E; ++e) {
         int c, y; long long off;
         unit(e, c, y, off);
         if (kx0 + c >= NXh) continue;
         const float2 v = buf[c][lds_idx<LY>(y)];
-        const float2 kv = K[off];
+        const float2 kv = kpre[e];
         if (has_col0 && c == 0) {
           const float2 m = cconj(buf[0][lds_idx<LY>((LY - y) % LY)]);
           const float2 ev = cscale(cadd(v, m), 0.5f);
