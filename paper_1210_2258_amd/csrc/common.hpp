@@ -92,6 +92,10 @@ struct Args {
   const float* const* psftab; // [nbatch] PSF of each item
   const float* const* srctab; // [nbatch] user start of each item, or null
   const int* zmap;            // [gridDim.z] item of each grid-z slice (null: slice = item)
+  // deferred second reduction stage: 1 + the row op whose partials (fin_nblk
+  // workgroups) this launch finalises first (0: none)
+  int fin_op;
+  int fin_nblk;
   long long item_field;       // NY*NX: grad, d
   long long item_obs;         // p*ny*nx: Af, Ad
   long long item_spec;        // p*NY*NX/2: spec, khat
@@ -130,8 +134,7 @@ enum PixOp {
   PIX_FLATSUM,      // sum_S (g - b) over all images -> flat start value
   PIX_INITF,        // write the start image
   PIX_INVW,         // boundary: R mask and M_R / alpha from aux (alpha_j)
-  PIX_ARMIJO_MORE,  // further Armijo candidates theta^2 .. theta^9
-  PIX_ARMIJO_REST,  // the remaining candidates theta^10 .. theta^40
+  PIX_ARMIJO,       // Armijo test of lambda = 1, theta; if both fail, further theta^m
   PIX_FLUX_INIT,    // flux projection: all-active multiplier and bracket
   PIX_FLUX_NEWTON,  // flux projection: one Newton step on the multiplier
   PIX_FSUM,         // sum of f (flux of the start image)

@@ -89,8 +89,7 @@ void launch_pix(int op, dim3 grid, const Args& a, hipStream_t s) {
     SGP_PIX_CASE(PIX_FLATSUM)
     SGP_PIX_CASE(PIX_INITF)
     SGP_PIX_CASE(PIX_INVW)
-    SGP_PIX_CASE(PIX_ARMIJO_MORE)
-    SGP_PIX_CASE(PIX_ARMIJO_REST)
+    SGP_PIX_CASE(PIX_ARMIJO)
     SGP_PIX_CASE(PIX_FLUX_INIT)
     SGP_PIX_CASE(PIX_FLUX_NEWTON)
     SGP_PIX_CASE(PIX_FSUM)

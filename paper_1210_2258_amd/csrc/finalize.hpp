@@ -61,6 +61,18 @@ __host__ __device__ inline void fin_armijo(DevState* st, const double* dJ, int m
   }
 }
 
+// Whether fin_armijo(st, dJ, m0, n) would ask for further candidates, without
+// touching the state (every workgroup of the Armijo kernel takes the test).
+__host__ __device__ inline bool armijo_needs_more(const DevState* st, const double* dJ, int m0, int n) {
+  for (int m = 0; m < n; ++m) {
+    const int mm = m0 + m;
+    if (mm > st->max_backtracks) break;
+    if (!__builtin_isfinite(dJ[m])) return false;
+    if (dJ[m] <= st->beta * st->lam_tab[mm] * st->gd) return false;
+  }
+  return m0 + n <= st->max_backtracks;
+}
+
 __host__ __device__ inline void fin_update(DevState* st, double Jn) {
   const int k = st->k;
   double* tr = trace_row(st, k);

@@ -352,6 +352,25 @@ struct RowKinds {
   }
 };
 
+// Second reduction stage of a row iteration kernel run by one workgroup of
+// NT threads at the start of the following launch (a.fin_op).
+template <int NT>
+__device__ void deferred_fin(const Args& a, DevState* st) {
+  if (a.fin_op - 1 == ROW_DIR) {
+    double t[1];
+    sum_partials<NT, 1>(RowKinds{ROW_DIR}, a.part, a.fin_nblk, t);
+    if (threadIdx.x == 0) row_finalize<ROW_DIR>(st, a, t);
+  } else if (a.fin_op - 1 == ROW_UPD) {
+    double t[1];
+    sum_partials<NT, 1>(RowKinds{ROW_UPD}, a.part, a.fin_nblk, t);
+    if (threadIdx.x == 0) row_finalize<ROW_UPD>(st, a, t);
+  } else if (a.fin_op - 1 == ROW_GRAD) {
+    double t[4];
+    sum_partials<NT, 4>(RowKinds{ROW_GRAD}, a.part, a.fin_nblk, t);
+    if (threadIdx.x == 0) row_finalize<ROW_GRAD>(st, a, t);
+  }
+}
+
 // Workgroup index -> work index such that the g workgroups sharing one
 // 128-byte spectrum line (an 8-row block, or two columns of one) land on the
 // same XCD: the hardware deals linear workgroup ids round-robin over the 8
@@ -519,6 +538,9 @@ __global__ __launch_bounds__(ColCfg<LY>::NT) void col_kernel(Args a_in) {
 #endif
   DevState* st = a.st;
   if (a.iter && (st->done || st->pause)) return;
+  // the first workgroup of each item finishes the preceding row kernel's
+  // reduction; a stop it decides is seen by the launches that follow
+  if (a.fin_op && blockIdx.x == 0 && blockIdx.y == 0) deferred_fin<NT>(a, st);
   const int NXh = a.NX / 2;
   const int kx0 = xcd_remap(blockIdx.x, gridDim.x, C >= 2 ? 1 : 2) * C;
   const int tid = threadIdx.x;

@@ -8,12 +8,11 @@
 
 namespace sgp {
 
-constexpr int kMoreCand = 8;                   // theta^2 .. theta^9
-constexpr int kRestCand = kMaxCand - 2 - kMoreCand;  // theta^10 .. theta^40
+constexpr int kArmCand = 8;  // candidates per Armijo pass: theta^2 .. theta^9, then 8 at a time
 
 __host__ __device__ constexpr int pix_nslots(int op) {
   return op == PIX_VALIDATE ? 3 : op == PIX_PSFSUM ? 3 : op == PIX_FLATSUM ? 2 :
-         op == PIX_ARMIJO_MORE ? kMoreCand : op == PIX_ARMIJO_REST ? kRestCand :
+         op == PIX_ARMIJO ? kArmCand :
          op == PIX_FLUX_INIT ? 5 : op == PIX_FLUX_NEWTON ? 3 : op == PIX_FSUM ? 1 : 0;
 }
 
@@ -27,14 +26,69 @@ struct PixKinds {
   }
 };
 
+// Candidates theta^10 .. theta^max_backtracks, kArmCand at a time, taken by
+// the one workgroup that finished the first pass (practically never needed:
+// it takes more than nine backtracks).  Every thread of the workgroup calls it.
+__device__ void armijo_tail(const Args& a, DevState* st) {
+  constexpr int NW = kPixThreads / 64;
+  __shared__ double sh[kArmCand][NW];
+  __shared__ int go;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const long long nS = (long long)a.ny * a.nx;
+  for (int m0 = 2 + kArmCand; m0 <= st->max_backtracks; m0 += kArmCand) {
+    const int n = min(kArmCand, st->max_backtracks + 1 - m0);
+    double acc[kArmCand];
+#pragma unroll
+    for (int m = 0; m < kArmCand; ++m) acc[m] = 0.0;
+    for (long long i = tid; i < a.p * nS; i += kPixThreads) {
+      const int j = (int)(i / nS);
+      const float adv = a.Ad[i];
+      const float g = a.g[i];
+      const float yv = fmaxf(a.Af[i] + (a.bmap ? a.bmap[i] : pick_b(a, j)), 1e-30f);
+#pragma unroll
+      for (int m = 0; m < kArmCand; ++m)
+        if (m < n) acc[m] += armijo_term(g, yv, (float)st->lam_tab[m0 + m] * adv);
+    }
+#pragma unroll
+    for (int m = 0; m < kArmCand; ++m) {
+      const double v = wave_reduce<kPixThreads>(RED_SUM, acc[m]);
+      if (lane == 0) sh[m][wave] = v;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      double t[kArmCand];
+      for (int m = 0; m < kArmCand; ++m) {
+        double v = sh[m][0];
+        for (int w = 1; w < NW; ++w) v += sh[m][w];
+        t[m] = v;
+      }
+      fin_armijo(st, t, m0, n);
+      go = st->need_more;
+    }
+    __syncthreads();
+    if (!go) return;
+  }
+}
+
 template <int OP>
 __global__ __launch_bounds__(kPixThreads) void pix_kernel(Args a_in) {
   const Args a = batch_view(a_in);
   constexpr int NS = pix_nslots(OP);
   DevState* st = a.st;
   if (a.iter && (st->done || st->pause)) return;
-  if constexpr (OP == PIX_ARMIJO_MORE || OP == PIX_ARMIJO_REST) {
-    if (!st->need_more) return;
+  if constexpr (OP == PIX_ARMIJO) {
+    // Armijo test of lambda = 1 and theta (sums of ROW_AD) taken by every
+    // workgroup; the first commits the outcome unless more candidates are
+    // needed, which is rare.
+    __shared__ int more;
+    double t2[2];
+    sum_partials<kPixThreads, 2>(RowKinds{ROW_AD}, a.part, a.fin_nblk, t2);
+    if (threadIdx.x == 0) {
+      more = armijo_needs_more(st, t2, 0, 2);
+      if (!more && blockIdx.x == 0) fin_armijo(st, t2, 0, 2);
+    }
+    __syncthreads();
+    if (!more) return;
   }
   if constexpr (OP == PIX_FLUX_NEWTON) {
     if (st->flux_done) return;
@@ -115,8 +169,8 @@ __global__ __launch_bounds__(kPixThreads) void pix_kernel(Args a_in) {
       }
       a.d[i] = inR ? (float)(1.0 / sum) : 0.f;  // a.d points at the invw buffer for this launch
     }
-  } else if constexpr (OP == PIX_ARMIJO_MORE || OP == PIX_ARMIJO_REST) {
-    constexpr int m0 = OP == PIX_ARMIJO_MORE ? 2 : 2 + kMoreCand;
+  } else if constexpr (OP == PIX_ARMIJO) {
+    constexpr int m0 = 2;
     const int n = st->max_backtracks + 1 - m0;  // candidates theta^m0 .. theta^max_backtracks
     for (long long i = i0; i < a.p * nS; i += stride) {
       const int j = (int)(i / nS);
@@ -163,9 +217,16 @@ __global__ __launch_bounds__(kPixThreads) void pix_kernel(Args a_in) {
     for (long long i = i0; i < nF; i += stride) a.f[i] = (float)((double)a.f[i] * s);
   }
 
+  __shared__ int arm_tail;
+  if constexpr (OP == PIX_ARMIJO) {
+    if (threadIdx.x == 0) arm_tail = 0;
+  }
   if constexpr (NS > 0) {
     double tot[NS];
-    if (grid_reduce<kPixThreads, NS>(acc, kinds, a.part, a.counter, a.nblk, blockIdx.x, tot)) {
+    // the Armijo kernel keeps ROW_AD's partials intact: slower workgroups may
+    // still be reading them
+    double* part = OP == PIX_ARMIJO ? a.part + 2 * a.fin_nblk : a.part;
+    if (grid_reduce<kPixThreads, NS>(acc, kinds, part, a.counter, a.nblk, blockIdx.x, tot)) {
       if constexpr (OP == PIX_VALIDATE) {
         if (tot[0] < 0.0 || tot[1] > 0.0) st->flags |= FLAG_BAD_DATA;
         if (tot[2] < 0.0) st->flags |= FLAG_BAD_BG;
@@ -179,10 +240,9 @@ __global__ __launch_bounds__(kPixThreads) void pix_kernel(Args a_in) {
         st->cflat = c;
         // default flux of the constraint: (mean) background-subtracted flux
         if (!(st->flux >= 0.0)) st->flux_c = tot[0] / (double)a.p;
-      } else if constexpr (OP == PIX_ARMIJO_MORE) {
-        fin_armijo(st, tot, 2, kMoreCand);
-      } else if constexpr (OP == PIX_ARMIJO_REST) {
-        fin_armijo(st, tot, 2 + kMoreCand, kRestCand);
+      } else if constexpr (OP == PIX_ARMIJO) {
+        fin_armijo(st, tot, 2, kArmCand);
+        arm_tail = st->need_more;
       } else if constexpr (OP == PIX_FLUX_INIT) {
         fin_flux_init(st, tot);
       } else if constexpr (OP == PIX_FLUX_NEWTON) {
@@ -191,6 +251,10 @@ __global__ __launch_bounds__(kPixThreads) void pix_kernel(Args a_in) {
         st->fsum = tot[0];
       }
     }
+  }
+  if constexpr (OP == PIX_ARMIJO) {
+    __syncthreads();
+    if (arm_tail) armijo_tail(a, st);  // the last workgroup only
   }
 }
 

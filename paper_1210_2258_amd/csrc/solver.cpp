@@ -92,10 +92,15 @@ struct Plan {
 static std::mutex g_mutex;
 static std::map<PlanKey, std::unique_ptr<Plan>> g_plans;
 
+// workgroups of the Armijo kernel (its rare candidate pass)
+constexpr int kArmBlocks = 512;
+
 static size_t part_capacity(const PlanKey& k) {
-  // row kernels: at most NY / 2 workgroups per image and 4 slots
+  // row kernels: at most NY / 2 workgroups per image and 4 slots; the Armijo
+  // kernel keeps ROW_AD's 2 slots and adds 8 slots of its own
   const size_t row_blocks = (size_t)(k.NY / 2) * k.p;
-  return std::max<size_t>((size_t)(kMaxCand) * kMaxPixBlocks, 4 * row_blocks);
+  return std::max<size_t>({(size_t)(kMaxCand) * kMaxPixBlocks, 4 * row_blocks,
+                           2 * row_blocks + (size_t)8 * kArmBlocks});
 }
 
 template <class T>
@@ -283,33 +288,42 @@ struct Launcher {
       marks.push_back({a, b, cls});
     }
   }
-  void row(int op, int jc, int iter, int flag = 0, int cls = -1) {
+  int row_nblk = 0;  // workgroups of the last row launch (its partials)
+  // Row kernel.  The iteration ops (row_fin_deferred) leave their reduction
+  // partials; fin = true finishes it in a one-workgroup launch, otherwise the
+  // next col() / pix() launch must be given the op as fin_op.
+  void row(int op, int jc, int iter, int flag = 0, int cls = -1, bool fin = false) {
     Args a = base;
     const int gx = NY / (2 * row_pairs(NX));
     a.nblk = gx * jc;
+    row_nblk = a.nblk;
     a.iter = iter;
     a.flag = flag;
     hipEvent_t e0 = nullptr;
     begin(cls, e0);
     launch_row(NX, op, dim3(gx, jc, nz), a, s);
-    if (row_fin_deferred(op)) launch_row_fin(op, nz, a, s);
+    if (fin) launch_row_fin(op, nz, a, s);
     end(cls, e0);
   }
-  void col(int mode, int conj, int jc, int iter, int cls = -1) {
+  void col(int mode, int conj, int jc, int iter, int cls = -1, int fin_op = -1) {
     Args a = base;
     const int C = col_width(NY);
+    a.fin_op = fin_op + 1;
+    a.fin_nblk = row_nblk;
     a.iter = iter;
     hipEvent_t e0 = nullptr;
     begin(cls, e0);
     launch_col(NY, mode, conj, dim3((NX / 2 + C - 1) / C, jc, nz), a, s);
     end(cls, e0);
   }
-  void pix(int op, long long n, int iter, int jsel = 0, int cls = -1) {
+  void pix(int op, long long n, int iter, int jsel = 0, int cls = -1, int fin_op = -1) {
     Args a = base;
+    a.fin_op = fin_op + 1;
+    a.fin_nblk = row_nblk;
     long long nb = (n + kPixThreads - 1) / kPixThreads;
     // the extra Armijo candidates are rarely needed: a small grid keeps the
     // usual early exit cheap
-    const long long cap = (op == PIX_ARMIJO_MORE || op == PIX_ARMIJO_REST) ? 256 : kMaxPixBlocks;
+    const long long cap = op == PIX_ARMIJO ? kArmBlocks : kMaxPixBlocks;
     nb = std::max<long long>(1, std::min<long long>(nb, cap));
     a.nblk = (int)nb;
     a.iter = iter;
@@ -430,14 +444,16 @@ static void enqueue_iteration(sgp_solver* S) {
       L.pix(PIX_FLUX_INIT, nF, 1, 0, SGP_KCLASS_ROW_DIR);
       for (int t = 0; t < kFluxNewton; ++t) L.pix(PIX_FLUX_NEWTON, nF, 1, 0, SGP_KCLASS_ROW_DIR);
     }
+    // each row kernel's reduction is finished at the start of the next launch
+    // (the direction and update sums by the column kernels, the Armijo test by
+    // the Armijo kernel), the BB sums by a one-workgroup launch
     L.row(ROW_DIR, 1, 1, 0, SGP_KCLASS_ROW_DIR);
-    L.col(COL_CONV, 0, 1, 1, SGP_KCLASS_COL_CONV);
+    L.col(COL_CONV, 0, 1, 1, SGP_KCLASS_COL_CONV, ROW_DIR);
     L.row(ROW_AD, p, 1, 0, SGP_KCLASS_ROW_AD);
-    L.pix(PIX_ARMIJO_MORE, p * nS, 1, 0, SGP_KCLASS_ARMIJO_MORE);
-    L.pix(PIX_ARMIJO_REST, p * nS, 1, 0, SGP_KCLASS_ARMIJO_MORE);
+    L.pix(PIX_ARMIJO, p * nS, 1, 0, SGP_KCLASS_ARMIJO_MORE, ROW_AD);
     L.row(ROW_UPD, p, 1, 0, SGP_KCLASS_ROW_UPD);
-    L.col(COL_CORRSUM, 1, 1, 1, SGP_KCLASS_COL_CORR);
-    L.row(ROW_GRAD, 1, 1, 0, SGP_KCLASS_ROW_GRAD);
+    L.col(COL_CORRSUM, 1, 1, 1, SGP_KCLASS_COL_CORR, ROW_UPD);
+    L.row(ROW_GRAD, 1, 1, 0, SGP_KCLASS_ROW_GRAD, true);
   } else {
     L.col(COL_CONV, 0, 1, 1, SGP_KCLASS_COL_CONV);
     L.row(ROW_RATIO, p, 1, 0, SGP_KCLASS_ROW_RATIO);

@@ -146,6 +146,23 @@ def test_sgp_alternation_branch(torch_dev, case):
     assert abs(rep["kl"] - io["kl"]) <= KL_TOL * io["kl"]
 
 
+@pytest.mark.parametrize("alpha0", [1e2, 1e5])
+def test_sgp_many_backtracks(torch_dev, alpha0):
+    """A large first steplength forces the line search past the first two
+    candidates (4 reductions at alpha0 = 1e2, 11 at 1e5: the candidates
+    beyond theta^9 are taken in a second stage)."""
+    w = CASES["single_64x80"]()
+    n = 4
+    f, rep = _run_gpu(torch_dev, "sgp_deconv", w, max_iter=n, alpha0=alpha0)
+    P = _oracle(w)
+    fo, io = P.sgp(P.start("flat"), O.Params(max_iter=n, alpha0=alpha0))
+    assert io["log"][0]["backtracks"] == (4 if alpha0 == 1e2 else 11)
+    _check_log(rep["trace"], io["log"], n)
+    assert rep["backtracks"] == sum(L["backtracks"] for L in io["log"][:n])
+    assert _rel(f.cpu().numpy(), fo) <= F_TOL, _rel(f.cpu().numpy(), fo)
+    assert abs(rep["kl"] - io["kl"]) <= KL_TOL * io["kl"], (rep["kl"], io["kl"])
+
+
 def test_sgp_decision_log_long_horizon(torch_dev):
     """Armijo and alternation decisions agree far past the fixed-count window
     on the 256x256 star field (their margins are wide)."""
