@@ -124,6 +124,7 @@ enum ColMode {
   COL_FWD = 0,      // spec[j] -> khat[j], knyq[j]   (setup)
   COL_CONV,         // spec[0] -> spec[j] = K_j x (or conj K_j x)
   COL_CORRSUM,      // spec[j] -> spec[0] = sum_j conj(K_j) x_j
+  COL_CORR1,        // COL_CORRSUM for p = 1 (fewer registers)
   COL_NMODES
 };
 

@@ -652,6 +652,49 @@ __global__ __launch_bounds__(ColCfg<LY>::NT) void col_kernel(Args a_in) {
       }
       __syncthreads();
     }
+  } else if constexpr (MODE == COL_CORR1) {  // COL_CORRSUM for one image
+    load(a.spec);
+    const float2* K = a.khat;
+    const float2* KN = a.knyq;
+    float2 kpre[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      int c, y; long long off;
+      unit(e, c, y, off);
+      kpre[e] = (kx0 + c < NXh) ? K[off] : make_float2(0.f, 0.f);
+    }
+    __syncthreads();
+    fft_lds<LY>(buf[tid / TF], tid % TF, tw);
+    float2 pr[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      int c, y; long long off;
+      unit(e, c, y, off);
+      const float2 v = buf[c][lds_idx<LY>(y)];
+      if (has_col0 && c == 0) {
+        const float2 m = cconj(buf[0][lds_idx<LY>((LY - y) % LY)]);
+        const float2 ev = cscale(cadd(v, m), 0.5f);
+        const float2 od = cscale(mul_mi(csub(v, m)), 0.5f);
+        pr[e] = cadd(cmulc(ev, kpre[e]), mul_pi(cmulc(od, KN[y])));
+      } else {
+        pr[e] = cmulc(v, kpre[e]);
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      int c, y; long long off;
+      unit(e, c, y, off);
+      buf[c][lds_idx<LY>(y)] = cconj(pr[e]);
+    }
+    __syncthreads();
+    fft_lds<LY>(buf[tid / TF], tid % TF, tw);
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      int c, y; long long off;
+      unit(e, c, y, off);
+      if (kx0 + c < NXh) a.spec[off] = cconj(buf[c][lds_idx<LY>(y)]);
+    }
   } else {  // COL_CORRSUM
     float2 acc[E];
 #pragma unroll
