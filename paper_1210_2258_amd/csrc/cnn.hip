@@ -51,32 +51,50 @@ constexpr int kParams = layer_off(kLayers);
 __device__ __forceinline__ int wrap(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
 
 // ------------------------------------------------------------------ kernels
-// Per-image scale and input: x = (g - b) / s (one workgroup per image).
-__global__ __launch_bounds__(NT) void prep_kernel(const float* const* g, const float* bgd, const float* const* ft,
-                                                  int H, int W, float* x, float* t, float* s_out) {
-  const int img = blockIdx.x;
+// Per-image scale and input, in two launches: partial sums of g - b over
+// kPrepSlices slices of each image (FP64), then s = max(mean(g - b), 1e-3)
+// (every workgroup sums the partials of its image in the same order) and
+// x = (g - b) / s, t = f_target / s.
+constexpr int kPrepSlices = 64;
+
+__global__ __launch_bounds__(NT) void prep_sum_kernel(const float* const* g, const float* bgd, int H, int W,
+                                                      double* part) {
+  const int img = blockIdx.y;
   const float* gi = g[img];
-  const float b = bgd[img];
+  const double b = (double)bgd[img];
   const long long N = (long long)H * W;
   __shared__ double red[NT];
-  __shared__ float s_sh;
   double acc = 0.0;
-  for (long long i = threadIdx.x; i < N; i += NT) acc += (double)gi[i] - (double)b;
+  for (long long i = (long long)blockIdx.x * NT + threadIdx.x; i < N; i += (long long)kPrepSlices * NT)
+    acc += (double)gi[i] - b;
   red[threadIdx.x] = acc;
   __syncthreads();
   for (int w = NT / 2; w > 0; w >>= 1) {
     if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
     __syncthreads();
   }
+  if (threadIdx.x == 0) part[img * kPrepSlices + blockIdx.x] = red[0];
+}
+
+__global__ __launch_bounds__(NT) void prep_scale_kernel(const float* const* g, const float* bgd,
+                                                        const float* const* ft, const double* part, int H, int W,
+                                                        float* x, float* t, float* s_out) {
+  const int img = blockIdx.y;
+  const long long N = (long long)H * W;
+  __shared__ float s_sh;
   if (threadIdx.x == 0) {
-    const double m = red[0] / (double)N;
+    double m = 0.0;
+    for (int k = 0; k < kPrepSlices; ++k) m += part[img * kPrepSlices + k];
+    m /= (double)N;
     s_sh = (float)(m > 1e-3 ? m : 1e-3);
-    s_out[img] = s_sh;
+    if (blockIdx.x == 0) s_out[img] = s_sh;
   }
   __syncthreads();
   const float s = s_sh;
-  for (long long i = threadIdx.x; i < N; i += NT) {
-    x[img * N + i] = (gi[i] - b) / s;
+  const float b = bgd[img];
+  const long long i = (long long)blockIdx.x * NT + threadIdx.x;
+  if (i < N) {
+    x[img * N + i] = (g[img][i] - b) / s;
     if (t) t[img * N + i] = ft[img][i] / s;
   }
 }
@@ -338,19 +356,21 @@ struct Net {
   float *da = nullptr, *db = nullptr, *d_o = nullptr, *part = nullptr;
   double* lpart = nullptr;
   double* host_lpart = nullptr;
+  double* ppart = nullptr;  // [cap_n][kPrepSlices] partial sums of the input scale
   const float** gtab = nullptr;
   const float** fttab = nullptr;
   float** f0tab = nullptr;
   float* btab = nullptr;
   ~Net() { release(); free_params(); }
   void release() {
-    void* p[] = {x, t, s, a[0], a[1], a[2], o, da, db, d_o, part, lpart, (void*)gtab, (void*)fttab, (void*)f0tab, btab};
+    void* p[] = {x, t, s, a[0], a[1], a[2], o, da, db, d_o, part, lpart, ppart, (void*)gtab, (void*)fttab, (void*)f0tab, btab};
     for (void* q : p)
       if (q) (void)hipFree(q);
     if (host_lpart) (void)hipHostFree(host_lpart);
     x = t = s = o = da = db = d_o = part = btab = nullptr;
     a[0] = a[1] = a[2] = nullptr;
     lpart = nullptr;
+    ppart = nullptr;
     host_lpart = nullptr;
     gtab = fttab = nullptr;
     f0tab = nullptr;
@@ -389,7 +409,8 @@ static int ensure(Net* net, int n, int H, int W, bool train) {
   int rc;
   if ((rc = dal(&net->x, px)) || (rc = dal(&net->s, nn)) || (rc = dal(&net->o, px)) ||
       (rc = dal(&net->a[0], px * C)) || (rc = dal(&net->a[1], px * C)) || (rc = dal(&net->gtab, nn)) ||
-      (rc = dal(&net->fttab, nn)) || (rc = dal(&net->f0tab, nn)) || (rc = dal(&net->btab, nn)))
+      (rc = dal(&net->fttab, nn)) || (rc = dal(&net->f0tab, nn)) || (rc = dal(&net->btab, nn)) ||
+      (rc = dal(&net->ppart, (size_t)nn * kPrepSlices)))
     return rc;
   if (tr) {
     if ((rc = dal(&net->a[2], px * C)) || (rc = dal(&net->t, px)) || (rc = dal(&net->da, px * C)) ||
@@ -417,6 +438,19 @@ static int forward(Net* net, int n, int H, int W, bool train, hipStream_t s) {
   hipLaunchKernelGGL((conv_fwd_kernel<C, C, true>), grid, dim3(NT), 0, s, net->a[0], wl(net, 1), bl(net, 1), net->a[1], H, W);
   hipLaunchKernelGGL((conv_fwd_kernel<C, C, true>), grid, dim3(NT), 0, s, net->a[1], wl(net, 2), bl(net, 2), a3, H, W);
   hipLaunchKernelGGL((conv_fwd_kernel<C, 1, false>), grid, dim3(NT), 0, s, a3, wl(net, 3), bl(net, 3), net->o, H, W);
+  CNN_HIP(hipGetLastError());
+  return 0;
+}
+
+// network input (and training target) of n images into x (t)
+static int prep(Net* net, int n, int H, int W, bool train, hipStream_t s) {
+  const long long N = (long long)H * W;
+  hipLaunchKernelGGL(prep_sum_kernel, dim3(kPrepSlices, n), dim3(NT), 0, s, (const float* const*)net->gtab,
+                     (const float*)net->btab, H, W, net->ppart);
+  hipLaunchKernelGGL(prep_scale_kernel, dim3((unsigned)((N + NT - 1) / NT), n), dim3(NT), 0, s,
+                     (const float* const*)net->gtab, (const float*)net->btab,
+                     train ? (const float* const*)net->fttab : (const float* const*)nullptr, (const double*)net->ppart,
+                     H, W, net->x, train ? net->t : (float*)nullptr, net->s);
   CNN_HIP(hipGetLastError());
   return 0;
 }
@@ -498,8 +532,7 @@ int sgp_cnn_infer(sgp_cnn* h, int n, const float* const* g, const float* b, int 
   hipStream_t s = (hipStream_t)stream;
   if ((rc = ensure(net, n, ny, nx, false))) return rc;
   if ((rc = set_tables(net, n, g, b, nullptr, f0, s))) return rc;
-  hipLaunchKernelGGL(prep_kernel, dim3(n), dim3(NT), 0, s, net->gtab, net->btab, (const float* const*)nullptr, ny, nx,
-                     net->x, (float*)nullptr, net->s);
+  if ((rc = prep(net, n, ny, nx, false, s))) return rc;
   if ((rc = forward(net, n, ny, nx, false, s))) return rc;
   const long long N = (long long)ny * nx;
   hipLaunchKernelGGL(output_kernel, dim3((unsigned)((N + 255) / 256), n), dim3(256), 0, s, net->o, net->s,
@@ -518,8 +551,7 @@ int sgp_cnn_loss_grad(sgp_cnn* h, int n, const float* const* g, const float* b, 
   hipStream_t s = (hipStream_t)stream;
   if ((rc = ensure(net, n, ny, nx, true))) return rc;
   if ((rc = set_tables(net, n, g, b, f_target, nullptr, s))) return rc;
-  hipLaunchKernelGGL(prep_kernel, dim3(n), dim3(NT), 0, s, net->gtab, net->btab, (const float* const*)net->fttab,
-                     ny, nx, net->x, net->t, net->s);
+  if ((rc = prep(net, n, ny, nx, true, s))) return rc;
   if ((rc = forward(net, n, ny, nx, true, s))) return rc;
   const long long total = (long long)n * ny * nx;
   hipLaunchKernelGGL(loss_grad_kernel, dim3(kLossWg), dim3(NT), 0, s, net->o, net->t, total, net->d_o, net->lpart);
