@@ -17,6 +17,8 @@ deconvolution methods for astronomical imaging: algorithms and IDL-GPU codes"
 * multiple images ........................... Sect. 2.3, Eqs. (multipleKL), (multipleRL), (multiplegradient)
 * boundary effect correction ................ Sect. 2.4, Eqs. (projection), (backprojection),
                                               (gradientboundary), (Rdef), (boundaryRL), (Dkbound)
+* OSEM (ordered subsets over the images) ..... Sect. 2.3, Algorithm 2, Eq. (OSEMstep);
+                                              Sect. 2.4, Eq. (boundaryOSEM)
 * start, parameters, adaptive bounds ........ Sect. 3.1, 3.2
 * stopping rules ............................ Sect. 3.3, Eqs. (convergence), (discrepancy)
 * flux-constrained projection ............... Sect. 2 intro (constraint set named, algorithm
@@ -263,6 +265,44 @@ class Problem:
             if (prm.stop & STOP_CONV) and abs(Jn - J) <= prm.tol * J:
                 reason = REASON_CONV
                 J = Jn
+                break
+            J = Jn
+        return f, dict(iters=k, kl=J, history=hist, reason=reason)
+
+    # -------------------------------------------------------------- OSEM
+    def osem_weight(self, j):
+        """M_R / alpha_j, zero outside R (Eq. boundaryOSEM); for periodic
+        problems alpha_j = A_j^T 1 = 1 and the weight is 1 (Eq. OSEMstep)."""
+        return np.where(self.MR > 0, 1.0 / np.where(self.MR > 0, self.alpha_j[j], 1.0), 0.0)
+
+    def osem_cycle(self, f):
+        """Algorithm 2, steps 1-3: h^(0) = f, then for j = 1..p
+        h^(j) = w_j o h^(j-1) o A_j^T (g_j / (A_j h^(j-1) + b_j)); returns h^(p)."""
+        h = f.copy()
+        for j in range(self.p):
+            h = self.osem_weight(j) * h * self.AT(j, self.g[j] / self.y(j, h))
+        return h
+
+    def osem(self, f0, n_iter, params: Params | None = None):
+        """OSEM cycles with the stopping rules of rl() (KL of each iterate f^(k))."""
+        prm = params or Params(max_iter=n_iter)
+        f = f0.copy()
+        J = self.kl(f)
+        hist = [J]
+        k = 0
+        if (prm.stop & STOP_DISCREPANCY) and self.discrepancy(J) <= prm.disc_target:
+            return f, dict(iters=0, kl=J, history=hist, reason=REASON_DISCREPANCY)
+        reason = REASON_MAXITER
+        while k < n_iter:
+            f = self.osem_cycle(f)
+            Jn = self.kl(f)
+            k += 1
+            hist.append(Jn)
+            if (prm.stop & STOP_DISCREPANCY) and self.discrepancy(Jn) <= prm.disc_target:
+                reason, J = REASON_DISCREPANCY, Jn
+                break
+            if (prm.stop & STOP_CONV) and abs(Jn - J) <= prm.tol * J:
+                reason, J = REASON_CONV, Jn
                 break
             J = Jn
         return f, dict(iters=k, kl=J, history=hist, reason=reason)
