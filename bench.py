@@ -58,6 +58,7 @@ def parse():
     ap.add_argument("--no-batch", action="store_true", help="skip the heterogeneous batch legs")
     ap.add_argument("--no-ttd", action="store_true", help="skip the time-to-discrepancy runs")
     ap.add_argument("--batch-images", type=int, default=512)
+    ap.add_argument("--no-multi", action="store_true", help="skip the multi-image RL / OSEM / SGP comparison")
     return ap.parse_args()
 
 
@@ -145,6 +146,28 @@ def time_to_discrepancy(torch, m, g, psf, b):
     return {"time_to_discrepancy_s": ttd, "iters_to_discrepancy": drep["iters"],
             "discrepancy_final": drep["discrepancy"], "kl_final": drep["kl"],
             "rl_time_to_discrepancy_s": ttd_rl, "rl_iters_to_discrepancy": rrep["iters"]}
+
+
+def multi_image_legs(torch, m, w):
+    """Multiple-image RL (Eq. multipleRL), OSEM (Algorithm 2) and SGP on the
+    3 x 1024^2 interferometric workload, each to the discrepancy stop, call to
+    return with the inputs resident (the comparison of the paper's Tables 5-8
+    on synthetic data)."""
+    g = torch.from_numpy(w.g).cuda()
+    psf = torch.from_numpy(w.psf).cuda()
+    out = {"workload": f"{w.g.shape[0]} x {w.g.shape[1]}x{w.g.shape[2]} fringe-PSF images of one object, b = 20",
+           "stop": "discrepancy <= 1 (cap 20000 iterations)"}
+    for name, fn in (("rl", m.rl_multi_deconv), ("osem", m.osem_deconv), ("sgp", m.sgp_multi_deconv)):
+        fn(g, psf, w.b, max_iter=2)  # workspace of this shape and kind
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, rep = fn(g, psf, w.b, max_iter=20000, stop=m.STOP_DISCREPANCY)
+        torch.cuda.synchronize()
+        out[name] = {"seconds": time.perf_counter() - t0, "iterations": rep["iters"], "reason": rep["reason"],
+                     "kl": rep["kl"], "discrepancy": rep["discrepancy"]}
+    out["speedup_sgp_vs_rl"] = out["rl"]["seconds"] / out["sgp"]["seconds"]
+    out["speedup_osem_vs_rl"] = out["rl"]["seconds"] / out["osem"]["seconds"]
+    return out
 
 
 COUNTER_FILE = os.path.join(ROOT, "profiles", "sgp_2048_hbm_counters.md")
@@ -293,6 +316,8 @@ def main():
     }
     if batch_items is not None:
         out["batch_512"] = batch_legs(torch, m, batch_items)
+    if not args.no_multi:
+        out["multi_image_3x1024"] = multi_image_legs(torch, m, W.config2())
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_iters)
     print(json.dumps(out))

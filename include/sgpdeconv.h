@@ -169,6 +169,22 @@ int rl_boundary_deconv(const float* g, const float* psf, const float* b_map,
                        int oy, int ox, const sgp_params* prm, float* f,
                        sgp_report* rep, void* hip_stream);
 
+/* OSEM, ordered subsets over the p images (Sect. 2.3 Algorithm 2,
+ * Eq. (OSEMstep)): every iteration cycles over the images,
+ * h <- h o A_j^T (g_j / (A_j h + b_j)), j = 1..p.  Arguments, layouts and
+ * errors as sgp_multi_deconv; the flux constraint and SGP_INIT_ZERO are
+ * rejected (SGP_E_INVALID_ARG).  The KL divergence of every iterate f^(k) is
+ * formed over all images for the stop rules and the report. */
+int osem_deconv(const float* g, const float* psf, const float* b_map, const float* b_const, int p,
+                int ny, int nx, const sgp_params* prm, float* f, sgp_report* rep, void* hip_stream);
+
+/* OSEM with boundary-effect correction (Sect. 2.4 Eq. (boundaryOSEM)):
+ * h <- (M_R / alpha_j) o h o A_j^T (g_j / (A_j h + b_j)), alpha_j = A_j^T 1
+ * before M_R.  Arguments as sgp_boundary_deconv. */
+int osem_boundary_deconv(const float* g, const float* psf, const float* b_map, const float* b_const, int p,
+                         int ny, int nx, int NY, int NX, int oy, int ox, const sgp_params* prm, float* f,
+                         sgp_report* rep, void* hip_stream);
+
 /* Operator application for checks and callers that build their own loops:
  * out = A_j x (adjoint = 0) or A_j^T x (adjoint = 1) for the periodic
  * operator of Sect. 1 (K_j unit-volume, centred).  x, out: [ny][nx];
@@ -187,6 +203,7 @@ int sgp_apply_operator(const float* psf, const float* x, int ny, int nx, int adj
  * ------------------------------------------------------------------------- */
 #define SGP_KIND_RL 0
 #define SGP_KIND_SGP 1
+#define SGP_KIND_OSEM 2
 
 typedef struct sgp_problem {
   const float* g;        /* device [p][ny][nx] */
@@ -200,7 +217,7 @@ typedef struct sgp_problem {
 
 typedef struct sgp_solver sgp_solver;
 
-/* kind: SGP_KIND_RL or SGP_KIND_SGP.  f: device [NY][NX], the iterate, owned
+/* kind: SGP_KIND_RL, SGP_KIND_SGP or SGP_KIND_OSEM.  f: device [NY][NX], the iterate, owned
  * by the caller and updated in place by step().  The parameters are copied;
  * prm->trace (if set) must stay valid until sgp_solver_destroy. */
 int sgp_solver_create(int kind, const sgp_problem* prob, const sgp_params* prm, float* f,
@@ -237,7 +254,7 @@ int sgp_solver_destroy(sgp_solver* s);
  * shape form one batched solver (every launch covers all of them); all
  * shapes advance together in one HIP graph of parallel branches, replayed
  * until every problem has met its own stop rule.  reps: n reports (optional).
- * Returns the most severe per-problem code.  kind: SGP_KIND_SGP or _RL. */
+ * Returns the most severe per-problem code.  kind: SGP_KIND_SGP, _RL or _OSEM. */
 int sgp_batch_deconv(int kind, const sgp_problem* probs, int n, float* const* f, const float* const* f0,
                      const sgp_params* prm, sgp_report* reps, void* hip_stream);
 

@@ -62,7 +62,7 @@ class _Problem(ctypes.Structure):
     ]
 
 
-KIND_RL, KIND_SGP = 0, 1
+KIND_RL, KIND_SGP, KIND_OSEM = 0, 1, 2
 KCLASSES = ["row_dir", "col_conv", "row_ad", "armijo_more", "row_upd", "col_corr", "row_grad",
             "row_ratio", "row_rlupd"]
 
@@ -71,7 +71,7 @@ EXPORTS = [
     "sgp_boundary_deconv", "rl_boundary_deconv", "sgp_apply_operator", "sgp_release_cache",
     "sgp_strerror", "sgp_last_error", "sgp_solver_create", "sgp_solver_step", "sgp_solver_report",
     "sgp_solver_set_timing", "sgp_solver_set_graph", "sgp_solver_timing", "sgp_solver_destroy",
-    "sgp_steplength_rule", "sgp_batch_deconv",
+    "sgp_steplength_rule", "sgp_batch_deconv", "osem_deconv", "osem_boundary_deconv",
     "sgp_cnn_num_params", "sgp_cnn_create", "sgp_cnn_get_params", "sgp_cnn_infer", "sgp_cnn_loss_grad",
     "sgp_cnn_adam_step", "sgp_cnn_train_step", "sgp_cnn_destroy",
 ]
@@ -92,9 +92,9 @@ def load():
     lib.sgp_params_init.argtypes = [P]
     for name in ("rl_deconv", "sgp_deconv"):
         getattr(lib, name).argtypes = [vp, vp, vp, f, i, i, P, vp, R, vp]
-    for name in ("sgp_multi_deconv", "rl_multi_deconv"):
+    for name in ("sgp_multi_deconv", "rl_multi_deconv", "osem_deconv"):
         getattr(lib, name).argtypes = [vp, vp, vp, vp, i, i, i, P, vp, R, vp]
-    for name in ("sgp_boundary_deconv", "rl_boundary_deconv"):
+    for name in ("sgp_boundary_deconv", "rl_boundary_deconv", "osem_boundary_deconv"):
         getattr(lib, name).argtypes = [vp, vp, vp, vp, i, i, i, i, i, i, i, P, vp, R, vp]
     lib.sgp_apply_operator.argtypes = [vp, vp, i, i, i, vp, vp]
     lib.sgp_solver_create.argtypes = [i, ctypes.POINTER(_Problem), P, vp, vp, ctypes.POINTER(vp)]
@@ -273,6 +273,16 @@ def sgp_boundary_deconv(g, psf, b, domain, *, b_map=None, f=None, stream=None, t
 def rl_boundary_deconv(g, psf, b, domain, *, b_map=None, f=None, stream=None, trace=False, **params):
     """RL with boundary-effect correction; domain = (NY, NX, oy, ox)."""
     return _solve_stack(load().rl_boundary_deconv, g, psf, b, b_map, f, stream, trace, params, domain)
+
+
+def osem_deconv(g, psf, b, *, b_map=None, f=None, stream=None, trace=False, **params):
+    """OSEM over the p images of g [p, ny, nx] (Algorithm 2)."""
+    return _solve_stack(load().osem_deconv, g, psf, b, b_map, f, stream, trace, params)
+
+
+def osem_boundary_deconv(g, psf, b, domain, *, b_map=None, f=None, stream=None, trace=False, **params):
+    """OSEM with boundary-effect correction (Eq. boundaryOSEM); domain = (NY, NX, oy, ox)."""
+    return _solve_stack(load().osem_boundary_deconv, g, psf, b, b_map, f, stream, trace, params, domain)
 
 
 def apply_operator(psf, x, adjoint=False, out=None, stream=None):

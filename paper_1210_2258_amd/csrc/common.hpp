@@ -96,6 +96,9 @@ struct Args {
   // workgroups) this launch finalises first (0: none)
   int fin_op;
   int fin_nblk;
+  // image range of a launch: row launches work on images j0 + blockIdx.y,
+  // column launches on images j0 .. j0 + jn - 1 (jn = 0: all p)
+  int j0, jn;
   long long item_field;       // NY*NX: grad, d
   long long item_obs;         // p*ny*nx: Af, Ad
   long long item_spec;        // p*NY*NX/2: spec, khat
@@ -141,6 +144,7 @@ enum PixOp {
   PIX_FSUM,         // sum of f (flux of the start image)
   PIX_FSCALE,       // scale f to the prescribed flux
   PIX_CHOOSE,       // keep the given start or fall back to the flat one (lower KL wins)
+  PIX_INVWJ,        // boundary OSEM: per-image weights M_R / alpha_j from aux
   PIX_NOPS
 };
 

@@ -95,6 +95,7 @@ void launch_pix(int op, dim3 grid, const Args& a, hipStream_t s) {
     SGP_PIX_CASE(PIX_FSUM)
     SGP_PIX_CASE(PIX_FSCALE)
     SGP_PIX_CASE(PIX_CHOOSE)
+    SGP_PIX_CASE(PIX_INVWJ)
 #undef SGP_PIX_CASE
     default: break;
   }

@@ -410,7 +410,7 @@ __global__ __launch_bounds__(RowCfg<L>::NT) void row_kernel(Args a_in) {
   DevState* st = a.st;
   if (a.iter && (st->done || st->pause)) return;
   const int tid = threadIdx.x;
-  const int j = blockIdx.y;
+  const int j = blockIdx.y + a.j0;
   const int wg = xcd_remap(blockIdx.x, gridDim.x, kRP / RP);
   const int y0 = wg * 2 * RP;  // first row of this workgroup
   const long long sstride = spec_elems(a.NY, a.NX);
@@ -504,7 +504,10 @@ __global__ __launch_bounds__(RowCfg<L>::NT) void row_kernel(Args a_in) {
     }
   }
 
-  if constexpr (NS > 0) {
+  // a ratio pass of one OSEM sub-step (flag bit 4) needs no KL sum
+  bool reduce = NS > 0;
+  if constexpr (OP == ROW_RATIO) reduce = !(a.flag & 4);
+  if constexpr (NS > 0) if (reduce) {
     const int bid = blockIdx.y * gridDim.x + blockIdx.x;
     if constexpr (row_deferred_fin(OP)) {
       block_partials<NT, NS>(acc, RowKinds{OP}, a.part, a.nblk, bid);
@@ -592,13 +595,15 @@ __global__ __launch_bounds__(ColCfg<LY>::NT) void col_kernel(Args a_in) {
       }
     }
   } else if constexpr (MODE == COL_CONV) {
+    const int jlo = a.j0, jhi = a.j0 + (a.jn ? a.jn : a.p);  // images to convolve
     load(a.spec);
-    float2 kpre[E];  // transfer function of image 0, fetched while the spectrum is transformed
+    float2 kpre[E];  // transfer function of image jlo, fetched while the spectrum is transformed
+    const float2* K0 = a.khat + jlo * sstride;
 #pragma unroll
     for (int e = 0; e < E; ++e) {
       int c, y; long long off;
       unit(e, c, y, off);
-      kpre[e] = (kx0 + c < NXh) ? a.khat[off] : make_float2(0.f, 0.f);
+      kpre[e] = (kx0 + c < NXh) ? K0[off] : make_float2(0.f, 0.f);
     }
     __syncthreads();
     fft_lds<LY>(buf[tid / TF], tid % TF, tw);
@@ -618,7 +623,7 @@ __global__ __launch_bounds__(ColCfg<LY>::NT) void col_kernel(Args a_in) {
       }
     }
     __syncthreads();
-    for (int jo = 0; jo < a.p; ++jo) {
+    for (int jo = jlo; jo < jhi; ++jo) {
       int lane = tid % TF;
       asm volatile("" : "+v"(lane));  // keeps per-pass address arithmetic inside the loop
       const float2* K = a.khat + jo * sstride;
@@ -629,7 +634,7 @@ __global__ __launch_bounds__(ColCfg<LY>::NT) void col_kernel(Args a_in) {
         unit(e, c, y, off);
         float2 pr = make_float2(0.f, 0.f);
         if (kx0 + c < NXh) {
-          const float2 kv = jo == 0 ? kpre[e] : K[off];
+          const float2 kv = jo == jlo ? kpre[e] : K[off];
           if (has_col0 && c == 0) {
             const float2 kn = KN[y];
             const float2 p0 = CONJ ? cmulc(x0[e], kv) : cmul(x0[e], kv);
@@ -699,7 +704,7 @@ __global__ __launch_bounds__(ColCfg<LY>::NT) void col_kernel(Args a_in) {
     float2 acc[E];
 #pragma unroll
     for (int e = 0; e < E; ++e) acc[e] = make_float2(0.f, 0.f);
-    for (int ji = 0; ji < a.p; ++ji) {
+    for (int ji = a.j0; ji < a.j0 + (a.jn ? a.jn : a.p); ++ji) {
       int lane = tid % TF;
       asm volatile("" : "+v"(lane));  // keeps per-pass address arithmetic inside the loop
       load(a.spec + ji * sstride);

@@ -169,6 +169,16 @@ __global__ __launch_bounds__(kPixThreads) void pix_kernel(Args a_in) {
       }
       a.d[i] = inR ? (float)(1.0 / sum) : 0.f;  // a.d points at the invw buffer for this launch
     }
+  } else if constexpr (OP == PIX_INVWJ) {
+    // Eq. (boundaryOSEM): M_R / alpha_j per image, R as for PIX_INVW
+    for (long long i = i0; i < nF; i += stride) {
+      bool inR = true;
+      for (int j = 0; j < a.p; ++j) inR = inR && ((double)a.aux[(long long)j * nF + i] >= st->sigma_R);
+      for (int j = 0; j < a.p; ++j) {
+        const float al = a.aux[(long long)j * nF + i];
+        a.d[(long long)j * nF + i] = inR ? (float)(1.0 / (double)al) : 0.f;  // a.d: the weight buffer
+      }
+    }
   } else if constexpr (OP == PIX_ARMIJO) {
     constexpr int m0 = 2;
     const int n = st->max_backtracks + 1 - m0;  // candidates theta^m0 .. theta^max_backtracks

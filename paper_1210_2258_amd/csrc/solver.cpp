@@ -41,7 +41,9 @@ void record_error(const std::string& msg) { g_last_error = msg; }
     if (e_ != hipSuccess) return fail(SGP_E_HIP, std::string(#x) + ": " + hipGetErrorString(e_)); \
   } while (0)
 
-enum Kind { KIND_RL = SGP_KIND_RL, KIND_SGP = SGP_KIND_SGP, KIND_OP = 2 };
+enum Kind { KIND_RL = SGP_KIND_RL, KIND_SGP = SGP_KIND_SGP, KIND_OSEM = SGP_KIND_OSEM, KIND_OP = 3 };
+// RL and OSEM share the multiplicative update and the per-iterate KL pass
+static bool em_kind(int kind) { return kind == KIND_RL || kind == KIND_OSEM; }
 
 struct PlanKey {
   int kind, p, NY, NX, ny, nx, oy, ox, boundary, dev;
@@ -58,6 +60,7 @@ struct Plan {
   float* grad = nullptr;
   float* d = nullptr;
   float* invw = nullptr;
+  float* invwj = nullptr;  // boundary OSEM: [p][NY][NX] per-image weights M_R / alpha_j
   float* Af = nullptr;
   float* Ad = nullptr;
   float* aux = nullptr;
@@ -81,7 +84,7 @@ struct Plan {
   int* zmap = nullptr;
 
   ~Plan() {
-    void* ptrs[] = {grad, d, invw, Af, Ad, aux, spec, khat, knyq, tw_row, tw_col, part, counter, st, trace,
+    void* ptrs[] = {grad, d, invw, invwj, Af, Ad, aux, spec, khat, knyq, tw_row, tw_col, part, counter, st, trace,
                     (void*)gtab, (void*)ftab, (void*)psftab, (void*)srctab, btab, zmap};
     for (void* q : ptrs)
       if (q) (void)hipFree(q);
@@ -124,6 +127,7 @@ static int make_plan(const PlanKey& key, hipStream_t s, std::unique_ptr<Plan>& p
   if (key.boundary) {
     if ((rc = dalloc(&pl->invw, nF))) return rc;
     if ((rc = dalloc(&pl->aux, nF * key.p))) return rc;
+    if (key.kind == KIND_OSEM && (rc = dalloc(&pl->invwj, nF * key.p))) return rc;
   } else if (key.kind == KIND_OP) {
     if ((rc = dalloc(&pl->aux, nF))) return rc;
   }
@@ -211,8 +215,8 @@ static int check_params(const sgp_params& p, int kind) {
   if (p.init < SGP_INIT_FLAT || p.init > SGP_INIT_WARM) return fail(SGP_E_INVALID_ARG, "unknown init");
   if ((p.init == SGP_INIT_USER || p.init == SGP_INIT_WARM) && !p.f0)
     return fail(SGP_E_INVALID_ARG, "SGP_INIT_USER / SGP_INIT_WARM need f0");
-  if (kind == KIND_RL && p.init == SGP_INIT_ZERO)
-    return fail(SGP_E_INVALID_ARG, "RL cannot start from the zero image");
+  if (em_kind(kind) && p.init == SGP_INIT_ZERO)
+    return fail(SGP_E_INVALID_ARG, "RL / OSEM cannot start from the zero image");
   if (kind == KIND_SGP) {
     if (!(p.beta > 0 && p.beta < 1)) return fail(SGP_E_INVALID_ARG, "beta must be in (0,1)");
     if (!(p.theta > 0 && p.theta < 1)) return fail(SGP_E_INVALID_ARG, "theta must be in (0,1)");
@@ -454,11 +458,35 @@ static void enqueue_iteration(sgp_solver* S) {
     L.row(ROW_UPD, p, 1, 0, SGP_KCLASS_ROW_UPD);
     L.col(COL_CORRSUM, 1, 1, 1, SGP_KCLASS_COL_CORR, ROW_UPD);
     L.row(ROW_GRAD, 1, 1, 0, SGP_KCLASS_ROW_GRAD, true);
-  } else {
+  } else if (S->kind == KIND_RL) {
     L.col(COL_CONV, 0, 1, 1, SGP_KCLASS_COL_CONV);
     L.row(ROW_RATIO, p, 1, 0, SGP_KCLASS_ROW_RATIO);
     L.col(COL_CORRSUM, 1, 1, 1, SGP_KCLASS_COL_CORR);
     L.row(ROW_RLUPD, 1, 1, 0, SGP_KCLASS_ROW_RLUPD);
+  } else {
+    // OSEM (Algorithm 2): the KL of f^(k) over all images (the stop rules),
+    // whose ratio pass also serves the first sub-step; then for each image j
+    // h <- w_j o h o A_j^T (g_j / (A_j h + b_j)), w_j = 1 (periodic) or
+    // M_R / alpha_j (Eq. boundaryOSEM)
+    L.col(COL_CONV, 0, 1, 1, SGP_KCLASS_COL_CONV);
+    L.row(ROW_RATIO, p, 1, 0, SGP_KCLASS_ROW_RATIO);
+    const Args save = L.base;
+    const long long nF = (long long)S->pb.NY * S->pb.NX;
+    for (int j = 0; j < p; ++j) {
+      L.base.j0 = j;
+      L.base.jn = 1;
+      if (j > 0) {
+        L.col(COL_CONV, 0, 1, 1, SGP_KCLASS_COL_CONV);
+        L.row(ROW_RATIO, 1, 1, 4, SGP_KCLASS_ROW_RATIO);
+      }
+      L.col(COL_CORRSUM, 1, 1, 1, SGP_KCLASS_COL_CORR);
+      L.base.j0 = 0;
+      L.base.jn = 0;
+      if (S->pb.boundary) L.base.invw = S->pl->invwj + (long long)j * nF;
+      else L.base.invw_s = 1.0f;
+      L.row(ROW_RLUPD, 1, 1, 0, SGP_KCLASS_ROW_RLUPD);
+      L.base = save;
+    }
   }
 }
 
@@ -492,6 +520,10 @@ static int setup(sgp_solver* S) {
     Args save = L.base;
     L.base.d = S->pl->invw;
     L.pix(PIX_INVW, nF, 0);
+    if (S->kind == KIND_OSEM) {
+      L.base.d = S->pl->invwj;
+      L.pix(PIX_INVWJ, nF, 0);
+    }
     L.base = save;
   }
   const int init = S->prm.init;
@@ -561,13 +593,13 @@ static int step(sgp_solver* S, int n, int* done_out) {
     return 0;
   }
   launch_resume(S->pl->st, n, S->nitems, S->s);
-  if (S->kind == KIND_RL) {
-    // the spectrum of f is rebuilt so a resumed RL call starts from f
+  if (em_kind(S->kind)) {
+    // the spectrum of f is rebuilt so a resumed RL / OSEM call starts from f
     src_iterate(S);
     S->L.row(ROW_FIELD, 1, 0);
   }
   const bool early = (S->prm.stop & (SGP_STOP_CONV | SGP_STOP_DISCREPANCY)) != 0;
-  const int iters = (S->kind == KIND_RL) ? n + 1 : n;  // RL evaluates J once more before pausing
+  const int iters = em_kind(S->kind) ? n + 1 : n;  // RL / OSEM evaluate J once more before pausing
   if (S->L.timing || !S->use_graph) {
     for (int it = 0; it < iters; ++it) {
       enqueue_iteration(S);
@@ -683,7 +715,7 @@ static int create_items(int kind, const std::vector<Problem>& items, const std::
   if (n < 1) return fail(SGP_E_INVALID_ARG, "no problem given");
   for (int i = 0; i < n; ++i)
     if (!fs[i]) return fail(SGP_E_INVALID_ARG, "f must be non-null");
-  if (kind != KIND_RL && kind != KIND_SGP) return fail(SGP_E_INVALID_ARG, "unknown solver kind");
+  if (kind != KIND_RL && kind != KIND_SGP && kind != KIND_OSEM) return fail(SGP_E_INVALID_ARG, "unknown solver kind");
   for (const Problem& q : items)
     if ((rc = check_problem(q))) return rc;
   if (n > 1) {
@@ -822,7 +854,7 @@ static int batch_run(int kind, const sgp_problem* probs, int n, float* const* fo
     idx.push_back(kv.second);
   }
   const int max_iter = sol[0]->prm.max_iter;
-  const int iters = kind == KIND_RL ? max_iter + 1 : max_iter;
+  const int iters = em_kind(kind) ? max_iter + 1 : max_iter;
   hipStream_t s0 = sol[0]->s;
   for (auto& S : sol) launch_resume(S->pl->st, max_iter, S->nitems, S->s);
   // the first group's stream carries the graph; the others fork from it
@@ -1038,6 +1070,17 @@ int rl_boundary_deconv(const float* g, const float* psf, const float* b_map, con
                        int ny, int nx, int NY, int NX, int oy, int ox, const sgp_params* prm, float* f,
                        sgp_report* rep, void* hip_stream) {
   SGP_GUARD(stack(KIND_RL, g, psf, b_map, b_const, p, ny, nx, NY, NX, oy, ox, 1, prm, f, rep, hip_stream));
+}
+
+int osem_deconv(const float* g, const float* psf, const float* b_map, const float* b_const, int p, int ny,
+                int nx, const sgp_params* prm, float* f, sgp_report* rep, void* hip_stream) {
+  SGP_GUARD(stack(KIND_OSEM, g, psf, b_map, b_const, p, ny, nx, ny, nx, 0, 0, 0, prm, f, rep, hip_stream));
+}
+
+int osem_boundary_deconv(const float* g, const float* psf, const float* b_map, const float* b_const, int p,
+                         int ny, int nx, int NY, int NX, int oy, int ox, const sgp_params* prm, float* f,
+                         sgp_report* rep, void* hip_stream) {
+  SGP_GUARD(stack(KIND_OSEM, g, psf, b_map, b_const, p, ny, nx, NY, NX, oy, ox, 1, prm, f, rep, hip_stream));
 }
 
 int sgp_apply_operator(const float* psf, const float* x, int ny, int nx, int adjoint, float* out,
