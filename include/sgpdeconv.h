@@ -233,7 +233,7 @@ int sgp_solver_report(sgp_solver* s, sgp_report* rep);
 #define SGP_KCLASS_ROW_DIR 0      /* scaling, projection, direction + row FFT */
 #define SGP_KCLASS_COL_CONV 1     /* column FFT x K x IFFT */
 #define SGP_KCLASS_ROW_AD 2       /* row IFFT -> A d, Armijo candidates */
-#define SGP_KCLASS_ARMIJO_MORE 3  /* further Armijo candidates, two launches (early exit if not needed) */
+#define SGP_KCLASS_ARMIJO_MORE 3  /* Armijo test of lambda = 1, theta; further candidates only when both fail */
 #define SGP_KCLASS_ROW_UPD 4      /* update f, A f, residual change + row FFT */
 #define SGP_KCLASS_COL_CORR 5     /* column FFT x conj K x IFFT, summed over images */
 #define SGP_KCLASS_ROW_GRAD 6     /* row IFFT -> gradient, BB sums */
@@ -247,14 +247,16 @@ int sgp_solver_set_graph(sgp_solver* s, int enable);
 int sgp_solver_timing(sgp_solver* s, double* ms, long long* counts, int ncls);
 int sgp_solver_destroy(sgp_solver* s);
 
-/* Many single-image periodic problems in one run (images of uneven sizes).
- * probs[i]: p = 1, boundary = 0, b_map = NULL (constant background
- * b_const[0]); f[i]: device [ny][nx] iterate of problem i; f0: NULL or
+/* Many single-image problems in one run (images of uneven sizes, periodic
+ * or boundary-corrected).  probs[i]: p = 1, b_map = NULL (constant
+ * background b_const[0]); boundary problems give their FFT domain and window
+ * (NY, NX, oy, ox).  f[i]: device [NY][NX] iterate of problem i; f0: NULL or
  * per-problem starts for SGP_INIT_USER / SGP_INIT_WARM.  Problems of one
- * shape form one batched solver (every launch covers all of them); all
- * shapes advance together in one HIP graph of parallel branches, replayed
- * until every problem has met its own stop rule.  reps: n reports (optional).
- * Returns the most severe per-problem code.  kind: SGP_KIND_SGP, _RL or _OSEM. */
+ * shape (window, domain and offsets) form one batched solver (every launch
+ * covers all of them); all shapes advance together in one HIP graph of
+ * parallel branches, replayed until every problem has met its own stop rule.
+ * reps: n reports (optional).  Returns the most severe per-problem code.
+ * kind: SGP_KIND_SGP, _RL or _OSEM. */
 int sgp_batch_deconv(int kind, const sgp_problem* probs, int n, float* const* f, const float* const* f0,
                      const sgp_params* prm, sgp_report* reps, void* hip_stream);
 

@@ -42,6 +42,8 @@ __device__ __forceinline__ Args batch_view(const Args& in) {
     a.bvec = in.bvec + b;  // one image per item
     a.grad += b * in.item_field;
     a.d += b * in.item_field;
+    if (a.invw) a.invw += b * in.item_field;      // boundary items
+    if (a.aux) a.aux += b * in.item_field * in.p;
     a.Af += b * in.item_obs;
     if (a.Ad) a.Ad += b * in.item_obs;
     a.spec += b * in.item_spec;

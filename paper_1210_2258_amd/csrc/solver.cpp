@@ -17,6 +17,7 @@
 #include <mutex>
 #include <string>
 #include <tuple>
+#include <array>
 #include <vector>
 
 #include "../../include/sgpdeconv.h"
@@ -827,14 +828,15 @@ static int create(int kind, const Problem& pb, const sgp_params* prm_in, float* 
 static int batch_run(int kind, const sgp_problem* probs, int n, float* const* fout, const float* const* f0s,
                      const sgp_params* prm, sgp_report* reps, void* stream) {
   if (!probs || n < 1 || !fout) return fail(SGP_E_INVALID_ARG, "need n >= 1 problems and outputs");
-  std::map<std::pair<int, int>, std::vector<int>> groups;
+  std::map<std::array<int, 7>, std::vector<int>> groups;  // by shape: ny, nx, NY, NX, oy, ox, boundary
   std::vector<Problem> all(n);
   int rc;
   for (int i = 0; i < n; ++i) {
     if ((rc = to_problem(&probs[i], all[i]))) return rc;
-    if (all[i].p != 1 || all[i].boundary || all[i].bmap)
-      return fail(SGP_E_INVALID_ARG, "batched problems must be single periodic images with constant background");
-    groups[{all[i].ny, all[i].nx}].push_back(i);
+    if (all[i].p != 1 || all[i].bmap)
+      return fail(SGP_E_INVALID_ARG, "batched problems must be single images with constant background");
+    const Problem& q = all[i];
+    groups[{q.ny, q.nx, q.NY, q.NX, q.oy, q.ox, q.boundary}].push_back(i);
   }
   std::lock_guard<std::mutex> lock(g_mutex);
   std::vector<std::unique_ptr<sgp_solver>> sol;
