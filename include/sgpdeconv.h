@@ -260,6 +260,22 @@ int sgp_solver_destroy(sgp_solver* s);
 int sgp_batch_deconv(int kind, const sgp_problem* probs, int n, float* const* f, const float* const* f0,
                      const sgp_params* prm, sgp_report* reps, void* hip_stream);
 
+/* Mosaic of boundary-corrected subdomains (the second experiment of
+ * Sect. 4.1; Sect. 2.4 for each subdomain).  The H x W image g (device,
+ * row-major) is cut into core x core tiles (H, W multiples of core); tile
+ * (i, j) is reconstructed from the window of g that extends the tile by
+ * `margin` pixels towards its neighbours (clipped at the image edge), placed
+ * at the centre of an N x N FFT domain with the N x N PSF psf (device, centre
+ * (N/2, N/2)) and constant background b, by the boundary-corrected method
+ * `kind` (SGP_KIND_SGP, _RL or _OSEM); all windows run as one batch and the
+ * tile cores are written into f (device H x W).  Needs core + 2 margin <= N
+ * and N a supported FFT size.  rep (optional): iterations and stop reason of
+ * the longest-running tile, KL and backtracks summed over the tiles, the
+ * largest tile discrepancy.  Staging memory is allocated per call.  Errors as
+ * sgp_batch_deconv. */
+int sgp_mosaic_deconv(int kind, const float* g, int H, int W, const float* psf, int N, float b, int core,
+                      int margin, const sgp_params* prm, float* f, sgp_report* rep, void* hip_stream);
+
 /* The steplength rule of Sect. 2.1 exactly as the device runs it, callable on
  * the host for validation.  k: index of the iteration just completed;
  * alpha: steplength used in it; Q/nQ: memory of alpha^(2) values (oldest

@@ -71,7 +71,7 @@ EXPORTS = [
     "sgp_boundary_deconv", "rl_boundary_deconv", "sgp_apply_operator", "sgp_release_cache",
     "sgp_strerror", "sgp_last_error", "sgp_solver_create", "sgp_solver_step", "sgp_solver_report",
     "sgp_solver_set_timing", "sgp_solver_set_graph", "sgp_solver_timing", "sgp_solver_destroy",
-    "sgp_steplength_rule", "sgp_batch_deconv", "osem_deconv", "osem_boundary_deconv",
+    "sgp_steplength_rule", "sgp_batch_deconv", "osem_deconv", "osem_boundary_deconv", "sgp_mosaic_deconv",
     "sgp_cnn_num_params", "sgp_cnn_create", "sgp_cnn_get_params", "sgp_cnn_infer", "sgp_cnn_loss_grad",
     "sgp_cnn_adam_step", "sgp_cnn_train_step", "sgp_cnn_destroy",
 ]
@@ -106,6 +106,7 @@ def load():
     lib.sgp_solver_destroy.argtypes = [vp]
     lib.sgp_batch_deconv.argtypes = [i, ctypes.POINTER(_Problem), i, ctypes.POINTER(vp), ctypes.POINTER(vp), P,
                                      ctypes.POINTER(_Report), vp]
+    lib.sgp_mosaic_deconv.argtypes = [i, vp, i, i, vp, i, f, i, i, P, vp, R, vp]
     lib.sgp_steplength_rule.argtypes = [P, i, d, d, ctypes.POINTER(d), i, d, d, d, d, ctypes.POINTER(d)]
     sz, fp = ctypes.c_size_t, ctypes.POINTER(ctypes.c_float)
     lib.sgp_cnn_num_params.argtypes = []
@@ -283,6 +284,28 @@ def osem_deconv(g, psf, b, *, b_map=None, f=None, stream=None, trace=False, **pa
 def osem_boundary_deconv(g, psf, b, domain, *, b_map=None, f=None, stream=None, trace=False, **params):
     """OSEM with boundary-effect correction (Eq. boundaryOSEM); domain = (NY, NX, oy, ox)."""
     return _solve_stack(load().osem_boundary_deconv, g, psf, b, b_map, f, stream, trace, params, domain)
+
+
+def mosaic_deconv(g, psf, b, core, margin, *, kind=KIND_SGP, f=None, stream=None, **params):
+    """Mosaic of boundary-corrected subdomains: g [H, W], psf [N, N] (the FFT
+    domain of every window); returns (f [H, W], report)."""
+    import torch
+    _check_dev(g, "g")
+    _check_dev(psf, "psf")
+    H, W = g.shape
+    N = psf.shape[-1]
+    if psf.shape != (N, N):
+        raise ValueError("psf must be N x N")
+    if f is None:
+        f = torch.empty_like(g)
+    _check_dev(f, "f")
+    prm, _, _ = _make_params(params, None)
+    rep = _Report()
+    rc = load().sgp_mosaic_deconv(int(kind), ctypes.c_void_p(g.data_ptr()), H, W, ctypes.c_void_p(psf.data_ptr()),
+                                  N, ctypes.c_float(float(b)), int(core), int(margin), ctypes.byref(prm),
+                                  ctypes.c_void_p(f.data_ptr()), ctypes.byref(rep), _stream(stream))
+    _raise(rc)
+    return f, _report(rep, rc, None)
 
 
 def apply_operator(psf, x, adjoint=False, out=None, stream=None):

@@ -1017,6 +1017,113 @@ int sgp_params_init(sgp_params* p) {
   return SGP_OK;
 }
 
+// Mosaic of boundary-corrected subdomains: every core x core tile of the
+// image is reconstructed from a window extended by `margin` pixels towards its
+// neighbours (clipped at the image edge), placed at the centre of an N x N
+// FFT domain; all windows run as one batch and the cores are stitched.
+static int mosaic_run(int kind, const float* g, int H, int W, const float* psf, int N, float b, int core,
+                      int margin, const sgp_params* prm, float* f, sgp_report* rep, void* stream) {
+  if (!g || !psf || !f) return fail(SGP_E_INVALID_ARG, "null pointer");
+  if (core < 1 || margin < 0 || H < core || W < core || H % core || W % core)
+    return fail(SGP_E_INVALID_ARG, "H and W must be positive multiples of core, margin >= 0");
+  if (core + 2 * margin > N) return fail(SGP_E_INVALID_ARG, "a window (core + 2 margin) must fit in N");
+  if (!size_supported(N)) return fail(SGP_E_UNSUPPORTED_SIZE, "unsupported FFT size N");
+  if (!(b >= 0) || !std::isfinite(b)) return fail(SGP_E_BAD_DATA, "background must be finite and >= 0");
+  hipStream_t s = (hipStream_t)stream;
+  struct Tile { int cy, cx, y0, y1, x0, x1, oy, ox; };
+  std::vector<Tile> tiles;
+  for (int i = 0; i < H / core; ++i)
+    for (int j = 0; j < W / core; ++j) {
+      Tile t;
+      t.cy = i * core;
+      t.cx = j * core;
+      t.y0 = std::max(0, t.cy - margin);
+      t.y1 = std::min(H, t.cy + core + margin);
+      t.x0 = std::max(0, t.cx - margin);
+      t.x1 = std::min(W, t.cx + core + margin);
+      t.oy = (N - (t.y1 - t.y0)) / 2;
+      t.ox = (N - (t.x1 - t.x0)) / 2;
+      tiles.push_back(t);
+    }
+  const int n = (int)tiles.size();
+  // staging: the windows (contiguous) and the per-tile iterates on N x N
+  size_t gtot = 0;
+  std::vector<size_t> goff(n);
+  for (int t = 0; t < n; ++t) {
+    goff[t] = gtot;
+    gtot += (size_t)(tiles[t].y1 - tiles[t].y0) * (tiles[t].x1 - tiles[t].x0);
+  }
+  float* gst = nullptr;
+  float* fst = nullptr;
+  int rc = 0;
+  if ((rc = dalloc(&gst, gtot))) return rc;
+  if ((rc = dalloc(&fst, (size_t)n * N * N))) {
+    (void)hipFree(gst);
+    return rc;
+  }
+  std::vector<sgp_problem> probs(n);
+  std::vector<float*> fp(n);
+  std::vector<sgp_report> reps(n);
+  const float bc[1] = {b};
+  hipError_t e = hipSuccess;
+  for (int t = 0; t < n && e == hipSuccess; ++t) {
+    const Tile& q = tiles[t];
+    const int wy = q.y1 - q.y0, wx = q.x1 - q.x0;
+    e = hipMemcpy2DAsync(gst + goff[t], sizeof(float) * wx, g + (size_t)q.y0 * W + q.x0, sizeof(float) * W,
+                         sizeof(float) * wx, wy, hipMemcpyDeviceToDevice, s);
+    sgp_problem& pr = probs[t];
+    pr.g = gst + goff[t];
+    pr.psf = psf;
+    pr.b_map = nullptr;
+    pr.b_const = bc;
+    pr.p = 1;
+    pr.ny = wy;
+    pr.nx = wx;
+    pr.NY = N;
+    pr.NX = N;
+    pr.oy = q.oy;
+    pr.ox = q.ox;
+    pr.boundary = 1;
+    fp[t] = fst + (size_t)t * N * N;
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) rc = fail(SGP_E_HIP, std::string("window copy: ") + hipGetErrorString(e));
+  if (!rc) rc = batch_run(kind, probs.data(), n, fp.data(), nullptr, prm, reps.data(), stream);
+  if (rc >= 0) {
+    for (int t = 0; t < n && e == hipSuccess; ++t) {
+      const Tile& q = tiles[t];
+      const int ry = q.oy + (q.cy - q.y0), rx = q.ox + (q.cx - q.x0);
+      e = hipMemcpy2DAsync(f + (size_t)q.cy * W + q.cx, sizeof(float) * W, fp[t] + (size_t)ry * N + rx,
+                           sizeof(float) * N, sizeof(float) * core, core, hipMemcpyDeviceToDevice, s);
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) rc = fail(SGP_E_HIP, std::string("stitching: ") + hipGetErrorString(e));
+  }
+  if (rep && rc >= 0) {
+    // the tile that ran longest gives iters and stop_reason; KL values and
+    // backtracks are summed over the tiles (windows overlap), the
+    // discrepancy is the largest of the tiles'
+    sgp_report r{};
+    for (int t = 0; t < n; ++t) {
+      if (t == 0 || reps[t].iters > r.iters) {
+        r.iters = reps[t].iters;
+        r.stop_reason = reps[t].stop_reason;
+      }
+      r.backtracks += reps[t].backtracks;
+      r.used_fallback += reps[t].used_fallback;
+      r.kl += reps[t].kl;
+      r.discrepancy = std::max(r.discrepancy, reps[t].discrepancy);
+      r.seconds = std::max(r.seconds, reps[t].seconds);
+    }
+    r.L1 = reps[0].L1;
+    r.L2 = reps[0].L2;
+    *rep = r;
+  }
+  (void)hipFree(gst);
+  (void)hipFree(fst);
+  return rc;
+}
+
 #define SGP_GUARD(expr)                                      \
   try {                                                      \
     return (expr);                                           \
@@ -1153,6 +1260,11 @@ int sgp_solver_destroy(sgp_solver* s) {
 int sgp_batch_deconv(int kind, const sgp_problem* probs, int n, float* const* f, const float* const* f0,
                      const sgp_params* prm, sgp_report* reps, void* hip_stream) {
   SGP_GUARD(batch_run(kind, probs, n, f, f0, prm, reps, hip_stream));
+}
+
+int sgp_mosaic_deconv(int kind, const float* g, int H, int W, const float* psf, int N, float b, int core,
+                      int margin, const sgp_params* prm, float* f, sgp_report* rep, void* hip_stream) {
+  SGP_GUARD(mosaic_run(kind, g, H, W, psf, N, b, core, margin, prm, f, rep, hip_stream));
 }
 
 int sgp_steplength_rule(const sgp_params* prm, int k, double alpha, double tau, const double* Q, int nQ,
