@@ -59,6 +59,9 @@ def parse():
     ap.add_argument("--no-ttd", action="store_true", help="skip the time-to-discrepancy runs")
     ap.add_argument("--batch-images", type=int, default=512)
     ap.add_argument("--no-multi", action="store_true", help="skip the multi-image RL / OSEM / SGP comparison")
+    ap.add_argument("--no-mosaic", action="store_true", help="skip the mosaic leg")
+    ap.add_argument("--sweep", action="store_true",
+                    help="also run the Fourier re-binning size sweep 256..2048 (RL and SGP, GPU and oracle)")
     return ap.parse_args()
 
 
@@ -143,9 +146,9 @@ def time_to_discrepancy(torch, m, g, psf, b):
     f_rl, rrep = m.rl_deconv(g, psf, b, max_iter=20000, stop=m.STOP_DISCREPANCY)
     torch.cuda.synchronize()
     ttd_rl = time.perf_counter() - t3
-    return {"time_to_discrepancy_s": ttd, "iters_to_discrepancy": drep["iters"],
-            "discrepancy_final": drep["discrepancy"], "kl_final": drep["kl"],
-            "rl_time_to_discrepancy_s": ttd_rl, "rl_iters_to_discrepancy": rrep["iters"]}
+    return ({"time_to_discrepancy_s": ttd, "iters_to_discrepancy": drep["iters"],
+             "discrepancy_final": drep["discrepancy"], "kl_final": drep["kl"],
+             "rl_time_to_discrepancy_s": ttd_rl, "rl_iters_to_discrepancy": rrep["iters"]}, f_out)
 
 
 def multi_image_legs(torch, m, w):
@@ -167,6 +170,77 @@ def multi_image_legs(torch, m, w):
                      "kl": rep["kl"], "discrepancy": rep["discrepancy"]}
     out["speedup_sgp_vs_rl"] = out["rl"]["seconds"] / out["sgp"]["seconds"]
     out["speedup_osem_vs_rl"] = out["rl"]["seconds"] / out["osem"]["seconds"]
+    return out
+
+
+def mosaic_leg(torch, m, w, g, psf, f_full):
+    """The 2048^2 galaxy field as a mosaic of four 1024^2 cores seen through
+    windows with 128-pixel margins on 1280^2 domains (one batch of boundary
+    problems), SGP to the discrepancy stop of every window; compared with the
+    full-image reconstruction f_full."""
+    N, core, margin = 1280, 1024, 128
+    c0 = (psf.shape[0] - N) // 2
+    psf_N = psf[c0:c0 + N, c0:c0 + N].contiguous()
+    m.mosaic_deconv(g, psf_N, float(w.b[0]), core, margin, max_iter=2)  # workspaces
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    f, rep = m.mosaic_deconv(g, psf_N, float(w.b[0]), core, margin, max_iter=5000, stop=m.STOP_DISCREPANCY)
+    torch.cuda.synchronize()
+    secs = time.perf_counter() - t0
+    diff = float(torch.linalg.vector_norm(f - f_full) / torch.linalg.vector_norm(f_full))
+    return {"tiles": 4, "core": core, "margin": margin, "fft_domain": N, "seconds": secs,
+            "iterations_longest_tile": rep["iters"], "max_tile_discrepancy": rep["discrepancy"],
+            "rel_l2_vs_full_image": diff}
+
+
+def rebin_sweep(torch, m, with_oracle):
+    """Sizes 256..2048 made by Fourier re-binning of the 256^2 galaxy field;
+    RL and SGP run at every size for the iteration counts the discrepancy rule
+    gives at 256^2 (the procedure of the paper's third experiment).  Reports
+    GPU seconds per run (call to return, setup included), the SGP-over-RL
+    speedup ("Alg") and, with the oracle, its seconds per run on one host core
+    extrapolated from two timed iterations ("Par" = oracle / GPU)."""
+    from synth import workloads as W
+    series = W.rebin_series(W.rebin_base(size=256, total=1e6))
+    out = {"object": "galaxy field drawn at 256^2 (1e6 counts, Airy PSF with first zero at 4 px, b = 50), "
+                     "re-binned by 2x steps to 2048^2", "sizes": {}}
+    counts = {}
+    for n, g_h, psf_h in series:
+        g = torch.from_numpy(g_h).cuda()
+        psf = torch.from_numpy(psf_h).cuda()
+        row = {}
+        for name, fn in (("rl", m.rl_deconv), ("sgp", m.sgp_deconv)):
+            if name not in counts:  # fixed from the 256^2 case by the discrepancy rule
+                _, r = fn(g, psf, 50.0, max_iter=20000, stop=m.STOP_DISCREPANCY)
+                counts[name] = max(r["iters"], 1)
+            fn(g, psf, 50.0, max_iter=2)  # workspace of this size
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, r = fn(g, psf, 50.0, max_iter=counts[name])
+            torch.cuda.synchronize()
+            row[name] = {"iterations": counts[name], "gpu_seconds": time.perf_counter() - t0, "kl": r["kl"]}
+        row["alg_speedup_sgp_vs_rl"] = row["rl"]["gpu_seconds"] / row["sgp"]["gpu_seconds"]
+        if with_oracle:
+            from oracle import sgp as O
+            P = O.Problem(g_h, psf_h, 50.0)
+            f0 = P.start("flat")
+            for name in ("rl", "sgp"):
+                t0 = time.perf_counter()
+                if name == "rl":
+                    P.rl(f0, 0)
+                else:
+                    P.sgp(f0, O.Params(max_iter=0))
+                t1 = time.perf_counter()
+                if name == "rl":
+                    P.rl(f0, 2)
+                else:
+                    P.sgp(f0, O.Params(max_iter=2))
+                t2 = time.perf_counter()
+                per_it = max((t2 - t1) - (t1 - t0), 1e-9) / 2
+                est = (t1 - t0) + per_it * counts[name]
+                row[name]["oracle_seconds_estimated"] = est
+                row[name]["par_speedup"] = est / row[name]["gpu_seconds"]
+        out["sizes"][str(n)] = row
     return out
 
 
@@ -284,8 +358,9 @@ def main():
     iter_roofline = ITER_BYTES_PER_PX * npx / (ms_per_step * 1e-3) / 1e9
 
     out_ttd = {}
+    f_full = None
     if not args.no_ttd:
-        out_ttd = time_to_discrepancy(torch, m, g, psf, b)
+        out_ttd, f_full = time_to_discrepancy(torch, m, g, psf, b)
     traffic = counter_traffic(dom, npx)
     
     out = {
@@ -318,6 +393,10 @@ def main():
         out["batch_512"] = batch_legs(torch, m, batch_items)
     if not args.no_multi:
         out["multi_image_3x1024"] = multi_image_legs(torch, m, W.config2())
+    if not args.no_mosaic and f_full is not None:
+        out["mosaic_2048"] = mosaic_leg(torch, m, w, g, psf, f_full)
+    if args.sweep:
+        out["rebin_sweep"] = rebin_sweep(torch, m, with_oracle=not args.no_cpu)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_iters)
     print(json.dumps(out))

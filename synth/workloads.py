@@ -250,3 +250,46 @@ def small_boundary(NY=80, NX=64, ny=64, nx=48, oy=8, ox=8, sigma=2.0, b=8.0, see
     g = rng_for(102, seed, "noise").poisson(lam).astype(np.float32)
     return Workload(f"smallbnd_{ny}x{nx}_in_{NY}x{NX}", g[None], psf.astype(np.float32)[None],
                     np.array([b], np.float32), obj, domain=(NY, NX, oy, ox))
+
+
+# ---------------------------------------------------- Fourier re-binning
+def rebin_fourier(img):
+    """Doubles the size of an image by Fourier re-binning (Sect. 4.1, third
+    experiment): its FFT is zero-padded to twice the size (centred), the
+    zero-frequency coefficient is multiplied by four, and the real part of
+    the inverse FFT is returned.  The mean level stays the same; no new high
+    frequencies appear.  Ringing below zero is clipped (the solvers need
+    g >= 0)."""
+    a = np.asarray(img, dtype=np.float64)
+    ny, nx = a.shape
+    F = np.fft.fftshift(np.fft.fft2(a))
+    G = np.zeros((2 * ny, 2 * nx), dtype=complex)
+    G[ny // 2:ny // 2 + ny, nx // 2:nx // 2 + nx] = F
+    G = np.fft.ifftshift(G)
+    G[0, 0] *= 4.0
+    return np.maximum(np.real(np.fft.ifft2(G)), 0.0)
+
+
+def rebin_base(size=256, total=1e7, r0=4.0, b=50.0):
+    """Starting image of the size sweep: the galaxy field of the 2048^2
+    workload drawn at size^2 with total counts `total`, blurred by an Airy PSF
+    whose first zero is at r0 pixels (as at 2048^2), background b, Poisson noise."""
+    base = config1(size=size, total=total)
+    psf = airy_psf(size, size, r0)
+    g = _observe(base.f_true, psf, b, rng_for(5, size, "noise"))
+    return Workload(f"rebin_base_{size}", g[None], psf.astype(np.float32)[None], np.array([b], np.float32),
+                    base.f_true)
+
+
+def rebin_series(w, sizes=(256, 512, 1024, 2048)):
+    """[(size, g, psf)] starting from a single-image workload of the first
+    size, each next one the Fourier re-binning of the previous (PSF re-binned
+    the same way and renormalised to unit sum)."""
+    g, psf = w.g[0].astype(np.float64), w.psf[0].astype(np.float64)
+    out = [(g.shape[0], g.astype(np.float32), psf.astype(np.float32))]
+    while out[-1][0] < sizes[-1]:
+        g = rebin_fourier(g)
+        psf = rebin_fourier(psf)
+        psf /= psf.sum()
+        out.append((g.shape[0], g.astype(np.float32), psf.astype(np.float32)))
+    return [o for o in out if o[0] in sizes]
