@@ -134,6 +134,57 @@ __global__ __launch_bounds__(NT) void conv_fwd_kernel(const float* __restrict__ 
   for (int co = 0; co < COUT; ++co) ob[co * N] = RELU ? fmaxf(acc[co], 0.f) : acc[co];
 }
 
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+// relu(conv 16 -> 16 (in)) on the matrix cores: a workgroup of four waves
+// computes one 16x16 output tile as an implicit GEMM, output pixels x output
+// channels x K, K = 16 input channels x 25 taps, in FP32 MFMA steps of
+// 16 pixels x 16 channels x 4 (v_mfma_f32_16x16x4_f32: lane l supplies
+// A[l % 16][l / 16] and B[l / 16][l % 16] and receives D[4 (l / 16) + r][l % 16]
+// in register r).  Wave w owns tile rows 4w .. 4w + 3, one 16-pixel row per
+// accumulator.  grid (W/T, H/T, images)
+__global__ __launch_bounds__(NT) void conv16_mfma_kernel(const float* __restrict__ in, const float* __restrict__ w,
+                                                         const float* __restrict__ bias, float* __restrict__ out,
+                                                         int H, int W) {
+  constexpr int KK = C * K * K;  // 400
+  __shared__ float tile[C][TH][TH];
+  __shared__ float wk[KK][C];    // weights as [ci * 25 + ky * 5 + kx][co]
+  const int img = blockIdx.z;
+  const int x0 = blockIdx.x * T, y0 = blockIdx.y * T;
+  const long long N = (long long)H * W;
+  const float* inb = in + (long long)img * C * N;
+  for (int i = threadIdx.x; i < C * TH * TH; i += NT) {
+    const int c = i / (TH * TH), r = (i / TH) % TH, q = i % TH;
+    tile[c][r][q] = inb[c * N + (long long)wrap(y0 + r - 2, H) * W + wrap(x0 + q - 2, W)];
+  }
+  for (int i = threadIdx.x; i < KK * C; i += NT) wk[i % KK][i / KK] = w[i];
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  floatx4 acc[4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) acc[r] = floatx4{0.f, 0.f, 0.f, 0.f};
+  for (int s = 0; s < KK / 4; ++s) {
+    const int k = 4 * s + lk;
+    const int ci = k / (K * K), t = k % (K * K), ky = t / K, kx = t % K;
+    const float b = wk[k][li];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const float a = tile[ci][4 * wave + r + ky][li + kx];
+      acc[r] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc[r], 0, 0, 0);
+    }
+  }
+  // acc[r][q]: channel li at pixel (4 wave + r, 4 lk + q) of the tile
+  const float bc = bias[li];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    float4 v = make_float4(fmaxf(acc[r][0] + bc, 0.f), fmaxf(acc[r][1] + bc, 0.f), fmaxf(acc[r][2] + bc, 0.f),
+                           fmaxf(acc[r][3] + bc, 0.f));
+    float* o = out + ((long long)img * C + li) * N + (long long)(y0 + 4 * wave + r) * W + x0 + 4 * lk;
+    *reinterpret_cast<float4*>(o) = v;
+  }
+}
+
 // din[ci](q) = sum_co sum_k W[co][ci][k] dout[co](q - k + 2), times the ReLU
 // mask (act > 0) of the layer input.  grid (W/T, H/T, images)
 template <int CIN, int COUT>
@@ -435,8 +486,8 @@ static int forward(Net* net, int n, int H, int W, bool train, hipStream_t s) {
   const dim3 grid(W / T, H / T, n);
   float* a3 = train ? net->a[2] : net->a[0];
   hipLaunchKernelGGL((conv_fwd_kernel<1, C, true>), grid, dim3(NT), 0, s, net->x, wl(net, 0), bl(net, 0), net->a[0], H, W);
-  hipLaunchKernelGGL((conv_fwd_kernel<C, C, true>), grid, dim3(NT), 0, s, net->a[0], wl(net, 1), bl(net, 1), net->a[1], H, W);
-  hipLaunchKernelGGL((conv_fwd_kernel<C, C, true>), grid, dim3(NT), 0, s, net->a[1], wl(net, 2), bl(net, 2), a3, H, W);
+  hipLaunchKernelGGL(conv16_mfma_kernel, grid, dim3(NT), 0, s, net->a[0], wl(net, 1), bl(net, 1), net->a[1], H, W);
+  hipLaunchKernelGGL(conv16_mfma_kernel, grid, dim3(NT), 0, s, net->a[1], wl(net, 2), bl(net, 2), a3, H, W);
   hipLaunchKernelGGL((conv_fwd_kernel<C, 1, false>), grid, dim3(NT), 0, s, a3, wl(net, 3), bl(net, 3), net->o, H, W);
   CNN_HIP(hipGetLastError());
   return 0;
