@@ -11,7 +11,8 @@
 // Several transforms share a workgroup; thread t works on transform t / TF
 // with lane t % TF.  Twiddles come from a per-length table
 // tw[m] = exp(-2 pi i m / L) built once per plan in double precision and
-// rounded to float.  Inverse transforms use conj(FFT(conj(x))).
+// rounded to float, regrouped per pass when a workgroup stages it in LDS
+// (stage_twiddles).  Inverse transforms use conj(FFT(conj(x))).
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -128,6 +129,37 @@ template <> __device__ __forceinline__ void dft<5>(float2* v) {
   v[3] = cadd(t2, mul_pi(u2));
 }
 
+// ---------------------------------------------------------------- twiddles
+// Pass order layout of the twiddles in LDS.  The pass of stride NS > 1 and
+// radix R needs W_{NS R}^{i k} for i = 1 .. R-1 and k = j mod NS; it keeps
+// them at NS - r0 + (i - 1) NS + k.  The lanes of a wave hold consecutive k,
+// so each of their twiddle reads covers consecutive entries and spreads over
+// the LDS banks (a gather from the length-L table at stride i k L / (NS R)
+// puts up to 32 lanes on one bank).  The offsets telescope: all passes
+// together hold L - r0 entries.
+template <int L, int R, int NS>
+__device__ __forceinline__ void stage_pass_tw(float2* twl, const float2* __restrict__ tw, int tid, int nt) {
+  if constexpr (NS > 1 && R > 1) {
+    constexpr int n = (R - 1) * NS, step = L / (NS * R);
+    for (int t = tid; t < n; t += nt) {
+      const int i = t / NS + 1, k = t % NS;
+      twl[NS - FftPlan<L>::r0 + t] = tw[i * k * step];
+    }
+  }
+}
+
+// Stages the twiddles of every pass of FftPlan<L> from the length-L table tw
+// into twl (L entries suffice).  Visible to the workgroup after its next
+// barrier.
+template <int L>
+__device__ __forceinline__ void stage_twiddles(float2* twl, const float2* __restrict__ tw, int tid, int nt) {
+  using P = FftPlan<L>;
+  stage_pass_tw<L, P::r1, P::r0>(twl, tw, tid, nt);
+  if constexpr (P::NP > 2) stage_pass_tw<L, P::r2, P::r0 * P::r1>(twl, tw, tid, nt);
+  if constexpr (P::NP > 3) stage_pass_tw<L, P::r3, P::r0 * P::r1 * P::r2>(twl, tw, tid, nt);
+  if constexpr (P::NP > 4) stage_pass_tw<L, P::r4, P::r0 * P::r1 * P::r2 * P::r3>(twl, tw, tid, nt);
+}
+
 // ------------------------------------------------------------------ passes
 template <int L, int TF, int R, int NS>
 __device__ __forceinline__ void stockham_pass(float2* buf, int lane, const float2* __restrict__ tw) {
@@ -148,7 +180,7 @@ __device__ __forceinline__ void stockham_pass(float2* buf, int lane, const float
     const int k = j % NS;
     if constexpr (NS > 1) {
 #pragma unroll
-      for (int i = 1; i < R; ++i) v[q][i] = cmul(v[q][i], tw[i * k * (L / (NS * R))]);
+      for (int i = 1; i < R; ++i) v[q][i] = cmul(v[q][i], tw[NS - FftPlan<L>::r0 + (i - 1) * NS + k]);
     }
     dft<R>(v[q]);
     const int base = (j / NS) * NS * R + k;
@@ -159,7 +191,8 @@ __device__ __forceinline__ void stockham_pass(float2* buf, int lane, const float
 }
 
 // Forward FFT of buf (logical index i stored at lds_idx<L>(i)) in place,
-// natural order in and out.  Every thread
+// natural order in and out, with the twiddles staged by stage_twiddles<L>.
+// Every thread
 // of the workgroup must call this (it contains barriers).
 template <int L>
 __device__ __forceinline__ void fft_lds(float2* buf, int lane, const float2* __restrict__ tw) {

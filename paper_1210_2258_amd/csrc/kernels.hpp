@@ -406,9 +406,7 @@ __global__ __launch_bounds__(RowCfg<L>::NT) void row_kernel(Args a_in) {
   constexpr int HALF = L / 2;
   constexpr int NS = row_nslots(OP);
   __shared__ float2 buf[RP][L];
-#ifndef SGP_TW_GLOBAL
-  __shared__ float2 twl[L];  // twiddle table staged in LDS
-#endif
+  __shared__ float2 twl[L];  // twiddles staged in LDS in pass order
   DevState* st = a.st;
   if (a.iter && (st->done || st->pause)) return;
   const int tid = threadIdx.x;
@@ -419,12 +417,8 @@ __global__ __launch_bounds__(RowCfg<L>::NT) void row_kernel(Args a_in) {
   // (A, B) of rows y0 + 2q, y0 + 2q + 1 at column k: float4 index 4k + q + (y0 % 8) / 2
   float2* spec = a.spec + (row_per_image(OP) ? j : 0) * sstride + (long long)(y0 >> 3) * HALF * kTile + (y0 & 7);
 
-#ifndef SGP_TW_GLOBAL
   const float2* tw = twl;
-  for (int i = tid; i < L; i += NT) twl[i] = a.tw_row[i];  // visible after the first barrier
-#else
-  const float2* tw = a.tw_row;
-#endif
+  stage_twiddles<L>(twl, a.tw_row, tid, NT);  // visible after the first barrier
   double acc[NS > 0 ? NS : 1];
   {
     RowKinds kinds{OP};
@@ -538,9 +532,7 @@ __global__ __launch_bounds__(ColCfg<LY>::NT) void col_kernel(Args a_in) {
   constexpr int NT = ColCfg<LY>::NT;
   constexpr int E = LY * C / NT;  // units per thread
   __shared__ float2 buf[C][LY];
-#ifndef SGP_TW_GLOBAL
-  __shared__ float2 twl[LY];  // twiddle table staged in LDS
-#endif
+  __shared__ float2 twl[LY];  // twiddles staged in LDS in pass order
   DevState* st = a.st;
   if (a.iter && (st->done || st->pause)) return;
   // the first workgroup of each item finishes the preceding row kernel's
@@ -551,12 +543,8 @@ __global__ __launch_bounds__(ColCfg<LY>::NT) void col_kernel(Args a_in) {
   const int tid = threadIdx.x;
   const long long sstride = spec_elems(a.NY, a.NX);
   const int jin = (MODE == COL_FWD) ? blockIdx.y : 0;
-#ifndef SGP_TW_GLOBAL
   const float2* tw = twl;
-  for (int i = tid; i < LY; i += NT) twl[i] = a.tw_col[i];  // visible after the first barrier
-#else
-  const float2* tw = a.tw_col;
-#endif
+  stage_twiddles<LY>(twl, a.tw_col, tid, NT);  // visible after the first barrier
 
   // unit e of this thread -> (column c, row y) and its offset in the layout
   auto unit = [&](int e, int& c, int& y, long long& off) {
