@@ -128,6 +128,7 @@ enum ColMode {
   COL_CONV,         // spec[0] -> spec[j] = K_j x (or conj K_j x)
   COL_CORRSUM,      // spec[j] -> spec[0] = sum_j conj(K_j) x_j
   COL_CORR1,        // COL_CORRSUM for p = 1 (fewer registers)
+  COL_CONV1,        // COL_CONV of one image (fewer registers)
   COL_NMODES
 };
 

@@ -37,6 +37,10 @@ void SGP_CAT(launch_col_, SGP_L)(int mode, int conj, dim3 grid, const Args& a, h
   constexpr int L = SGP_L;
   const dim3 blk(ColCfg<L>::NT);
   if (mode == COL_FWD) hipLaunchKernelGGL((col_kernel<L, COL_FWD, 0>), grid, blk, 0, s, a);
+  else if (mode == COL_CONV && (a.jn ? a.jn : a.p) == 1) {
+    if (conj) hipLaunchKernelGGL((col_kernel<L, COL_CONV1, 1>), grid, blk, 0, s, a);
+    else hipLaunchKernelGGL((col_kernel<L, COL_CONV1, 0>), grid, blk, 0, s, a);
+  }
   else if (mode == COL_CONV && !conj) hipLaunchKernelGGL((col_kernel<L, COL_CONV, 0>), grid, blk, 0, s, a);
   else if (mode == COL_CONV) hipLaunchKernelGGL((col_kernel<L, COL_CONV, 1>), grid, blk, 0, s, a);
   else if (a.p == 1) hipLaunchKernelGGL((col_kernel<L, COL_CORR1, 1>), grid, blk, 0, s, a);

@@ -647,10 +647,13 @@ __global__ __launch_bounds__(ColCfg<LY>::NT) void col_kernel(Args a_in) {
       }
       __syncthreads();
     }
-  } else if constexpr (MODE == COL_CORR1) {  // COL_CORRSUM for one image
+  } else if constexpr (MODE == COL_CORR1 || MODE == COL_CONV1) {
+    // one image jo: spec[0] -> spec[jo] = K_jo x (or conj K_jo x); the
+    // adjoint of one image (COL_CORRSUM for p = 1) is the case jo = 0, CONJ
+    const int jo = MODE == COL_CONV1 ? a.j0 : 0;
     load(a.spec);
-    const float2* K = a.khat;
-    const float2* KN = a.knyq;
+    const float2* K = a.khat + jo * sstride;
+    const float2* KN = a.knyq + (long long)jo * LY;
     float2 kpre[E];
 #pragma unroll
     for (int e = 0; e < E; ++e) {
@@ -670,9 +673,10 @@ __global__ __launch_bounds__(ColCfg<LY>::NT) void col_kernel(Args a_in) {
         const float2 m = cconj(buf[0][lds_idx<LY>((LY - y) % LY)]);
         const float2 ev = cscale(cadd(v, m), 0.5f);
         const float2 od = cscale(mul_mi(csub(v, m)), 0.5f);
-        pr[e] = cadd(cmulc(ev, kpre[e]), mul_pi(cmulc(od, KN[y])));
+        const float2 kn = KN[y];
+        pr[e] = cadd(CONJ ? cmulc(ev, kpre[e]) : cmul(ev, kpre[e]), mul_pi(CONJ ? cmulc(od, kn) : cmul(od, kn)));
       } else {
-        pr[e] = cmulc(v, kpre[e]);
+        pr[e] = CONJ ? cmulc(v, kpre[e]) : cmul(v, kpre[e]);
       }
     }
     __syncthreads();
@@ -688,7 +692,7 @@ __global__ __launch_bounds__(ColCfg<LY>::NT) void col_kernel(Args a_in) {
     for (int e = 0; e < E; ++e) {
       int c, y; long long off;
       unit(e, c, y, off);
-      if (kx0 + c < NXh) a.spec[off] = cconj(buf[c][lds_idx<LY>(y)]);
+      if (kx0 + c < NXh) a.spec[jo * sstride + off] = cconj(buf[c][lds_idx<LY>(y)]);
     }
   } else {  // COL_CORRSUM
     float2 acc[E];
