@@ -190,6 +190,66 @@ __device__ __forceinline__ void stockham_pass(float2* buf, int lane, const float
   __syncthreads();
 }
 
+// A pass whose inputs come from registers (the first pass, NS = 1) or whose
+// outputs stay in registers (the last pass, NS R = L).  In both, butterfly
+// q of the thread touches elements lane + TF (q + PER i), so register e holds
+// element lane + TF e: x[e] on entry to the first pass, and on exit from the
+// last.  A register-fed first pass writes buf without a barrier before it:
+// the caller makes sure no thread still reads buf.
+template <int L, int TF, int R, int NS, bool FROM_REGS, bool TO_REGS>
+__device__ __forceinline__ void stockham_pass_x(float2* buf, int lane, const float2* __restrict__ tw, float2* x) {
+  constexpr int NB = L / R;
+  constexpr int PER = NB / TF;
+  static_assert(PER * TF == NB, "threads per transform must divide the butterfly count");
+  static_assert(!FROM_REGS || NS == 1, "only the first pass reads registers");
+  static_assert(!TO_REGS || NS * R == L, "only the last pass writes registers");
+  float2 v[PER][R];
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int j = lane + q * TF;
+#pragma unroll
+    for (int i = 0; i < R; ++i) v[q][i] = FROM_REGS ? x[q + PER * i] : buf[lds_idx<L>(j + i * NB)];
+  }
+  if constexpr (!FROM_REGS) __syncthreads();
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int j = lane + q * TF;
+    const int k = j % NS;
+    if constexpr (NS > 1) {
+#pragma unroll
+      for (int i = 1; i < R; ++i) v[q][i] = cmul(v[q][i], tw[NS - FftPlan<L>::r0 + (i - 1) * NS + k]);
+    }
+    dft<R>(v[q]);
+    if constexpr (TO_REGS) {
+#pragma unroll
+      for (int i = 0; i < R; ++i) x[q + PER * i] = v[q][i];
+    } else {
+      const int base = (j / NS) * NS * R + k;
+#pragma unroll
+      for (int i = 0; i < R; ++i) buf[lds_idx<L>(base + i * NS)] = v[q][i];
+    }
+  }
+  if constexpr (!TO_REGS) __syncthreads();
+}
+
+// Forward FFT with the input (IN) and / or the output (OUT) held in
+// registers, x[e] = element lane + TF e of the transform; the other side is
+// buf as in fft_lds.  Saves the LDS round trip of staging the data.  With
+// IN, every thread must have finished reading buf before the call; with OUT,
+// buf is free for writes after the call.
+template <int L, bool IN, bool OUT>
+__device__ __forceinline__ void fft_lds_x(float2* buf, int lane, const float2* __restrict__ tw,
+                                          float2 (&x)[FftPlan<L>::E]) {
+  using P = FftPlan<L>;
+  constexpr int TF = P::TF;
+  constexpr int N0 = 1, N1 = P::r0, N2 = N1 * P::r1, N3 = N2 * P::r2, N4 = N3 * P::r3;
+  stockham_pass_x<L, TF, P::r0, N0, IN, OUT && P::NP == 1>(buf, lane, tw, x);
+  stockham_pass_x<L, TF, P::r1, N1, false, OUT && P::NP == 2>(buf, lane, tw, x);
+  if constexpr (P::NP > 2) stockham_pass_x<L, TF, P::r2, N2, false, OUT && P::NP == 3>(buf, lane, tw, x);
+  if constexpr (P::NP > 3) stockham_pass_x<L, TF, P::r3, N3, false, OUT && P::NP == 4>(buf, lane, tw, x);
+  if constexpr (P::NP > 4) stockham_pass_x<L, TF, P::r4, N4, false, OUT && P::NP == 5>(buf, lane, tw, x);
+}
+
 // Forward FFT of buf (logical index i stored at lds_idx<L>(i)) in place,
 // natural order in and out, with the twiddles staged by stage_twiddles<L>.
 // Every thread

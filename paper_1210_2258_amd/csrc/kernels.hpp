@@ -161,11 +161,21 @@ __device__ __forceinline__ RowScal row_scalars(const DevState* st, int j) {
   return c;
 }
 
-// Units per load chunk: the largest divisor of nu not above 8.
-__host__ __device__ constexpr int row_chunk(int nu) {
-  int c = nu < 8 ? nu : 8;
+// Units per load chunk: the largest divisor of nu not above cap.
+__host__ __device__ constexpr int row_chunk(int nu, int cap = 8) {
+  int c = nu < cap ? nu : cap;
   while (nu % c) --c;
   return c;
+}
+
+#ifndef SGP_XR_UPD_CHUNK
+#define SGP_XR_UPD_CHUNK 0
+#endif
+// Row ops that keep the data between their transforms and the pointwise
+// stage in registers.  The ratio pass and the update hold the most loads in
+// flight; with the transform data on top they would spill.
+__host__ __device__ constexpr bool row_regs_ok(int op) {
+  return op != ROW_RATIO && (op != ROW_UPD || SGP_XR_UPD_CHUNK > 0);
 }
 
 // Global inputs of one pixel of the pointwise stage, loaded ahead of the
@@ -426,6 +436,13 @@ __global__ __launch_bounds__(RowCfg<L>::NT) void row_kernel(Args a_in) {
     for (int s = 0; s < (NS > 0 ? NS : 1); ++s) acc[s] = red_identity(kinds(s));
   }
 
+  // with up to 8 points per thread the data passes between the transforms
+  // and the pointwise stage in registers: thread tid owns pixels
+  // x = lt + TF e (e < E) of row pair qt, the points its first / last FFT
+  // pass reads / writes
+  constexpr bool XR = P::E <= 8 && row_regs_ok(OP);
+  const int qt = tid / TF, lt = tid % TF;
+  float2 xr[P::E];
   if constexpr (row_has_inv(OP)) {
     const float4* S4 = reinterpret_cast<const float4*>(spec);
 #pragma unroll
@@ -441,7 +458,8 @@ __global__ __launch_bounds__(RowCfg<L>::NT) void row_kernel(Args a_in) {
       }
     }
     __syncthreads();
-    fft_lds<L>(buf[tid / TF], tid % TF, tw);
+    if constexpr (XR) fft_lds_x<L, false, true>(buf[qt], lt, tw, xr);
+    else fft_lds<L>(buf[qt], lt, tw);
   }
 
   // pointwise stage in chunks of CH units per thread: every load of a chunk
@@ -450,7 +468,7 @@ __global__ __launch_bounds__(RowCfg<L>::NT) void row_kernel(Args a_in) {
     const RowScal sc = row_scalars<OP>(st, j);
     constexpr int NU = RP * L / NT;  // units (pixel pairs) per thread
     static_assert(NU * NT == RP * L, "threads must tile the rows");
-    constexpr int CH = row_chunk(NU);
+    constexpr int CH = row_chunk(NU, OP == ROW_UPD && XR ? SGP_XR_UPD_CHUNK : 8);
     static_assert(NU % CH == 0, "chunks must tile the units");
 #pragma unroll
     for (int c0 = 0; c0 < NU; c0 += CH) {
@@ -458,30 +476,39 @@ __global__ __launch_bounds__(RowCfg<L>::NT) void row_kernel(Args a_in) {
 #pragma unroll
       for (int c = 0; c < CH; ++c) {
         const int u = tid + (c0 + c) * NT;
-        const int q = u / L, x = u % L;
+        const int q = XR ? qt : u / L, x = XR ? lt + TF * (c0 + c) : u % L;
         in[c][0] = row_load<OP>(a, j, y0 + 2 * q, x);
         in[c][1] = row_load<OP>(a, j, y0 + 2 * q + 1, x);
       }
 #pragma unroll
       for (int c = 0; c < CH; ++c) {
         const int u = tid + (c0 + c) * NT;
-        const int q = u / L, x = u % L;
+        const int q = XR ? qt : u / L, x = XR ? lt + TF * (c0 + c) : u % L;
         const int ya = y0 + 2 * q;
         float2 v = make_float2(0.f, 0.f);
         if constexpr (row_has_inv(OP)) {
-          const float2 w = buf[q][lds_idx<L>(x)];
+          const float2 w = XR ? xr[c0 + c] : buf[q][lds_idx<L>(x)];
           v = make_float2(w.x, -w.y);
         }
         const float ua = row_point<OP, NS>(a, sc, j, ya, x, v.x, in[c][0], acc);
         const float ub = row_point<OP, NS>(a, sc, j, ya + 1, x, v.y, in[c][1], acc);
-        if constexpr (row_has_fwd(OP)) buf[q][lds_idx<L>(x)] = make_float2(ua, ub);
+        if constexpr (row_has_fwd(OP)) {
+          if constexpr (XR) xr[c0 + c] = make_float2(ua, ub);
+          else buf[q][lds_idx<L>(x)] = make_float2(ua, ub);
+        }
       }
     }
   }
 
   if constexpr (row_has_fwd(OP)) {
-    __syncthreads();
-    fft_lds<L>(buf[tid / TF], tid % TF, tw);
+    // (register-fed: the inverse transform's last pass ended its LDS reads
+    // with a barrier, and a forward-only op has not used buf)
+    if constexpr (XR) {
+      fft_lds_x<L, true, false>(buf[qt], lt, tw, xr);
+    } else {
+      __syncthreads();
+      fft_lds<L>(buf[qt], lt, tw);
+    }
     float4* O4 = reinterpret_cast<float4*>(spec);
 #pragma unroll
     for (int u = tid; u < HALF * RP; u += NT) {
@@ -646,6 +673,60 @@ __global__ __launch_bounds__(ColCfg<LY>::NT) void col_kernel(Args a_in) {
         if (kx0 + c < NXh) O[off] = cconj(buf[c][lds_idx<LY>(y)]);
       }
       __syncthreads();
+    }
+  } else if constexpr ((MODE == COL_CORR1 || MODE == COL_CONV1) && C == 1 && E <= 8) {
+    // one column per workgroup: thread tid holds rows tid + TF e in
+    // registers from the load to the store, the points its first and last
+    // FFT passes touch; only the workgroup of column 0 stages the forward
+    // transform in LDS, for the mirrored points of its even / odd split
+    if (kx0 >= NXh) return;  // uniform over the workgroup
+    const int jo = MODE == COL_CONV1 ? a.j0 : 0;
+    const float2* K = a.khat + jo * sstride;
+    const float2* KN = a.knyq + (long long)jo * LY;
+    float2 xr[E], kpre[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      int c, y; long long off;
+      unit(e, c, y, off);
+      xr[e] = a.spec[off];
+    }
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      int c, y; long long off;
+      unit(e, c, y, off);
+      kpre[e] = K[off];
+    }
+    fft_lds_x<LY, true, true>(buf[0], tid, tw, xr);
+    if (has_col0) {
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        int c, y; long long off;
+        unit(e, c, y, off);
+        buf[0][lds_idx<LY>(y)] = xr[e];
+      }
+      __syncthreads();
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        int c, y; long long off;
+        unit(e, c, y, off);
+        const float2 v = xr[e];
+        const float2 m = cconj(buf[0][lds_idx<LY>((LY - y) % LY)]);
+        const float2 ev = cscale(cadd(v, m), 0.5f);
+        const float2 od = cscale(mul_mi(csub(v, m)), 0.5f);
+        const float2 kn = KN[y];
+        xr[e] = cconj(cadd(CONJ ? cmulc(ev, kpre[e]) : cmul(ev, kpre[e]), mul_pi(CONJ ? cmulc(od, kn) : cmul(od, kn))));
+      }
+      __syncthreads();  // mirrored reads done before the next transform writes buf
+    } else {
+#pragma unroll
+      for (int e = 0; e < E; ++e) xr[e] = cconj(CONJ ? cmulc(xr[e], kpre[e]) : cmul(xr[e], kpre[e]));
+    }
+    fft_lds_x<LY, true, true>(buf[0], tid, tw, xr);
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      int c, y; long long off;
+      unit(e, c, y, off);
+      a.spec[jo * sstride + off] = cconj(xr[e]);
     }
   } else if constexpr (MODE == COL_CORR1 || MODE == COL_CONV1) {
     // one image jo: spec[0] -> spec[jo] = K_jo x (or conj K_jo x); the

@@ -107,10 +107,14 @@ def test_rl_fixed_iterations(torch_dev, case):
 # KL by ~2e-6 after 20 iterations on the 64x80 case, tests/test_oracle_fp32_floor.py)
 # and the ~1e-7 relative error of FP32 FFTs, which on the 64x80 case already
 # puts ~1e-6 into the BB inner products at k = 3 and grows the KL gap past
-# 1e-6 by k = 8.  Fixed-count parity is checked where both bars hold: 6
-# iterations on the 64x80-class cases, 20 on the 256x256 field, 10 at full
-# size (tests/test_gpu_fullsize.py).
-SGP_K = {"single_64x80": 6, "single_c0_256": 20, "multi_3x64": 6, "boundary_64x48_in_80x64": 4}
+# 1e-6 by k = 8.  How soon it grows depends on rounding choices as small as
+# whether the compiler fuses a twiddle product into the following butterfly
+# add (one such change moved 58 pixels of the 3 x 64 x 64 case by a few ulps
+# after one iteration and its KL gap after 6 iterations from 2e-7 to 1.7e-6).
+# Fixed-count parity is checked where both bars hold with margin: 6
+# iterations on the 64x80 case, 4 on the three-image and boundary cases, 20
+# on the 256x256 field, 10 at full size (tests/test_gpu_fullsize.py).
+SGP_K = {"single_64x80": 6, "single_c0_256": 20, "multi_3x64": 4, "boundary_64x48_in_80x64": 4}
 
 
 @pytest.mark.parametrize("case", list(CASES))
@@ -132,9 +136,10 @@ def test_sgp_fixed_iterations(torch_dev, case):
 @pytest.mark.parametrize("case", ["single_64x80", "multi_3x64"])
 def test_sgp_alternation_branch(torch_dev, case):
     """n_bb2_only = 2 makes the alternation of Eq. (alphadef) act within the
-    parity window."""
+    parity window (from k = 2: 7 iterations on the 64x80 case, 4 on the
+    three-image case, whose FP32 drift reaches the KL bar sooner)."""
     w = CASES[case]()
-    n = 7
+    n = {"single_64x80": 7, "multi_3x64": 4}[case]
     fn = "sgp_deconv" if w.p == 1 else "sgp_multi_deconv"
     f, rep = _run_gpu(torch_dev, fn, w, max_iter=n, n_bb2_only=2)
     P = _oracle(w)
