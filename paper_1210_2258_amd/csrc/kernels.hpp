@@ -86,6 +86,11 @@ __host__ __device__ constexpr bool row_per_image(int op) {
 // scratch memory.
 __device__ __forceinline__ float pick_b(const Args& a, int j) { return a.bvec[j]; }
 
+// Non-temporal store, for outputs that no kernel reads before they leave
+// the cache (measured at 2048^2: the direction d and A d stores gain from it;
+// the spectrum stores and the other field stores lose).
+__device__ __forceinline__ void st_nt(float* p, float v) { __builtin_nontemporal_store(v, p); }
+
 struct Pix {
   const Args& a;
   int j;
@@ -286,13 +291,13 @@ __device__ __forceinline__ float row_point(const Args& a, const RowScal& sc, int
     const float z = f - sc.alpha * D * gr;
     // projection onto f >= 0, or with the flux constraint onto {f >= 0, sum f = c}
     const float dd = (sc.flux && D > 0.f ? (float)fmax(0.0, (double)z - sc.mu * (double)D) : fmaxf(0.f, z)) - f;
-    a.d[pix] = dd;
+    st_nt(&a.d[pix], dd);
     acc[0] += (double)gr * (double)dd;
     return dd;
   } else if constexpr (OP == ROW_AD) {
     if (!P.inS(y, x)) return 0.f;
     const long long s = P.s_of(y, x);
-    a.Ad[s] = v;
+    st_nt(&a.Ad[s], v);
     const float g = in.c[0];
     const float yv = fmaxf(in.c[1] + in.c[2], 1e-30f);
     acc[0] += armijo_term(g, yv, sc.lam0 * v);
