@@ -26,6 +26,7 @@ deconvolution methods for astronomical imaging: algorithms and IDL-GPU codes"
 * stopping rules ............................ Sect. 3.3, Eqs. (convergence), (discrepancy)
 * flux-constrained projection ............... Sect. 2 intro (constraint set named, algorithm
                                               not given); derived here from the KKT conditions
+* relaxed RL ................................ Sect. 1, Eq. (RL1) (multiplicative relaxation)
 
 Every array is float64.  Inputs given in float32 are promoted.  The iteration
 is written step by step in the paper's order and notation; library primitives
@@ -47,7 +48,11 @@ documented choice, shared with the HIP library by specification, not by code):
 * flat start = mean_j sum_S (g_j - b_j) / |S|, put on R only;
 * discrepancy stop at the first k with 2 J / (p |S|) <= b_D; KL summed over S;
 * backtracking capped at ``max_backtracks``; d = 0 stops as stationary;
-* BB sums taken over pixels with D > 0 (D^{-1} is undefined off R).
+* BB sums taken over pixels with D > 0 (D^{-1} is undefined off R);
+* relaxed RL for several images or a boundary problem: Eq. (RL1) is written
+  for one image with A^T 1 = 1; the factor it raises to the power a is taken
+  as the RL factor q = (M_R / alpha) o sum_j A_j^T (g_j / (A_j f + b_j)) of
+  Eqs. (multipleRL), (boundaryRL), so the step is f o q^a (RL for a = 1).
 """
 from __future__ import annotations
 
@@ -91,6 +96,7 @@ class Params:
     flux: float = -1.0
     max_backtracks: int = 40
     f_true: np.ndarray | None = None
+    rl_alpha: float = 1.0   # exponent of Eq. (RL1); 1 is RL
 
 
 def _as_stack(a, p=None):
@@ -211,13 +217,22 @@ class Problem:
         return 2.0 * J / (self.p * self.nS)
 
     # ---------------------------------------------------------- RL family
-    def rl_step(self, f):
-        """Eqs. (RL), (multipleRL), (boundaryRL):
-        f <- (M_R / alpha) o f o sum_j A_j^T (g_j / (A_j f + b_j))."""
+    def rl_factor(self, f):
+        """q = (M_R / alpha) o sum_j A_j^T (g_j / (A_j f + b_j)), the factor of
+        Eqs. (RL), (multipleRL), (boundaryRL)."""
         s = np.zeros((self.NY, self.NX))
         for j in range(self.p):
             s += self.AT(j, self.g[j] / self.y(j, f))
-        return self.invw * f * s
+        return self.invw * s
+
+    def rl_step(self, f, rl_alpha=1.0):
+        """Eqs. (RL), (multipleRL), (boundaryRL): f <- f o q; with
+        rl_alpha != 1 the multiplicative relaxation of Eq. (RL1), f o q^a
+        (f stays 0 off R, as in RL)."""
+        q = self.rl_factor(f)
+        if rl_alpha == 1.0:
+            return f * q
+        return np.where(self.invw > 0, f * q ** rl_alpha, 0.0)
 
     def start(self, kind="flat", user=None):
         """Sect. 3.1 initial points."""
@@ -247,7 +262,8 @@ class Problem:
         return ymin, ymax
 
     def rl(self, f0, n_iter, params: Params | None = None):
-        """Plain RL iteration with the Sect. 3.3 stopping rules."""
+        """RL iteration (relaxed by Eq. (RL1) when rl_alpha differs from 1)
+        with the Sect. 3.3 stopping rules."""
         prm = params or Params(max_iter=n_iter)
         f = f0.copy()
         J = self.kl(f)
@@ -257,7 +273,7 @@ class Problem:
         if (prm.stop & STOP_DISCREPANCY) and self.discrepancy(J) <= prm.disc_target:
             return f, dict(iters=0, kl=J, history=hist, reason=REASON_DISCREPANCY)
         while k < n_iter:
-            f = self.rl_step(f)
+            f = self.rl_step(f, prm.rl_alpha)
             Jn = self.kl(f)
             k += 1
             hist.append(Jn)
