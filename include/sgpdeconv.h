@@ -108,6 +108,11 @@ typedef struct sgp_params {
   double sigma_R;        /* threshold sigma of Eq. (Rdef) (default 1e-3) */
   int max_backtracks;    /* Armijo reductions allowed, 0..40 (default 40) */
   double* trace;         /* optional HOST buffer [(max_iter + 1) * SGP_TRACE_COLS] doubles */
+  double rl_alpha;       /* RL only: exponent a of the multiplicative relaxation, Sect. 1
+                            Eq. (RL1), f <- f o q^a with q the RL factor of Eqs. (RL),
+                            (multipleRL), (boundaryRL); in (0, 8], default 1 (plain RL;
+                            the paper cites convergence for a < 2).  Other values are
+                            rejected with SGP_E_INVALID_ARG, as is a != 1 for SGP / OSEM. */
 } sgp_params;
 
 typedef struct sgp_report {

@@ -40,7 +40,7 @@ class _Params(ctypes.Structure):
         ("m_alpha", ctypes.c_int), ("n_bb2_only", ctypes.c_int), ("auto_bounds", ctypes.c_int),
         ("L1", ctypes.c_double), ("L2", ctypes.c_double), ("flux_constraint", ctypes.c_int),
         ("flux", ctypes.c_double), ("sigma_R", ctypes.c_double), ("max_backtracks", ctypes.c_int),
-        ("trace", ctypes.c_void_p),
+        ("trace", ctypes.c_void_p), ("rl_alpha", ctypes.c_double),
     ]
 
 

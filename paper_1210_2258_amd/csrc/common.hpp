@@ -52,6 +52,7 @@ struct DevState {
   double flux_cnt;   // active-set size at the current mu
   int flux_done;     // Newton iteration for mu has converged
   double* trace;     // [max_iter + 1][kTraceCols] or null
+  double rl_alpha;   // exponent of the relaxed RL step, Eq. (RL1) (1: RL)
 };
 
 // Kernel arguments (passed by value).

@@ -139,7 +139,7 @@ __device__ __forceinline__ double armijo_term(float g, float y, float t) {
 // Solver scalars a row kernel uses, read once per workgroup (the kernel's
 // global stores could otherwise force them to be re-read at every pixel).
 struct RowScal {
-  float alpha, L1, L2, lam, lam0, lam1;
+  float alpha, L1, L2, lam, lam0, lam1, rl_a;
   double lamd, mu, psf_scale;
   int flux;
 };
@@ -163,6 +163,7 @@ __device__ __forceinline__ RowScal row_scalars(const DevState* st, int j) {
   }
   if constexpr (OP == ROW_UPD) c.lam = (float)st->lam;
   if constexpr (OP == ROW_GRAD) c.lamd = st->lam;
+  if constexpr (OP == ROW_RLUPD) c.rl_a = (float)st->rl_alpha;
   return c;
 }
 
@@ -269,9 +270,16 @@ __device__ __forceinline__ float row_point(const Args& a, const RowScal& sc, int
     acc[0] += kl_term(g, yv);
     return (g - yv) / yv;
   } else if constexpr (OP == ROW_RLUPD) {
+    // RL factor q = 1 + (M_R / alpha) v in residual form; relaxed RL
+    // (Eq. (RL1)) raises it to the power rl_a
     const float w = in.c[0];
     const float f = in.c[1];
-    const float fn = w > 0.f ? fmaxf(0.f, f * (1.f + w * v)) : 0.f;
+    const float q = 1.f + w * v;
+    float fn = w > 0.f ? fmaxf(0.f, f * q) : 0.f;
+    // q^a = 2^(a log2 q) on the hardware log2 / exp2 (about 1 ulp each;
+    // q = 0 gives 0)
+    if (sc.rl_a != 1.f && w > 0.f)
+      fn = f * __builtin_amdgcn_exp2f(sc.rl_a * __builtin_amdgcn_logf(fmaxf(q, 0.f)));
     a.f[pix] = fn;
     return fn;
   } else if constexpr (OP == ROW_SETUPGRAD) {

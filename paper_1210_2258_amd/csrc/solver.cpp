@@ -205,6 +205,7 @@ static void defaults(sgp_params* p) {
   p->sigma_R = 1e-3;
   p->max_backtracks = 40;
   p->trace = nullptr;
+  p->rl_alpha = 1.0;
 }
 
 static int check_params(const sgp_params& p, int kind) {
@@ -231,6 +232,8 @@ static int check_params(const sgp_params& p, int kind) {
       return fail(SGP_E_INVALID_ARG, "max_backtracks must be in 0..40");
   }
   if (p.flux_constraint && kind != KIND_SGP) return fail(SGP_E_INVALID_ARG, "the flux constraint applies to SGP only");
+  if (!(p.rl_alpha > 0 && p.rl_alpha <= 8)) return fail(SGP_E_INVALID_ARG, "rl_alpha must be in (0, 8]");
+  if (p.rl_alpha != 1.0 && kind != KIND_RL) return fail(SGP_E_INVALID_ARG, "rl_alpha (Eq. (RL1)) applies to RL only");
   if (!(p.sigma_R > 0)) return fail(SGP_E_INVALID_ARG, "sigma_R must be > 0");
   return 0;
 }
@@ -370,6 +373,7 @@ static void fill_state(DevState& h, const sgp_params& p, const Problem& pb, doub
   h.flux = p.flux;
   h.flux_c = p.flux;
   h.norm_disc = 2.0 / ((double)pb.p * (double)pb.ny * (double)pb.nx);
+  h.rl_alpha = p.rl_alpha;
   h.alpha = p.alpha0;
   h.tau = p.tau1;
   h.lam = 1.0;

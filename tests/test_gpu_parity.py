@@ -102,6 +102,49 @@ def test_rl_fixed_iterations(torch_dev, case):
     assert abs(rep["kl"] - io["kl"]) <= KL_TOL * io["kl"], (rep["kl"], io["kl"])
 
 
+@pytest.mark.parametrize("case,a", [("single_64x80", 1.5), ("single_c0_256", 1.9), ("multi_3x64", 1.7),
+                                    ("boundary_64x48_in_80x64", 1.5)])
+def test_relaxed_rl_fixed_iterations(torch_dev, case, a):
+    """Multiplicative relaxation of Eq. (RL1) against the oracle's, same bar as RL."""
+    w = CASES[case]()
+    n = 60 if case == "single_c0_256" else 20
+    fn = "rl_deconv" if (w.domain is None and w.p == 1) else (
+        "rl_multi_deconv" if w.domain is None else "rl_boundary_deconv")
+    f, rep = _run_gpu(torch_dev, fn, w, max_iter=n, rl_alpha=a)
+    P = _oracle(w)
+    fo, io = P.rl(P.start("flat"), n, O.Params(max_iter=n, rl_alpha=a))
+    assert rep["iters"] == n
+    assert _rel(f.cpu().numpy(), fo) <= F_TOL, _rel(f.cpu().numpy(), fo)
+    assert abs(rep["kl"] - io["kl"]) <= KL_TOL * io["kl"], (rep["kl"], io["kl"])
+
+
+def test_relaxed_rl_discrepancy_stop_and_rl_identity(torch_dev):
+    """Eq. (RL1) to the discrepancy stop takes the oracle's iteration count
+    (RL trajectories do not separate as SGP's do), fewer than plain RL; the
+    exponent 1 reproduces RL bit for bit."""
+    import paper_1210_2258_amd as m
+    w = CASES["single_64x80"]()
+    P = _oracle(w)
+    f15, rep = _run_gpu(torch_dev, "rl_deconv", w, max_iter=2000, stop=m.STOP_DISCREPANCY, rl_alpha=1.5)
+    _, io = P.rl(P.start("flat"), 2000, O.Params(max_iter=2000, stop=O.STOP_DISCREPANCY, rl_alpha=1.5))
+    assert rep["reason"] == "discrepancy" and abs(rep["iters"] - io["iters"]) <= 1, (rep["iters"], io["iters"])
+    f1, rep1 = _run_gpu(torch_dev, "rl_deconv", w, max_iter=2000, stop=m.STOP_DISCREPANCY)
+    assert rep1["iters"] > 1.3 * rep["iters"]
+    fa, _ = _run_gpu(torch_dev, "rl_deconv", w, max_iter=25, rl_alpha=1.0)
+    fb, _ = _run_gpu(torch_dev, "rl_deconv", w, max_iter=25)
+    assert torch_dev.equal(fa, fb)
+
+
+def test_relaxed_rl_rejects_bad_exponents(torch_dev):
+    import paper_1210_2258_amd as m
+    w = CASES["single_64x80"]()
+    for bad in (0.0, -1.0, 9.0, float("nan")):
+        with pytest.raises(m.SgpError):
+            _run_gpu(torch_dev, "rl_deconv", w, max_iter=2, rl_alpha=bad)
+    with pytest.raises(m.SgpError):  # the relaxation is an RL option
+        _run_gpu(torch_dev, "sgp_deconv", w, max_iter=2, rl_alpha=1.5)
+
+
 # SGP iterates carried in FP32 drift from the FP64 oracle's.  Two sources:
 # FP32 storage of f and d (rounding them inside the oracle itself moves the
 # KL by ~2e-6 after 20 iterations on the 64x80 case, tests/test_oracle_fp32_floor.py)
