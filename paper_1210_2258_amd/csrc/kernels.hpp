@@ -167,21 +167,19 @@ __device__ __forceinline__ RowScal row_scalars(const DevState* st, int j) {
   return c;
 }
 
-// Units per load chunk: the largest divisor of nu not above cap.
-__host__ __device__ constexpr int row_chunk(int nu, int cap = 8) {
-  int c = nu < cap ? nu : cap;
+// Units per load chunk: the largest divisor of nu not above 8.
+__host__ __device__ constexpr int row_chunk(int nu) {
+  int c = nu < 8 ? nu : 8;
   while (nu % c) --c;
   return c;
 }
 
-#ifndef SGP_XR_UPD_CHUNK
-#define SGP_XR_UPD_CHUNK 0
-#endif
 // Row ops that keep the data between their transforms and the pointwise
 // stage in registers.  The ratio pass and the update hold the most loads in
-// flight; with the transform data on top they would spill.
+// flight; with the transform data on top they spill (with fewer loads in
+// flight the update measured slower).
 __host__ __device__ constexpr bool row_regs_ok(int op) {
-  return op != ROW_RATIO && (op != ROW_UPD || SGP_XR_UPD_CHUNK > 0);
+  return op != ROW_RATIO && op != ROW_UPD;
 }
 
 // Global inputs of one pixel of the pointwise stage, loaded ahead of the
@@ -481,7 +479,7 @@ __global__ __launch_bounds__(RowCfg<L>::NT) void row_kernel(Args a_in) {
     const RowScal sc = row_scalars<OP>(st, j);
     constexpr int NU = RP * L / NT;  // units (pixel pairs) per thread
     static_assert(NU * NT == RP * L, "threads must tile the rows");
-    constexpr int CH = row_chunk(NU, OP == ROW_UPD && XR ? SGP_XR_UPD_CHUNK : 8);
+    constexpr int CH = row_chunk(NU);
     static_assert(NU % CH == 0, "chunks must tile the units");
 #pragma unroll
     for (int c0 = 0; c0 < NU; c0 += CH) {

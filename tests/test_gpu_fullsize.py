@@ -47,6 +47,21 @@ def test_full_size_sgp_parity(torch_dev, cfg):
     assert abs(rep["kl"] - io["kl"]) <= 1e-6 * io["kl"], (rep["kl"], io["kl"])
 
 
+@pytest.mark.parametrize("a", [1.0, 1.7])
+def test_full_size_rl_parity(torch_dev, a):
+    """RL and its multiplicative relaxation (Eq. (RL1)) on the 2048x2048 field."""
+    import paper_1210_2258_amd as m
+    torch = torch_dev
+    w = W.config1()
+    g = torch.from_numpy(np.ascontiguousarray(w.g[0])).cuda()
+    psf = torch.from_numpy(np.ascontiguousarray(w.psf[0])).cuda()
+    f, rep = m.rl_deconv(g, psf, float(w.b[0]), max_iter=K, rl_alpha=a)
+    P = O.Problem(w.g, w.psf, w.b)
+    fo, io = P.rl(P.start("flat"), K, O.Params(max_iter=K, rl_alpha=a))
+    assert _rel(f.cpu().numpy(), fo) <= 1e-4, _rel(f.cpu().numpy(), fo)
+    assert abs(rep["kl"] - io["kl"]) <= 1e-6 * io["kl"], (rep["kl"], io["kl"])
+
+
 def test_full_size_operator_sampled(torch_dev):
     """A and A^T at 2048x2048 against the direct definition of the periodic
     convolution at sampled output pixels (each a full O(N) sum)."""
