@@ -96,6 +96,22 @@ struct Plan {
 static std::mutex g_mutex;
 static std::map<PlanKey, std::unique_ptr<Plan>> g_plans;
 
+// Internal stream and ordering event of the one-shot calls, one pair per
+// device, kept for the process (creating a stream costs more than a small
+// solve's setup).  The calls hold g_mutex, so they never share it at once.
+struct SharedStream {
+  hipStream_t s = nullptr;
+  hipEvent_t e = nullptr;
+};
+static std::map<int, SharedStream> g_streams;
+static int shared_stream(int dev, SharedStream** out) {
+  SharedStream& ss = g_streams[dev];
+  if (!ss.s) SGP_HIP(hipStreamCreateWithFlags(&ss.s, hipStreamNonBlocking));
+  if (!ss.e) SGP_HIP(hipEventCreateWithFlags(&ss.e, hipEventDisableTiming));
+  *out = &ss;
+  return 0;
+}
+
 // workgroups of the Armijo kernel (its rare candidate pass)
 constexpr int kArmBlocks = 512;
 
@@ -406,10 +422,11 @@ struct sgp_solver {
   double ms[SGP_KCLASS_COUNT] = {0};
   long long cnt[SGP_KCLASS_COUNT] = {0};
 
+  bool own_stream = true;   // false: the per-device stream of the one-shot calls
   ~sgp_solver() {
     if (graph) (void)hipGraphExecDestroy(graph);
     if (graph_def) (void)hipGraphDestroy(graph_def);
-    if (s) (void)hipStreamDestroy(s);
+    if (s && own_stream) (void)hipStreamDestroy(s);
   }
 };
 
@@ -502,18 +519,13 @@ static int setup(sgp_solver* S) {
   Launcher& L = S->L;
   const Problem& pb = S->pb;
   const long long nS = (long long)pb.ny * pb.nx, nF = (long long)pb.NY * pb.NX;
+  // the data checks are read back with the rest of the setup (one host
+  // synchronisation): on bad data the setup kernels compute non-finite values
+  // in bounds, and the call fails before any iteration
   L.pix(PIX_VALIDATE, pb.p * nS, 0);
   for (int j = 0; j < pb.p; ++j) L.pix(PIX_PSFSUM, nF, 0, j);
   SGP_HIP(hipGetLastError());
   int rc;
-  if ((rc = read_state(S))) return rc;
-  for (int i = 0; i < S->nitems; ++i) {
-    const int fl = S->pl->host_st[i].flags;
-    const std::string who = S->nitems > 1 ? " (batch item " + std::to_string(i) + ")" : "";
-    if (fl & FLAG_BAD_PSF) return fail(SGP_E_BAD_PSF, "PSF has negative or non-finite entries or a non-positive sum" + who);
-    if (fl & FLAG_BAD_DATA) return fail(SGP_E_BAD_DATA, "g must be finite and >= 0" + who);
-    if (fl & FLAG_BAD_BG) return fail(SGP_E_BAD_DATA, "background map must be finite and >= 0" + who);
-  }
   // transfer functions K_j / (NY NX): shifted PSF -> row FFT -> column FFT
   L.row(ROW_PSF, pb.p, 0);
   L.col(COL_FWD, 0, pb.p, 0);
@@ -566,6 +578,13 @@ static int setup(sgp_solver* S) {
   }
   SGP_HIP(hipGetLastError());
   if ((rc = read_state(S))) return rc;
+  for (int i = 0; i < S->nitems; ++i) {
+    const int fl = S->pl->host_st[i].flags;
+    const std::string who = S->nitems > 1 ? " (batch item " + std::to_string(i) + ")" : "";
+    if (fl & FLAG_BAD_PSF) return fail(SGP_E_BAD_PSF, "PSF has negative or non-finite entries or a non-positive sum" + who);
+    if (fl & FLAG_BAD_DATA) return fail(SGP_E_BAD_DATA, "g must be finite and >= 0" + who);
+    if (fl & FLAG_BAD_BG) return fail(SGP_E_BAD_DATA, "background map must be finite and >= 0" + who);
+  }
   S->done = all_done(S);
   return 0;
 }
@@ -624,14 +643,17 @@ static int step(sgp_solver* S, int n, int* done_out) {
     S->L.marks.clear();
     S->L.used = 0;
   } else {
-    const int block = std::min(iters, 32);
+    // a run with an early stop replays blocks of 16 iterations and reads the
+    // state after each of the first four (a short run then ends with no
+    // replay of iterations that only exit), later after every second one
+    const int block = std::min(iters, early ? 16 : 32);
     if (!S->graph || S->graph_block != block) {
       if ((rc = capture_graph(S, block))) return rc;
     }
     const int reps = (iters + block - 1) / block;
     for (int r = 0; r < reps; ++r) {
       SGP_HIP(hipGraphLaunch(S->graph, S->s));
-      if (early && r + 1 < reps && (r % 2) == 1) {
+      if (early && r + 1 < reps && (r < 4 || (r % 2) == 1)) {
         if ((rc = read_state(S))) return rc;
         if (all_done(S)) break;
       }
@@ -710,7 +732,7 @@ static int to_problem(const sgp_problem* pr, Problem& pb) {
 // caller), otherwise the solver owns it.
 static int create_items(int kind, const std::vector<Problem>& items, const std::vector<float*>& fs,
                         const std::vector<const float*>& f0s, const sgp_params* prm_in, void* stream,
-                        bool cached, std::unique_ptr<sgp_solver>& out) {
+                        bool cached, std::unique_ptr<sgp_solver>& out, bool shared = false) {
   auto S = std::make_unique<sgp_solver>();
   S->t0 = std::chrono::steady_clock::now();
   if (prm_in) S->prm = *prm_in;
@@ -741,13 +763,22 @@ static int create_items(int kind, const std::vector<Problem>& items, const std::
   S->nitems = n;
   S->fs = fs;
   S->user = (hipStream_t)stream;
-  SGP_HIP(hipStreamCreateWithFlags(&S->s, hipStreamNonBlocking));
   // order the internal stream after the caller's stream
-  hipEvent_t e;
-  SGP_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
-  SGP_HIP(hipEventRecord(e, S->user));
-  SGP_HIP(hipStreamWaitEvent(S->s, e, 0));
-  SGP_HIP(hipEventDestroy(e));
+  if (shared) {
+    SharedStream* ss;
+    if ((rc = shared_stream(dev, &ss))) return rc;
+    S->s = ss->s;
+    S->own_stream = false;
+    SGP_HIP(hipEventRecord(ss->e, S->user));
+    SGP_HIP(hipStreamWaitEvent(S->s, ss->e, 0));
+  } else {
+    SGP_HIP(hipStreamCreateWithFlags(&S->s, hipStreamNonBlocking));
+    hipEvent_t e;
+    SGP_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    SGP_HIP(hipEventRecord(e, S->user));
+    SGP_HIP(hipStreamWaitEvent(S->s, e, 0));
+    SGP_HIP(hipEventDestroy(e));
+  }
   PlanKey key{kind, pb.p, pb.NY, pb.NX, pb.ny, pb.nx, pb.oy, pb.ox, pb.boundary ? 1 : 0, dev};
   key.nitems = n;
   if (cached) {
@@ -819,9 +850,10 @@ static int create_items(int kind, const std::vector<Problem>& items, const std::
 }
 
 static int create(int kind, const Problem& pb, const sgp_params* prm_in, float* f, void* stream, bool cached,
-                  std::unique_ptr<sgp_solver>& out) {
+                  std::unique_ptr<sgp_solver>& out, bool shared = false) {
   return create_items(kind, std::vector<Problem>{pb}, std::vector<float*>{f},
-                      std::vector<const float*>{prm_in ? prm_in->f0 : nullptr}, prm_in, stream, cached, out);
+                      std::vector<const float*>{prm_in ? prm_in->f0 : nullptr}, prm_in, stream, cached, out,
+                      shared);
 }
 
 // Many problems in one run: problems are grouped by shape, each group is one
@@ -957,7 +989,7 @@ static int batch_run(int kind, const sgp_problem* probs, int n, float* const* fo
 static int one_shot(int kind, const Problem& pb, const sgp_params* prm, float* f, sgp_report* rep, void* stream) {
   std::lock_guard<std::mutex> lock(g_mutex);
   std::unique_ptr<sgp_solver> S;
-  int rc = create(kind, pb, prm, f, stream, true, S);
+  int rc = create(kind, pb, prm, f, stream, true, S, true);
   if (rc) return rc;
   const int n = S->prm.max_iter;
   if ((rc = step(S.get(), n, nullptr))) return rc;
@@ -1302,6 +1334,11 @@ int sgp_release_cache(void) {
   std::lock_guard<std::mutex> lock(g_mutex);
   (void)hipDeviceSynchronize();
   g_plans.clear();
+  for (auto& kv : g_streams) {
+    if (kv.second.e) (void)hipEventDestroy(kv.second.e);
+    if (kv.second.s) (void)hipStreamDestroy(kv.second.s);
+  }
+  g_streams.clear();
   return SGP_OK;
 }
 
