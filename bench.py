@@ -37,12 +37,12 @@ HBM_PEAK_GBS = 8000.0
 #   row_dir  reads f, grad            writes d, spectrum           16 B/px
 #   col_conv reads spectrum, K         writes spectrum              12 B/px
 #   row_ad   reads spectrum, Af, g     writes Ad                    16 B/px
-#   row_upd  reads f, d, Af, Ad, g     writes f, Af, spectrum       32 B/px
+#   row_upd  reads Af, Ad, g           writes Af, spectrum          20 B/px
 #   col_corr reads spectrum, K         writes spectrum              12 B/px
-#   row_grad reads spectrum, grad, f, d writes grad                 20 B/px
-BYTES_PER_PX = {"row_dir": 16, "col_conv": 12, "row_ad": 16, "row_upd": 32, "col_corr": 12,
-                "row_grad": 20}
-ITER_BYTES_PER_PX = sum(BYTES_PER_PX.values())  # 108
+#   row_grad reads spectrum, grad, f, d writes grad, f              24 B/px
+BYTES_PER_PX = {"row_dir": 16, "col_conv": 12, "row_ad": 16, "row_upd": 20, "col_corr": 12,
+                "row_grad": 24}
+ITER_BYTES_PER_PX = sum(BYTES_PER_PX.values())  # 100
 
 
 def parse():

@@ -53,6 +53,8 @@ struct DevState {
   int flux_done;     // Newton iteration for mu has converged
   double* trace;     // [max_iter + 1][kTraceCols] or null
   double rl_alpha;   // exponent of the relaxed RL step, Eq. (RL1) (1: RL)
+  int f_pending;     // an accepted step waits for f += lam d (taken by the
+                     // gradient pass, also after a stop; cleared after it)
 };
 
 // Kernel arguments (passed by value).

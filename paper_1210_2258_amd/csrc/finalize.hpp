@@ -50,6 +50,7 @@ __host__ __device__ inline void fin_armijo(DevState* st, const double* dJ, int m
     if (dJ[m] <= st->beta * lam * st->gd) {
       st->lam = lam;
       st->nback = mm;
+      st->f_pending = 1;
       return;
     }
   }

@@ -162,24 +162,26 @@ __device__ __forceinline__ RowScal row_scalars(const DevState* st, int j) {
     c.lam1 = (float)st->lam_tab[1];
   }
   if constexpr (OP == ROW_UPD) c.lam = (float)st->lam;
-  if constexpr (OP == ROW_GRAD) c.lamd = st->lam;
+  if constexpr (OP == ROW_GRAD) {
+    c.lamd = st->lam;
+    c.lam = (float)st->lam;
+  }
   if constexpr (OP == ROW_RLUPD) c.rl_a = (float)st->rl_alpha;
   return c;
 }
 
 // Units per load chunk: the largest divisor of nu not above 8.
-__host__ __device__ constexpr int row_chunk(int nu) {
-  int c = nu < 8 ? nu : 8;
+__host__ __device__ constexpr int row_chunk(int nu, int cap = 8) {
+  int c = nu < cap ? nu : cap;
   while (nu % c) --c;
   return c;
 }
 
 // Row ops that keep the data between their transforms and the pointwise
-// stage in registers.  The ratio pass and the update hold the most loads in
-// flight; with the transform data on top they spill (with fewer loads in
-// flight the update measured slower).
+// stage in registers.  The ratio pass holds the most loads in flight; with
+// the transform data on top it spills.
 __host__ __device__ constexpr bool row_regs_ok(int op) {
-  return op != ROW_RATIO && op != ROW_UPD;
+  return op != ROW_RATIO;
 }
 
 // Global inputs of one pixel of the pointwise stage, loaded ahead of the
@@ -221,10 +223,6 @@ __device__ __forceinline__ RowIn row_load(const Args& a, int j, int y, int x) {
       in.c[2] = P.bg(s);
     }
   } else if constexpr (OP == ROW_UPD) {
-    if (j == 0) {
-      in.c[0] = a.f[pix];
-      in.c[1] = a.d[pix];
-    }
     if (P.inS(y, x)) {
       const long long s = P.s_of(y, x);
       in.c[2] = a.Af[s];
@@ -310,11 +308,11 @@ __device__ __forceinline__ float row_point(const Args& a, const RowScal& sc, int
     acc[1] += armijo_term(g, yv, sc.lam1 * v);
     return 0.f;
   } else if constexpr (OP == ROW_UPD) {
-    // f += lam d, A_j f += lam A_j d; feeds delta rho_j = g/y_new - g/y_old
+    // A_j f += lam A_j d (f += lam d is taken by the gradient pass, which
+    // reads f and d anyway); feeds delta rho_j = g/y_new - g/y_old
     // = -g lam A_j d / (y_old y_new) to the transform (no cancellation), so
     // the adjoint directly yields z = grad_new - grad_old
     const float lam = sc.lam;
-    if (j == 0) a.f[pix] = in.c[0] + lam * in.c[1];
     if (!P.inS(y, x)) return 0.f;
     const long long s = P.s_of(y, x);
     const float bgv = in.c[5];
@@ -328,13 +326,16 @@ __device__ __forceinline__ float row_point(const Args& a, const RowScal& sc, int
     acc[0] += kl_term(g, yn);
     return g > 0.f ? -g * step / (yo * yn) : 0.f;
   } else if constexpr (OP == ROW_GRAD) {
-    // v = sum_j A_j^T delta rho_j, so z = grad_new - grad_old = -M_R v
+    // v = sum_j A_j^T delta rho_j, so z = grad_new - grad_old = -M_R v; the
+    // step of Algorithm 1 step 6, f_new = f + lam d, is taken here
     const float w = in.c[0];
     const float zf = w > 0.f ? -v : 0.f;
     a.grad[pix] = in.c[1] + zf;
+    const float fn = in.c[3] + sc.lam * in.c[2];
+    a.f[pix] = fn;
     const double s = sc.lamd * (double)in.c[2];
     const double z = (double)zf;
-    const double D = (double)(w * fminf(sc.L2, fmaxf(sc.L1, in.c[3])));
+    const double D = (double)(w * fminf(sc.L2, fmaxf(sc.L1, fn)));
     if (D > 0) {
       const double sd = s / D;
       acc[0] += sd * sd;
@@ -429,7 +430,9 @@ __global__ __launch_bounds__(RowCfg<L>::NT) void row_kernel(Args a_in) {
   __shared__ float2 buf[RP][L];
   __shared__ float2 twl[L];  // twiddles staged in LDS in pass order
   DevState* st = a.st;
-  if (a.iter && (st->done || st->pause)) return;
+  // the gradient pass also runs after a stop when an accepted step still
+  // has to be applied to f
+  if (a.iter && ((st->done && !(OP == ROW_GRAD && st->f_pending)) || st->pause)) return;
   const int tid = threadIdx.x;
   const int j = blockIdx.y + a.j0;
   const int wg = xcd_remap(blockIdx.x, gridDim.x, kRP / RP);
@@ -479,7 +482,7 @@ __global__ __launch_bounds__(RowCfg<L>::NT) void row_kernel(Args a_in) {
     const RowScal sc = row_scalars<OP>(st, j);
     constexpr int NU = RP * L / NT;  // units (pixel pairs) per thread
     static_assert(NU * NT == RP * L, "threads must tile the rows");
-    constexpr int CH = row_chunk(NU);
+    constexpr int CH = OP == ROW_GRAD ? row_chunk(NU, 4) : row_chunk(NU);
     static_assert(NU % CH == 0, "chunks must tile the units");
 #pragma unroll
     for (int c0 = 0; c0 < NU; c0 += CH) {

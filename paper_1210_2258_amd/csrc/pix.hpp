@@ -276,6 +276,8 @@ template <int OP>
 __global__ __launch_bounds__(kFinThreads) void row_fin_kernel(Args a_in) {
   const Args a = batch_view(a_in);
   DevState* st = a.st;
+  // the gradient pass before this launch has applied the accepted step
+  if (OP == ROW_GRAD && a.iter && threadIdx.x == 0) st->f_pending = 0;
   if (a.iter && (st->done || st->pause)) return;
   constexpr int NS = row_nslots(OP);
   double tot[NS];
