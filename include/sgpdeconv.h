@@ -244,7 +244,8 @@ int sgp_solver_report(sgp_solver* s, sgp_report* rep);
 #define SGP_KCLASS_ROW_GRAD 6     /* row IFFT -> gradient, BB sums */
 #define SGP_KCLASS_ROW_RATIO 7    /* RL: row IFFT -> ratio, KL -> row FFT */
 #define SGP_KCLASS_ROW_RLUPD 8    /* RL: row IFFT -> update -> row FFT */
-#define SGP_KCLASS_COUNT 9
+#define SGP_KCLASS_ROW_FIN 9      /* one-workgroup finish of a row reduction (the BB steplength rule) */
+#define SGP_KCLASS_COUNT 10
 int sgp_solver_set_timing(sgp_solver* s, int enable);
 /* Graph replay of the iteration loop (default on); off launches every kernel
  * from the host. */

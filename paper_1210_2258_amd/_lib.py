@@ -64,7 +64,7 @@ class _Problem(ctypes.Structure):
 
 KIND_RL, KIND_SGP, KIND_OSEM = 0, 1, 2
 KCLASSES = ["row_dir", "col_conv", "row_ad", "armijo_more", "row_upd", "col_corr", "row_grad",
-            "row_ratio", "row_rlupd"]
+            "row_ratio", "row_rlupd", "row_fin"]
 
 EXPORTS = [
     "sgp_params_init", "rl_deconv", "sgp_deconv", "sgp_multi_deconv", "rl_multi_deconv",

@@ -326,8 +326,12 @@ struct Launcher {
     hipEvent_t e0 = nullptr;
     begin(cls, e0);
     launch_row(NX, op, dim3(gx, jc, nz), a, s);
-    if (fin) launch_row_fin(op, nz, a, s);
     end(cls, e0);
+    if (fin) {
+      begin(cls >= 0 ? SGP_KCLASS_ROW_FIN : -1, e0);
+      launch_row_fin(op, nz, a, s);
+      end(cls >= 0 ? SGP_KCLASS_ROW_FIN : -1, e0);
+    }
   }
   void col(int mode, int conj, int jc, int iter, int cls = -1, int fin_op = -1) {
     Args a = base;
