@@ -34,15 +34,16 @@ HBM_PEAK_GBS = 8000.0
 
 # Algorithmic bytes per pixel and launch (FP32 fields, complex64 half spectra,
 # one HBM pass per 2D-FFT transpose), single image with a constant background:
-#   row_dir  reads f, grad            writes d, spectrum           16 B/px
+#   row_dir  reads f, grad            writes spectrum              12 B/px
 #   col_conv reads spectrum, K         writes spectrum              12 B/px
 #   row_ad   reads spectrum, Af, g     writes Ad                    16 B/px
 #   row_upd  reads Af, Ad, g           writes Af, spectrum          20 B/px
 #   col_corr reads spectrum, K         writes spectrum              12 B/px
-#   row_grad reads spectrum, grad, f, d writes grad, f              24 B/px
-BYTES_PER_PX = {"row_dir": 16, "col_conv": 12, "row_ad": 16, "row_upd": 20, "col_corr": 12,
-                "row_grad": 24}
-ITER_BYTES_PER_PX = sum(BYTES_PER_PX.values())  # 100
+#   row_grad reads spectrum, grad, f   writes grad, f               20 B/px
+# (the gradient pass takes f + lam d, evaluating d again from f and grad)
+BYTES_PER_PX = {"row_dir": 12, "col_conv": 12, "row_ad": 16, "row_upd": 20, "col_corr": 12,
+                "row_grad": 20}
+ITER_BYTES_PER_PX = sum(BYTES_PER_PX.values())  # 92
 
 
 def parse():

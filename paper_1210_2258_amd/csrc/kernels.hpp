@@ -87,8 +87,8 @@ __host__ __device__ constexpr bool row_per_image(int op) {
 __device__ __forceinline__ float pick_b(const Args& a, int j) { return a.bvec[j]; }
 
 // Non-temporal store, for outputs that no kernel reads before they leave
-// the cache (measured at 2048^2: the direction d and A d stores gain from it;
-// the spectrum stores and the other field stores lose).
+// the cache (measured at 2048^2: the A d stores gain from it; the spectrum
+// stores and the other field stores lose).
 __device__ __forceinline__ void st_nt(float* p, float v) { __builtin_nontemporal_store(v, p); }
 
 struct Pix {
@@ -152,7 +152,7 @@ __device__ __forceinline__ RowScal row_scalars(const DevState* st, int j) {
     c.L1 = (float)st->L1;
     c.L2 = (float)st->L2;
   }
-  if constexpr (OP == ROW_DIR) {
+  if constexpr (OP == ROW_DIR || OP == ROW_GRAD) {
     c.alpha = (float)st->alpha;
     c.flux = st->flux_constraint;
     c.mu = st->mu;
@@ -170,7 +170,21 @@ __device__ __forceinline__ RowScal row_scalars(const DevState* st, int j) {
   return c;
 }
 
-// Units per load chunk: the largest divisor of nu not above 8.
+// Direction of Algorithm 1 steps 2-3 at one pixel: D = w clip(f, L1, L2)
+// (Eq. (Dk)), y = P(f - alpha D grad) onto f >= 0 (with the flux constraint
+// onto {f >= 0, sum f = c}: max(0, z - mu D)), d = y - f.  The direction
+// kernel uses it, and the gradient pass takes f + lam d with it instead of
+// storing d; the products are fused explicitly, so both evaluate the same
+// arithmetic and get the same d.
+__device__ __forceinline__ float dir_value(float f, float gr, float w, const RowScal& sc) {
+  const float D = w * fminf(sc.L2, fmaxf(sc.L1, f));
+  const float z = fmaf(-(sc.alpha * D), gr, f);
+  const float y = sc.flux && D > 0.f ? (float)fmax(0.0, fma(-sc.mu, (double)D, (double)z)) : fmaxf(0.f, z);
+  return y - f;
+}
+
+// Units per load chunk: the largest divisor of nu not above cap (8; 4 in
+// the gradient pass, which with 8 would exceed 128 registers and spill).
 __host__ __device__ constexpr int row_chunk(int nu, int cap = 8) {
   int c = nu < cap ? nu : cap;
   while (nu % c) --c;
@@ -233,7 +247,6 @@ __device__ __forceinline__ RowIn row_load(const Args& a, int j, int y, int x) {
   } else if constexpr (OP == ROW_GRAD) {
     in.c[0] = P.w(pix);
     in.c[1] = a.grad[pix];
-    in.c[2] = a.d[pix];
     in.c[3] = a.f[pix];
   }
   return in;
@@ -290,12 +303,8 @@ __device__ __forceinline__ float row_point(const Args& a, const RowScal& sc, int
     }
     return 0.f;
   } else if constexpr (OP == ROW_DIR) {
-    const float f = in.c[0], gr = in.c[1];
-    const float D = in.c[2] * fminf(sc.L2, fmaxf(sc.L1, f));
-    const float z = f - sc.alpha * D * gr;
-    // projection onto f >= 0, or with the flux constraint onto {f >= 0, sum f = c}
-    const float dd = (sc.flux && D > 0.f ? (float)fmax(0.0, (double)z - sc.mu * (double)D) : fmaxf(0.f, z)) - f;
-    st_nt(&a.d[pix], dd);
+    const float gr = in.c[1];
+    const float dd = dir_value(in.c[0], gr, in.c[2], sc);
     acc[0] += (double)gr * (double)dd;
     return dd;
   } else if constexpr (OP == ROW_AD) {
@@ -327,13 +336,15 @@ __device__ __forceinline__ float row_point(const Args& a, const RowScal& sc, int
     return g > 0.f ? -g * step / (yo * yn) : 0.f;
   } else if constexpr (OP == ROW_GRAD) {
     // v = sum_j A_j^T delta rho_j, so z = grad_new - grad_old = -M_R v; the
-    // step of Algorithm 1 step 6, f_new = f + lam d, is taken here
+    // step of Algorithm 1 step 6, f_new = f + lam d, is taken here, with d
+    // evaluated again from the f and grad of the direction kernel
     const float w = in.c[0];
+    const float dv = dir_value(in.c[3], in.c[1], w, sc);
     const float zf = w > 0.f ? -v : 0.f;
     a.grad[pix] = in.c[1] + zf;
-    const float fn = in.c[3] + sc.lam * in.c[2];
+    const float fn = in.c[3] + sc.lam * dv;
     a.f[pix] = fn;
-    const double s = sc.lamd * (double)in.c[2];
+    const double s = sc.lamd * (double)dv;
     const double z = (double)zf;
     const double D = (double)(w * fminf(sc.L2, fmaxf(sc.L1, fn)));
     if (D > 0) {
