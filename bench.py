@@ -36,14 +36,16 @@ HBM_PEAK_GBS = 8000.0
 # one HBM pass per 2D-FFT transpose), single image with a constant background:
 #   row_dir  reads f, grad            writes spectrum              12 B/px
 #   col_conv reads spectrum, K         writes spectrum              12 B/px
-#   row_ad   reads spectrum, Af, g     writes Ad                    16 B/px
-#   row_upd  reads Af, Ad, g           writes Af, spectrum          20 B/px
+#   row_ad   reads spectrum, Af, g     writes Ad, Af', spectrum     24 B/px
 #   col_corr reads spectrum, K         writes spectrum              12 B/px
 #   row_grad reads spectrum, grad, f   writes grad, f               20 B/px
-# (the gradient pass takes f + lam d, evaluating d again from f and grad)
-BYTES_PER_PX = {"row_dir": 12, "col_conv": 12, "row_ad": 16, "row_upd": 20, "col_corr": 12,
+# (the A d pass also makes the update for lambda = 1; the update pass,
+#   row_upd  reads Af, Ad, g           writes Af', spectrum         20 B/px
+# runs only when another lambda is accepted; the gradient pass takes
+# f + lam d, evaluating d again from f and grad)
+BYTES_PER_PX = {"row_dir": 12, "col_conv": 12, "row_ad": 24, "row_upd": 20, "col_corr": 12,
                 "row_grad": 20}
-ITER_BYTES_PER_PX = sum(BYTES_PER_PX.values())  # 92
+ITER_BYTES_PER_PX = sum(v for k, v in BYTES_PER_PX.items() if k != "row_upd")  # 80
 
 
 def parse():

@@ -55,6 +55,7 @@ struct DevState {
   double rl_alpha;   // exponent of the relaxed RL step, Eq. (RL1) (1: RL)
   int f_pending;     // an accepted step waits for f += lam d (taken by the
                      // gradient pass, also after a stop; cleared after it)
+  int spec_ok;       // lambda = 1 accepted: the update the A d pass made for it stands
 };
 
 // Kernel arguments (passed by value).
@@ -75,6 +76,8 @@ struct Args {
   const float* invw;     // [NY][NX] M_R / alpha, or null for the scalar invw_s
   float invw_s;
   float* Af;             // [p][ny][nx]
+  float* Af2;            // [p][ny][nx] second A f: SGP iteration k reads Af (k even) or Af2
+                         // (k odd) and writes the other
   float* Ad;             // [p][ny][nx]
   float2* spec;          // [p][NY * NX / 2] row-blocked half spectra
   float2* khat;          // [p][NY * NX / 2] transfer functions / (NY NX)
@@ -119,8 +122,9 @@ enum RowOp {
   ROW_RLUPD,        // inv+fwd: RL update of f    -> spec[0]
   ROW_SETUPGRAD,    // inv: gradient at f0, min/max of one RL step (bounds)
   ROW_DIR,          // fwd: scaling, projection, direction d -> spec[0]
-  ROW_AD,           // inv: A_j d, Armijo candidates lambda = 1, theta
-  ROW_UPD,          // fwd: f += lam d, A_j f += lam A_j d, delta rho_j -> spec[j]
+  ROW_AD,           // inv+fwd: A_j d, Armijo candidates lambda = 1, theta, and the
+                    // update for lambda = 1: A_j f + A_j d, KL, delta rho_j -> spec[j]
+  ROW_UPD,          // fwd: the update for an accepted lambda other than 1 (else no work)
   ROW_GRAD,         // inv: gradient change z, new gradient, BB sums
   ROW_NOPS
 };

@@ -38,6 +38,7 @@ __host__ __device__ inline void fin_dir(DevState* st, double gd) {
 // dJ[m] = J(f + theta^(m0+m) d) - J(f) for m = 0..n-1.
 __host__ __device__ inline void fin_armijo(DevState* st, const double* dJ, int m0, int n) {
   st->need_more = 0;
+  st->spec_ok = 0;
   for (int m = 0; m < n; ++m) {
     const int mm = m0 + m;
     if (mm > st->max_backtracks) break;
@@ -51,6 +52,7 @@ __host__ __device__ inline void fin_armijo(DevState* st, const double* dJ, int m
       st->lam = lam;
       st->nback = mm;
       st->f_pending = 1;
+      st->spec_ok = mm == 0;  // lambda = theta^0 = 1: the A d pass already made this update
       return;
     }
   }

@@ -45,6 +45,7 @@ __device__ __forceinline__ Args batch_view(const Args& in) {
     if (a.invw) a.invw += b * in.item_field;      // boundary items
     if (a.aux) a.aux += b * in.item_field * in.p;
     a.Af += b * in.item_obs;
+    if (a.Af2) a.Af2 += b * in.item_obs;
     if (a.Ad) a.Ad += b * in.item_obs;
     a.spec += b * in.item_spec;
     a.khat += b * in.item_spec;
@@ -63,12 +64,16 @@ __host__ __device__ constexpr bool row_has_inv(int op) {
 }
 __host__ __device__ constexpr bool row_has_fwd(int op) {
   return op == ROW_PSF || op == ROW_MASKS || op == ROW_FIELD || op == ROW_RATIO ||
-         op == ROW_RLUPD || op == ROW_DIR || op == ROW_UPD;
+         op == ROW_RLUPD || op == ROW_DIR || op == ROW_AD || op == ROW_UPD;
 }
 __host__ __device__ constexpr int row_nslots(int op) {
   return op == ROW_RATIO ? 1 : op == ROW_SETUPGRAD ? 2 : op == ROW_DIR ? 1 :
-         op == ROW_AD ? 2 : op == ROW_UPD ? 1 : op == ROW_GRAD ? 4 : 0;
+         op == ROW_AD ? 3 : op == ROW_UPD ? 1 : op == ROW_GRAD ? 4 : 0;
 }
+// First partials slot of a row op.  The KL sum of the update lands in slot
+// 2 whichever pass made the update (the A d pass for lambda = 1, whose slots
+// 0, 1 hold the Armijo sums; the update pass otherwise).
+__host__ __device__ constexpr int row_slot0(int op) { return op == ROW_UPD ? 2 : 0; }
 // Iteration kernels whose reduction is finished by a separate one-workgroup
 // launch (row_fin_kernel) instead of the last workgroup: the last-workgroup
 // pattern needs a device-scope release in every workgroup, which writes back
@@ -184,7 +189,9 @@ __device__ __forceinline__ float dir_value(float f, float gr, float w, const Row
 }
 
 // Units per load chunk: the largest divisor of nu not above cap (8; 4 in
-// the gradient pass, which with 8 would exceed 128 registers and spill).
+// the gradient pass and 2 in the A d pass, which with more would exceed 128
+// registers and spill; the A d pass measured faster so, with the register
+// handoff, than with chunks of 4 through LDS).
 __host__ __device__ constexpr int row_chunk(int nu, int cap = 8) {
   int c = nu < cap ? nu : cap;
   while (nu % c) --c;
@@ -192,8 +199,7 @@ __host__ __device__ constexpr int row_chunk(int nu, int cap = 8) {
 }
 
 // Row ops that keep the data between their transforms and the pointwise
-// stage in registers.  The ratio pass holds the most loads in flight; with
-// the transform data on top it spills.
+// stage in registers.  The ratio pass would then spill.
 __host__ __device__ constexpr bool row_regs_ok(int op) {
   return op != ROW_RATIO;
 }
@@ -233,7 +239,7 @@ __device__ __forceinline__ RowIn row_load(const Args& a, int j, int y, int x) {
     if (P.inS(y, x)) {
       const long long s = P.s_of(y, x);
       in.c[0] = a.g[s];
-      in.c[1] = a.Af[s];
+      in.c[1] = a.Af[s];  // A f of this iteration (see the buffer swap in row_kernel)
       in.c[2] = P.bg(s);
     }
   } else if constexpr (OP == ROW_UPD) {
@@ -308,14 +314,25 @@ __device__ __forceinline__ float row_point(const Args& a, const RowScal& sc, int
     acc[0] += (double)gr * (double)dd;
     return dd;
   } else if constexpr (OP == ROW_AD) {
+    // A_j d, the Armijo sums for lambda = 1, theta, and the update of
+    // Algorithm 1 step 6 for lambda = 1 (the usual outcome; ROW_UPD redoes it
+    // for another lambda): A_j f + A_j d into the other A f buffer, its KL,
+    // and delta rho_j = -g A_j d / (y_old y_new) for the adjoint
     if (!P.inS(y, x)) return 0.f;
     const long long s = P.s_of(y, x);
     st_nt(&a.Ad[s], v);
     const float g = in.c[0];
-    const float yv = fmaxf(in.c[1] + in.c[2], 1e-30f);
+    const float afo = in.c[1];
+    const float bgv = in.c[2];
+    const float yv = fmaxf(afo + bgv, 1e-30f);
     acc[0] += armijo_term(g, yv, sc.lam0 * v);
     acc[1] += armijo_term(g, yv, sc.lam1 * v);
-    return 0.f;
+    const float step = sc.lam0 * v;  // lambda = 1
+    const float afn = afo + step;
+    a.Af2[s] = afn;
+    const float yn = fmaxf(afn + bgv, 1e-30f);
+    acc[2] += kl_term(g, yn);
+    return g > 0.f ? -g * step / (yv * yn) : 0.f;
   } else if constexpr (OP == ROW_UPD) {
     // A_j f += lam A_j d (f += lam d is taken by the gradient pass, which
     // reads f and d anyway); feeds delta rho_j = g/y_new - g/y_old
@@ -328,7 +345,7 @@ __device__ __forceinline__ float row_point(const Args& a, const RowScal& sc, int
     const float afo = in.c[2];
     const float step = lam * in.c[3];
     const float afn = afo + step;
-    a.Af[s] = afn;
+    a.Af2[s] = afn;  // the other A f buffer (see the buffer swap in row_kernel)
     const float g = in.c[4];
     const float yo = fmaxf(afo + bgv, 1e-30f);
     const float yn = fmaxf(afn + bgv, 1e-30f);
@@ -397,7 +414,7 @@ __device__ void deferred_fin(const Args& a, DevState* st) {
     if (threadIdx.x == 0) row_finalize<ROW_DIR>(st, a, t);
   } else if (a.fin_op - 1 == ROW_UPD) {
     double t[1];
-    sum_partials<NT, 1>(RowKinds{ROW_UPD}, a.part, a.fin_nblk, t);
+    sum_partials<NT, 1>(RowKinds{ROW_UPD}, a.part + (long long)row_slot0(ROW_UPD) * a.fin_nblk, a.fin_nblk, t);
     if (threadIdx.x == 0) row_finalize<ROW_UPD>(st, a, t);
   } else if (a.fin_op - 1 == ROW_GRAD) {
     double t[4];
@@ -431,7 +448,7 @@ template <int L> struct RowCfg {
 
 template <int L, int OP>
 __global__ __launch_bounds__(RowCfg<L>::NT) void row_kernel(Args a_in) {
-  const Args a = batch_view(a_in);
+  Args a = batch_view(a_in);
   using P = FftPlan<L>;
   constexpr int TF = P::TF;
   constexpr int RP = RowCfg<L>::RP;
@@ -442,8 +459,20 @@ __global__ __launch_bounds__(RowCfg<L>::NT) void row_kernel(Args a_in) {
   __shared__ float2 twl[L];  // twiddles staged in LDS in pass order
   DevState* st = a.st;
   // the gradient pass also runs after a stop when an accepted step still
-  // has to be applied to f
+  // has to be applied to f; the update pass only when lambda is not 1
   if (a.iter && ((st->done && !(OP == ROW_GRAD && st->f_pending)) || st->pause)) return;
+  if constexpr (OP == ROW_UPD) {
+    if (a.iter && st->spec_ok) return;
+  }
+  if constexpr (OP == ROW_AD || OP == ROW_UPD) {
+    // A f alternates between two buffers: iteration k reads Af (k even) or
+    // Af2 (k odd) and writes the other; from here on a.Af is the one read
+    if (st->k & 1) {
+      float* t = a.Af;
+      a.Af = a.Af2;
+      a.Af2 = t;
+    }
+  }
   const int tid = threadIdx.x;
   const int j = blockIdx.y + a.j0;
   const int wg = xcd_remap(blockIdx.x, gridDim.x, kRP / RP);
@@ -493,7 +522,7 @@ __global__ __launch_bounds__(RowCfg<L>::NT) void row_kernel(Args a_in) {
     const RowScal sc = row_scalars<OP>(st, j);
     constexpr int NU = RP * L / NT;  // units (pixel pairs) per thread
     static_assert(NU * NT == RP * L, "threads must tile the rows");
-    constexpr int CH = OP == ROW_GRAD ? row_chunk(NU, 4) : row_chunk(NU);
+    constexpr int CH = OP == ROW_GRAD ? row_chunk(NU, 4) : OP == ROW_AD ? row_chunk(NU, 2) : row_chunk(NU);
     static_assert(NU % CH == 0, "chunks must tile the units");
 #pragma unroll
     for (int c0 = 0; c0 < NU; c0 += CH) {
@@ -558,7 +587,7 @@ __global__ __launch_bounds__(RowCfg<L>::NT) void row_kernel(Args a_in) {
   if constexpr (NS > 0) if (reduce) {
     const int bid = blockIdx.y * gridDim.x + blockIdx.x;
     if constexpr (row_deferred_fin(OP)) {
-      block_partials<NT, NS>(acc, RowKinds{OP}, a.part, a.nblk, bid);
+      block_partials<NT, NS>(acc, RowKinds{OP}, a.part + (long long)row_slot0(OP) * a.nblk, a.nblk, bid);
     } else {
       double tot[NS];
       if (grid_reduce<NT, NS>(acc, RowKinds{OP}, a.part, a.counter, a.nblk, bid, tot))

@@ -35,6 +35,7 @@ __device__ void armijo_tail(const Args& a, DevState* st) {
   __shared__ int go;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const long long nS = (long long)a.ny * a.nx;
+  const float* af = (st->k & 1) ? a.Af2 : a.Af;  // A f of this iteration
   for (int m0 = 2 + kArmCand; m0 <= st->max_backtracks; m0 += kArmCand) {
     const int n = min(kArmCand, st->max_backtracks + 1 - m0);
     double acc[kArmCand];
@@ -44,7 +45,7 @@ __device__ void armijo_tail(const Args& a, DevState* st) {
       const int j = (int)(i / nS);
       const float adv = a.Ad[i];
       const float g = a.g[i];
-      const float yv = fmaxf(a.Af[i] + (a.bmap ? a.bmap[i] : pick_b(a, j)), 1e-30f);
+      const float yv = fmaxf(af[i] + (a.bmap ? a.bmap[i] : pick_b(a, j)), 1e-30f);
 #pragma unroll
       for (int m = 0; m < kArmCand; ++m)
         if (m < n) acc[m] += armijo_term(g, yv, (float)st->lam_tab[m0 + m] * adv);
@@ -182,11 +183,12 @@ __global__ __launch_bounds__(kPixThreads) void pix_kernel(Args a_in) {
   } else if constexpr (OP == PIX_ARMIJO) {
     constexpr int m0 = 2;
     const int n = st->max_backtracks + 1 - m0;  // candidates theta^m0 .. theta^max_backtracks
+    const float* af = (st->k & 1) ? a.Af2 : a.Af;  // A f of this iteration
     for (long long i = i0; i < a.p * nS; i += stride) {
       const int j = (int)(i / nS);
       const float adv = a.Ad[i];
       const float g = a.g[i];
-      const float yv = fmaxf(a.Af[i] + (a.bmap ? a.bmap[i] : pick_b(a, j)), 1e-30f);
+      const float yv = fmaxf(af[i] + (a.bmap ? a.bmap[i] : pick_b(a, j)), 1e-30f);
 #pragma unroll
       for (int m = 0; m < NS; ++m) {
         if (m < n) acc[m] += armijo_term(g, yv, (float)st->lam_tab[m0 + m] * adv);
@@ -233,9 +235,9 @@ __global__ __launch_bounds__(kPixThreads) void pix_kernel(Args a_in) {
   }
   if constexpr (NS > 0) {
     double tot[NS];
-    // the Armijo kernel keeps ROW_AD's partials intact: slower workgroups may
-    // still be reading them
-    double* part = OP == PIX_ARMIJO ? a.part + 2 * a.fin_nblk : a.part;
+    // the Armijo kernel keeps ROW_AD's partials (Armijo sums, KL) intact:
+    // slower workgroups may still be reading them
+    double* part = OP == PIX_ARMIJO ? a.part + 3 * a.fin_nblk : a.part;
     if (grid_reduce<kPixThreads, NS>(acc, kinds, part, a.counter, a.nblk, blockIdx.x, tot)) {
       if constexpr (OP == PIX_VALIDATE) {
         if (tot[0] < 0.0 || tot[1] > 0.0) st->flags |= FLAG_BAD_DATA;
@@ -281,7 +283,7 @@ __global__ __launch_bounds__(kFinThreads) void row_fin_kernel(Args a_in) {
   if (a.iter && (st->done || st->pause)) return;
   constexpr int NS = row_nslots(OP);
   double tot[NS];
-  sum_partials<kFinThreads, NS>(RowKinds{OP}, a.part, a.nblk, tot);
+  sum_partials<kFinThreads, NS>(RowKinds{OP}, a.part + (long long)row_slot0(OP) * a.nblk, a.nblk, tot);
   if (threadIdx.x == 0) row_finalize<OP>(st, a, tot);
 }
 

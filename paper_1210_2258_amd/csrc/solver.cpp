@@ -63,6 +63,7 @@ struct Plan {
   float* invw = nullptr;
   float* invwj = nullptr;  // boundary OSEM: [p][NY][NX] per-image weights M_R / alpha_j
   float* Af = nullptr;
+  float* Af2 = nullptr;  // SGP: the second A f buffer (iterations alternate)
   float* Ad = nullptr;
   float* aux = nullptr;
   float2* spec = nullptr;
@@ -85,7 +86,7 @@ struct Plan {
   int* zmap = nullptr;
 
   ~Plan() {
-    void* ptrs[] = {grad, d, invw, invwj, Af, Ad, aux, spec, khat, knyq, tw_row, tw_col, part, counter, st, trace,
+    void* ptrs[] = {grad, d, invw, invwj, Af, Af2, Ad, aux, spec, khat, knyq, tw_row, tw_col, part, counter, st, trace,
                     (void*)gtab, (void*)ftab, (void*)psftab, (void*)srctab, btab, zmap};
     for (void* q : ptrs)
       if (q) (void)hipFree(q);
@@ -117,10 +118,10 @@ constexpr int kArmBlocks = 512;
 
 static size_t part_capacity(const PlanKey& k) {
   // row kernels: at most NY / 2 workgroups per image and 4 slots; the Armijo
-  // kernel keeps ROW_AD's 2 slots and adds 8 slots of its own
+  // kernel keeps ROW_AD's 3 slots and adds 8 slots of its own
   const size_t row_blocks = (size_t)(k.NY / 2) * k.p;
   return std::max<size_t>({(size_t)(kMaxCand) * kMaxPixBlocks, 4 * row_blocks,
-                           2 * row_blocks + (size_t)8 * kArmBlocks});
+                           3 * row_blocks + (size_t)8 * kArmBlocks});
 }
 
 template <class T>
@@ -150,6 +151,7 @@ static int make_plan(const PlanKey& key, hipStream_t s, std::unique_ptr<Plan>& p
   }
   if ((rc = dalloc(&pl->Af, nS * key.p))) return rc;
   if (key.kind == KIND_SGP && (rc = dalloc(&pl->Ad, nS * key.p))) return rc;
+  if (key.kind == KIND_SGP && (rc = dalloc(&pl->Af2, nS * key.p))) return rc;
   if ((rc = dalloc(&pl->spec, nSpec * key.p))) return rc;
   if ((rc = dalloc(&pl->khat, nSpec * key.p))) return rc;
   if ((rc = dalloc(&pl->knyq, (size_t)key.NY * key.p * n))) return rc;
@@ -814,7 +816,7 @@ static int create_items(int kind, const std::vector<Problem>& items, const std::
   a.f = fs[0]; a.grad = pl->grad; a.d = pl->d;
   a.invw = pb.boundary ? pl->invw : nullptr;
   a.invw_s = 1.0f / (float)pb.p;
-  a.Af = pl->Af; a.Ad = pl->Ad; a.spec = pl->spec; a.khat = pl->khat; a.knyq = pl->knyq;
+  a.Af = pl->Af; a.Af2 = pl->Af2; a.Ad = pl->Ad; a.spec = pl->spec; a.khat = pl->khat; a.knyq = pl->knyq;
   a.psf = pb.psf; a.aux = pl->aux; a.src = S->prm.f0;
   a.tw_row = pl->tw_row; a.tw_col = pl->tw_col;
   a.part = pl->part; a.counter = pl->counter; a.st = pl->st;
