@@ -299,8 +299,8 @@ def cpu_baseline(w, iters):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
-              "(the multi-GPU design is described in DESIGN.md, not built)", file=sys.stderr)
+        print(f"bench.py: the solver runs on one GPU; --gpus {args.gpus} is not supported "
+              "(sharding over several GPUs is designed, not implemented)", file=sys.stderr)
         sys.exit(2)
     batch_items = None if args.no_batch else make_batch_inputs(args.batch_images)
     import numpy as np
