@@ -224,7 +224,8 @@ def sgp_deconv(g, psf, b=0.0, *, b_map=None, f=None, stream=None, trace=False, *
 
 
 def rl_deconv(g, psf, b=0.0, *, b_map=None, f=None, stream=None, trace=False, **params):
-    """Richardson-Lucy single-image deconvolution; returns (f, report)."""
+    """Richardson-Lucy single-image deconvolution (Eq. (RL); with rl_alpha != 1
+    the multiplicative relaxation of Eq. (RL1)); returns (f, report)."""
     return _solve_single(load().rl_deconv, g, psf, b, b_map, f, stream, trace, params)
 
 
