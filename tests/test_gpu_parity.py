@@ -211,6 +211,26 @@ def test_sgp_many_backtracks(torch_dev, alpha0):
     assert abs(rep["kl"] - io["kl"]) <= KL_TOL * io["kl"], (rep["kl"], io["kl"])
 
 
+@pytest.mark.parametrize("case", ["multi_3x64", "boundary_64x48_in_80x64"])
+@pytest.mark.parametrize("alpha0", [1e1, 1e2])
+def test_sgp_backtracks_multi_and_boundary(torch_dev, case, alpha0):
+    """Backtracking on the three-image and the boundary-corrected problems:
+    one reduction at alpha0 = 10 (the update for theta redone by the update
+    pass, the A f buffers alternating), 3-4 at 1e2 (the candidate pass of the
+    Armijo kernel first)."""
+    w = CASES[case]()
+    n = 4
+    fn = "sgp_multi_deconv" if w.domain is None else "sgp_boundary_deconv"
+    f, rep = _run_gpu(torch_dev, fn, w, max_iter=n, alpha0=alpha0)
+    P = _oracle(w)
+    fo, io = P.sgp(P.start("flat"), O.Params(max_iter=n, alpha0=alpha0))
+    assert io["log"][0]["backtracks"] >= 1
+    _check_log(rep["trace"], io["log"], n)
+    assert rep["backtracks"] == sum(L["backtracks"] for L in io["log"][:n])
+    assert _rel(f.cpu().numpy(), fo) <= F_TOL, _rel(f.cpu().numpy(), fo)
+    assert abs(rep["kl"] - io["kl"]) <= KL_TOL * io["kl"], (rep["kl"], io["kl"])
+
+
 def test_sgp_decision_log_long_horizon(torch_dev):
     """Armijo and alternation decisions agree far past the fixed-count window
     on the 256x256 star field (their margins are wide)."""
