@@ -11,3 +11,52 @@ if ROOT not in sys.path:
 def pytest_configure(config):
     config.addinivalue_line("markers", "gpu: needs an MI355X (gfx950) GPU")
     config.addinivalue_line("markers", "slow: long-running CPU test")
+
+
+@pytest.fixture
+def one_step_at_depth():
+    """Returns check(torch, w, depth, f_tol, kl_tol): the HIP path's SGP
+    iteration number ``depth`` against one FP64 oracle iteration started from
+    the HIP path's own iterate f_depth, steplength alpha_depth and bounds
+    L1, L2.  Whole trajectories part after some tens of iterations (the
+    Barzilai-Borwein steplengths amplify FP32 rounding), while this compares
+    the arithmetic of one iteration at any depth: the Armijo decision, the
+    updated f and its KL, and the two Barzilai-Borwein values formed from
+    the new gradient."""
+    import numpy as np
+
+    from oracle import sgp as O
+
+    def check(torch, w, depth, f_tol, kl_tol):
+        import paper_1210_2258_amd as m
+        dev = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+        stacked = w.p > 1 or w.domain is not None
+        g = dev(w.g if stacked else w.g[0])
+        psf = dev(w.psf if stacked else w.psf[0])
+        b = w.b if stacked else float(w.b[0])
+        # two iterations past the one checked: the capped last iteration
+        # does not form the next steplength
+        S = m.Solver(m.KIND_SGP, g, psf, b, domain=w.domain, trace=True, max_iter=depth + 2)
+        S.step(depth)
+        torch.cuda.synchronize()
+        fk = S.f.cpu().numpy().astype(np.float64)
+        S.step(1)
+        torch.cuda.synchronize()
+        f1 = S.f.cpu().numpy()
+        rep = S.report()
+        S.close()
+        assert rep["iters"] == depth + 1
+        tr = {k: v[depth] for k, v in rep["trace"].items()}
+        P = O.Problem(w.g, w.psf, w.b, domain=w.domain)
+        fo, io = P.sgp(fk, O.Params(max_iter=1, alpha0=float(tr["alpha"])),
+                       bounds=(rep["L1"], rep["L2"]))
+        L = io["log"][0]
+        assert int(tr["backtracks"]) == L["backtracks"], (tr["backtracks"], L["backtracks"])
+        rel = float(np.linalg.norm(f1.astype(np.float64) - fo) / np.linalg.norm(fo))
+        assert rel <= f_tol, rel
+        assert abs(rep["kl"] - io["kl"]) <= kl_tol * io["kl"], (rep["kl"], io["kl"])
+        for key in ("a1", "a2"):
+            assert abs(tr[key] - L[key]) <= 1e-2 * abs(L[key]), (key, tr[key], L[key])
+        return rel
+
+    return check

@@ -47,6 +47,16 @@ def test_full_size_sgp_parity(torch_dev, cfg):
     assert abs(rep["kl"] - io["kl"]) <= 1e-6 * io["kl"], (rep["kl"], io["kl"])
 
 
+@pytest.mark.parametrize("cfg,depth", [("c1_2048", 15), ("c2_multi_3x1024", 40),
+                                        ("c3_boundary_1280", 40)])
+def test_full_size_one_iteration_at_depth(torch_dev, one_step_at_depth, cfg, depth):
+    """Iteration ``depth`` from the GPU's own iterate against one oracle
+    iteration (the 2048x2048 field reaches the discrepancy level at its 16th
+    iteration, depth 15)."""
+    w = {"c1_2048": W.config1, "c2_multi_3x1024": W.config2, "c3_boundary_1280": W.config3}[cfg]()
+    one_step_at_depth(torch_dev, w, depth, 1e-4, 1e-6)
+
+
 @pytest.mark.parametrize("a", [1.0, 1.7])
 def test_full_size_rl_parity(torch_dev, a):
     """RL and its multiplicative relaxation (Eq. (RL1)) on the 2048x2048 field."""

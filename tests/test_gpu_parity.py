@@ -176,6 +176,15 @@ def test_sgp_fixed_iterations(torch_dev, case):
     assert abs(rep["kl"] - io["kl"]) <= KL_TOL * io["kl"], (rep["kl"], io["kl"])
 
 
+@pytest.mark.parametrize("case,depth", [("single_c0_256", 50), ("single_c0_256", 99),
+                                        ("multi_3x64", 40), ("boundary_64x48_in_80x64", 40)])
+def test_sgp_one_iteration_at_depth(torch_dev, one_step_at_depth, case, depth):
+    """Past the fixed-count window: iteration ``depth`` (the 100th of the
+    256x256 field's fixed-count run at depth 99) from the GPU's own iterate
+    against one oracle iteration, to the parity bar."""
+    one_step_at_depth(torch_dev, CASES[case](), depth, F_TOL, KL_TOL)
+
+
 @pytest.mark.parametrize("case", ["single_64x80", "multi_3x64"])
 def test_sgp_alternation_branch(torch_dev, case):
     """n_bb2_only = 2 makes the alternation of Eq. (alphadef) act within the
