@@ -63,6 +63,8 @@ def parse():
     ap.add_argument("--batch-images", type=int, default=512)
     ap.add_argument("--no-multi", action="store_true", help="skip the multi-image RL / OSEM / SGP comparison")
     ap.add_argument("--no-mosaic", action="store_true", help="skip the mosaic leg")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep tile variant 0 instead of timing the tile variants per FFT length")
     ap.add_argument("--sweep", action="store_true",
                     help="also run the Fourier re-binning size sweep 256..2048 (RL and SGP, GPU and oracle)")
     return ap.parse_args()
@@ -83,7 +85,15 @@ def make_batch_inputs(n):
         return list(ex.map(_c4_item, range(n), chunksize=8))
 
 
-def batch_legs(torch, m, items):
+def tune(m, g, psf, b, iters, record):
+    """Autotuner of the FFT tile schedule on one problem of this size; the
+    choice stays in the library's table for the runs that follow."""
+    r, c, ms = m.autotune(g, psf, b, iters=iters)
+    record["x".join(map(str, g.shape))] = {"rows_variant": r, "cols_variant": c,
+                                           "ms_per_iter": {f"{k[0]}{k[1]}": v for k, v in ms.items()}}
+
+
+def batch_legs(torch, m, items, tiles=None):
     """Plain (one image at a time, flat start), flat batch and warm batch,
     each timed from call to return with the inputs resident."""
     import numpy as np
@@ -93,10 +103,13 @@ def batch_legs(torch, m, items):
     bs = [b for _, _, b in items]
     kw = dict(max_iter=3000, stop=m.STOP_DISCREPANCY | m.STOP_CONV, tol=1e-7)
     net = WS.load_net()
-    # warm-up: workspaces of every shape and group size, network buffers
     seen = {}
     for i, g in enumerate(gs):
         seen.setdefault(tuple(g.shape), i)
+    if tiles is not None:  # tile schedule of every size in the batch, before any timed leg
+        for i in seen.values():
+            tune(m, gs[i], ps[i], bs[i], 50, tiles)
+    # warm-up: workspaces of every shape and group size, network buffers
     for i in seen.values():
         m.sgp_deconv(gs[i], ps[i], bs[i], max_iter=2)
     m.batch_deconv(gs, ps, bs, max_iter=1)
@@ -333,6 +346,11 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
+    tiles = None
+    if not args.no_autotune:
+        tiles = {}
+        tune(m, g, psf, b, 40, tiles)
+
     # ---- throughput: W warm-up iterations, then exactly K timed iterations
     total = args.warmup + args.steps
     S = m.Solver(m.KIND_SGP, g, psf, b, max_iter=total + 10)
@@ -393,7 +411,9 @@ def main():
         **out_ttd,
     }
     if batch_items is not None:
-        out["batch_512"] = batch_legs(torch, m, batch_items)
+        out["batch_512"] = batch_legs(torch, m, batch_items, tiles)
+    if tiles is not None:
+        out["tile_schedule"] = tiles
     if not args.no_multi:
         out["multi_image_3x1024"] = multi_image_legs(torch, m, W.config2())
     if not args.no_mosaic and f_full is not None:

@@ -291,6 +291,56 @@ int sgp_mosaic_deconv(int kind, const float* g, int H, int W, const float* psf, 
 int sgp_steplength_rule(const sgp_params* prm, int k, double alpha, double tau, const double* Q,
                         int nQ, double a, double c1, double c2, double e, double* out);
 
+/* ---------------------------------------------------------------------------
+ * FFT tile schedule and its autotuner.  The FFTs are the main cost of an
+ * iteration (Sect. 3.4, Sect. 5); the radix sequence of each length is fixed,
+ * and the workgroup shape of its row and column passes comes in two tile
+ * variants per length L:
+ *   rows    variant 0: as many row pairs per workgroup as fit 1024 threads
+ *                      (at most the 8-row block); variant 1: half as many;
+ *   columns variant 0: as many columns as fit 256 threads and 40 KB of LDS;
+ *           variant 1: twice as many (512 threads) where the LDS tile allows,
+ *                      else half as many.
+ * A variant that cannot differ at some L (it would leave a wavefront
+ * partly empty or overflow the LDS) equals variant 0 there.  Both variants
+ * compute the same per-pixel arithmetic; the FP64 reductions may add their
+ * per-workgroup partial sums in another grouping.  The schedule is one
+ * process-wide table indexed by L (variant 0 where unset); a solver or
+ * one-shot call reads it when it starts (rows of length NX, columns of
+ * length NY) and keeps those variants.  Table calls are thread-safe.
+ * ------------------------------------------------------------------------- */
+
+/* Shape of tile variant `variant` (0/1) at FFT length L: threads per
+ * workgroup and row pairs of the row kernel, threads and columns of the
+ * column kernel (each output optional).  Host only, no device needed.
+ * SGP_E_UNSUPPORTED_SIZE for a length the library has no FFT for. */
+int sgp_tile_info(int L, int variant, int* row_threads, int* row_pairs, int* col_threads, int* col_width);
+/* Sets / reads the variants used for rows and for columns of length L. */
+int sgp_set_tile_schedule(int L, int row_variant, int col_variant);
+int sgp_get_tile_schedule(int L, int* row_variant, int* col_variant);
+/* Writes the table to a text file (a comment line, then one line
+ * "L row_variant col_variant" per length set) / reads such a file and
+ * applies every line.  A malformed line, unsupported length or variant other
+ * than 0/1 fails the whole load with SGP_E_INVALID_ARG (naming the line) and
+ * applies nothing; so does a file that cannot be opened. */
+int sgp_save_tile_schedule(const char* path);
+int sgp_load_tile_schedule(const char* path);
+/* Autotuner: times `iters` SGP iterations of the caller's problem (periodic,
+ * multi-image or boundary, as for sgp_solver_create; 1 <= iters <= 100000)
+ * under every distinct combination of row variant (length NX) and column
+ * variant (length NY): one untimed call that captures the graph, then three
+ * timed calls of `iters` iterations each, whose median wall time per
+ * iteration is the combination's time.  The fastest combination is set in
+ * the table and returned in *row_variant / *col_variant (optional).
+ * ms (optional, 4 doubles): ms per iteration of (row, column) = (0,0),
+ * (0,1), (1,0), (1,1); -1 for a combination equal to one already timed.
+ * f: device [NY][NX], caller-owned scratch that is overwritten.  The problem
+ * must run 4 iters iterations without a stop (fixed-count SGP: only a
+ * numerical failure stops it), otherwise SGP_E_INVALID_ARG.  On any error
+ * the table is left as it was.  Synchronous on return. */
+int sgp_autotune(const sgp_problem* prob, float* f, int iters, int* row_variant, int* col_variant, double* ms,
+                 void* hip_stream);
+
 /* Releases every cached workspace of the calling process on the current device. */
 int sgp_release_cache(void);
 

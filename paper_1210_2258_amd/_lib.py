@@ -74,6 +74,8 @@ EXPORTS = [
     "sgp_steplength_rule", "sgp_batch_deconv", "osem_deconv", "osem_boundary_deconv", "sgp_mosaic_deconv",
     "sgp_cnn_num_params", "sgp_cnn_create", "sgp_cnn_get_params", "sgp_cnn_infer", "sgp_cnn_loss_grad",
     "sgp_cnn_adam_step", "sgp_cnn_train_step", "sgp_cnn_destroy",
+    "sgp_tile_info", "sgp_set_tile_schedule", "sgp_get_tile_schedule", "sgp_save_tile_schedule",
+    "sgp_load_tile_schedule", "sgp_autotune",
 ]
 
 _lib = None
@@ -119,6 +121,13 @@ def load():
     lib.sgp_cnn_train_step.argtypes = [vp, i, ctypes.POINTER(vp), fp, ctypes.POINTER(vp), i, i, f,
                                        ctypes.POINTER(d), vp]
     lib.sgp_cnn_destroy.argtypes = [vp]
+    ip = ctypes.POINTER(i)
+    lib.sgp_tile_info.argtypes = [i, i, ip, ip, ip, ip]
+    lib.sgp_set_tile_schedule.argtypes = [i, i, i]
+    lib.sgp_get_tile_schedule.argtypes = [i, ip, ip]
+    lib.sgp_save_tile_schedule.argtypes = [ctypes.c_char_p]
+    lib.sgp_load_tile_schedule.argtypes = [ctypes.c_char_p]
+    lib.sgp_autotune.argtypes = [ctypes.POINTER(_Problem), vp, i, ip, ip, ctypes.POINTER(d), vp]
     lib.sgp_strerror.restype = ctypes.c_char_p
     lib.sgp_strerror.argtypes = [i]
     lib.sgp_last_error.restype = ctypes.c_char_p
@@ -326,6 +335,59 @@ def apply_operator(psf, x, adjoint=False, out=None, stream=None):
 
 def release_cache():
     return load().sgp_release_cache()
+
+
+def tile_info(L, variant):
+    """Workgroup shape of tile variant ``variant`` at FFT length L (no GPU
+    needed): row-kernel threads and row pairs, column-kernel threads and
+    columns."""
+    lib = load()
+    v = [ctypes.c_int() for _ in range(4)]
+    _raise(lib.sgp_tile_info(int(L), int(variant), *[ctypes.byref(x) for x in v]))
+    return dict(row_threads=v[0].value, row_pairs=v[1].value, col_threads=v[2].value, col_width=v[3].value)
+
+
+def set_tile_schedule(L, row_variant, col_variant):
+    _raise(load().sgp_set_tile_schedule(int(L), int(row_variant), int(col_variant)))
+
+
+def get_tile_schedule(L):
+    r, c = ctypes.c_int(), ctypes.c_int()
+    _raise(load().sgp_get_tile_schedule(int(L), ctypes.byref(r), ctypes.byref(c)))
+    return r.value, c.value
+
+
+def save_tile_schedule(path):
+    _raise(load().sgp_save_tile_schedule(os.fsencode(path)))
+
+
+def load_tile_schedule(path):
+    _raise(load().sgp_load_tile_schedule(os.fsencode(path)))
+
+
+def autotune(g, psf, b, *, domain=None, iters=20, stream=None):
+    """Times every distinct tile combination on this problem (``g``/``psf``
+    as for Solver) and keeps the fastest in the schedule table.  Returns
+    (row_variant, col_variant, ms) with ms[(r, c)] the median ms per
+    iteration (absent for a combination equal to another)."""
+    import torch
+    lib = load()
+    _check_dev(g, "g")
+    _check_dev(psf, "psf")
+    g3 = g.unsqueeze(0) if g.dim() == 2 else g
+    psf3 = psf.unsqueeze(0) if psf.dim() == 2 else psf
+    p, ny, nx = g3.shape
+    NY, NX, oy, ox = domain if domain is not None else (ny, nx, 0, 0)
+    bc = _bconst(b, p)
+    pr = _Problem(g3.data_ptr(), psf3.data_ptr(), None, ctypes.cast(bc, ctypes.c_void_p), p, ny, nx, NY, NX,
+                  oy, ox, 1 if domain is not None else 0)
+    f = torch.empty((NY, NX), dtype=torch.float32, device=g.device)
+    r, c = ctypes.c_int(), ctypes.c_int()
+    ms = (ctypes.c_double * 4)()
+    _raise(lib.sgp_autotune(ctypes.byref(pr), ctypes.c_void_p(f.data_ptr()), int(iters), ctypes.byref(r),
+                            ctypes.byref(c), ms, _stream(stream)))
+    times = {(k >> 1, k & 1): ms[k] for k in range(4) if ms[k] >= 0}
+    return r.value, c.value, times
 
 
 class Solver:

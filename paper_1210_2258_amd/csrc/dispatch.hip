@@ -8,12 +8,12 @@
 namespace sgp {
 
 #define SGP_DECL(L)                                                           \
-  void launch_row_##L(int op, dim3 grid, const Args& a, hipStream_t s);       \
-  void launch_col_##L(int mode, int conj, dim3 grid, const Args& a, hipStream_t s); \
-  int col_width_##L();                                                        \
-  int row_threads_##L();                                                      \
-  int row_pairs_##L();                                                        \
-  int col_threads_##L();
+  void launch_row_##L(int op, int v, dim3 grid, const Args& a, hipStream_t s); \
+  void launch_col_##L(int mode, int conj, int v, dim3 grid, const Args& a, hipStream_t s); \
+  int col_width_##L(int v);                                                   \
+  int row_threads_##L(int v);                                                 \
+  int row_pairs_##L(int v);                                                   \
+  int col_threads_##L(int v);
 SGP_SIZES(SGP_DECL)
 #undef SGP_DECL
 
@@ -26,54 +26,54 @@ bool size_supported(int L) {
   }
 }
 
-int col_width(int L) {
+int col_width(int L, int v) {
   switch (L) {
-#define SGP_CASE(L) case L: return col_width_##L();
+#define SGP_CASE(L) case L: return col_width_##L(v);
     SGP_SIZES(SGP_CASE)
 #undef SGP_CASE
     default: return 0;
   }
 }
 
-int row_pairs(int L) {
+int row_pairs(int L, int v) {
   switch (L) {
-#define SGP_CASE(L) case L: return row_pairs_##L();
+#define SGP_CASE(L) case L: return row_pairs_##L(v);
     SGP_SIZES(SGP_CASE)
 #undef SGP_CASE
     default: return 0;
   }
 }
 
-int row_threads(int L) {
+int row_threads(int L, int v) {
   switch (L) {
-#define SGP_CASE(L) case L: return row_threads_##L();
+#define SGP_CASE(L) case L: return row_threads_##L(v);
     SGP_SIZES(SGP_CASE)
 #undef SGP_CASE
     default: return 0;
   }
 }
 
-int col_threads(int L) {
+int col_threads(int L, int v) {
   switch (L) {
-#define SGP_CASE(L) case L: return col_threads_##L();
+#define SGP_CASE(L) case L: return col_threads_##L(v);
     SGP_SIZES(SGP_CASE)
 #undef SGP_CASE
     default: return 0;
   }
 }
 
-void launch_row(int L, int op, dim3 grid, const Args& a, hipStream_t s) {
+void launch_row(int L, int v, int op, dim3 grid, const Args& a, hipStream_t s) {
   switch (L) {
-#define SGP_CASE(L) case L: launch_row_##L(op, grid, a, s); break;
+#define SGP_CASE(L) case L: launch_row_##L(op, v, grid, a, s); break;
     SGP_SIZES(SGP_CASE)
 #undef SGP_CASE
     default: break;
   }
 }
 
-void launch_col(int L, int mode, int conj, dim3 grid, const Args& a, hipStream_t s) {
+void launch_col(int L, int v, int mode, int conj, dim3 grid, const Args& a, hipStream_t s) {
   switch (L) {
-#define SGP_CASE(L) case L: launch_col_##L(mode, conj, grid, a, s); break;
+#define SGP_CASE(L) case L: launch_col_##L(mode, conj, v, grid, a, s); break;
     SGP_SIZES(SGP_CASE)
 #undef SGP_CASE
     default: break;

@@ -12,11 +12,12 @@
 
 namespace sgp {
 
-void SGP_CAT(launch_row_, SGP_L)(int op, dim3 grid, const Args& a, hipStream_t s) {
+template <int V>
+static void launch_row_v(int op, dim3 grid, const Args& a, hipStream_t s) {
   constexpr int L = SGP_L;
-  const dim3 blk(RowCfg<L>::NT);
+  const dim3 blk(RowCfg<L, V>::NT);
   switch (op) {
-#define SGP_ROW_CASE(OPV) case OPV: hipLaunchKernelGGL((row_kernel<L, OPV>), grid, blk, 0, s, a); break;
+#define SGP_ROW_CASE(OPV) case OPV: hipLaunchKernelGGL((row_kernel<L, OPV, V>), grid, blk, 0, s, a); break;
     SGP_ROW_CASE(ROW_PSF)
     SGP_ROW_CASE(ROW_MASKS)
     SGP_ROW_CASE(ROW_STORE)
@@ -33,23 +34,42 @@ void SGP_CAT(launch_row_, SGP_L)(int op, dim3 grid, const Args& a, hipStream_t s
   }
 }
 
-void SGP_CAT(launch_col_, SGP_L)(int mode, int conj, dim3 grid, const Args& a, hipStream_t s) {
-  constexpr int L = SGP_L;
-  const dim3 blk(ColCfg<L>::NT);
-  if (mode == COL_FWD) hipLaunchKernelGGL((col_kernel<L, COL_FWD, 0>), grid, blk, 0, s, a);
-  else if (mode == COL_CONV && (a.jn ? a.jn : a.p) == 1) {
-    if (conj) hipLaunchKernelGGL((col_kernel<L, COL_CONV1, 1>), grid, blk, 0, s, a);
-    else hipLaunchKernelGGL((col_kernel<L, COL_CONV1, 0>), grid, blk, 0, s, a);
+// a tile variant equal to variant 0 is not instantiated
+constexpr bool kRowV1 = RowCfg<SGP_L, 1>::RP != RowCfg<SGP_L, 0>::RP;
+constexpr bool kColV1 = ColCfg<SGP_L, 1>::C != ColCfg<SGP_L, 0>::C;
+
+void SGP_CAT(launch_row_, SGP_L)(int op, int v, dim3 grid, const Args& a, hipStream_t s) {
+  if constexpr (kRowV1) {
+    if (v == 1) return launch_row_v<1>(op, grid, a, s);
   }
-  else if (mode == COL_CONV && !conj) hipLaunchKernelGGL((col_kernel<L, COL_CONV, 0>), grid, blk, 0, s, a);
-  else if (mode == COL_CONV) hipLaunchKernelGGL((col_kernel<L, COL_CONV, 1>), grid, blk, 0, s, a);
-  else if (a.p == 1) hipLaunchKernelGGL((col_kernel<L, COL_CORR1, 1>), grid, blk, 0, s, a);
-  else hipLaunchKernelGGL((col_kernel<L, COL_CORRSUM, 1>), grid, blk, 0, s, a);
+  launch_row_v<0>(op, grid, a, s);
 }
 
-int SGP_CAT(col_width_, SGP_L)() { return ColCfg<SGP_L>::C; }
-int SGP_CAT(row_threads_, SGP_L)() { return RowCfg<SGP_L>::NT; }
-int SGP_CAT(row_pairs_, SGP_L)() { return RowCfg<SGP_L>::RP; }
-int SGP_CAT(col_threads_, SGP_L)() { return ColCfg<SGP_L>::NT; }
+template <int V>
+static void launch_col_v(int mode, int conj, dim3 grid, const Args& a, hipStream_t s) {
+  constexpr int L = SGP_L;
+  const dim3 blk(ColCfg<L, V>::NT);
+  if (mode == COL_FWD) hipLaunchKernelGGL((col_kernel<L, COL_FWD, 0, V>), grid, blk, 0, s, a);
+  else if (mode == COL_CONV && (a.jn ? a.jn : a.p) == 1) {
+    if (conj) hipLaunchKernelGGL((col_kernel<L, COL_CONV1, 1, V>), grid, blk, 0, s, a);
+    else hipLaunchKernelGGL((col_kernel<L, COL_CONV1, 0, V>), grid, blk, 0, s, a);
+  }
+  else if (mode == COL_CONV && !conj) hipLaunchKernelGGL((col_kernel<L, COL_CONV, 0, V>), grid, blk, 0, s, a);
+  else if (mode == COL_CONV) hipLaunchKernelGGL((col_kernel<L, COL_CONV, 1, V>), grid, blk, 0, s, a);
+  else if (a.p == 1) hipLaunchKernelGGL((col_kernel<L, COL_CORR1, 1, V>), grid, blk, 0, s, a);
+  else hipLaunchKernelGGL((col_kernel<L, COL_CORRSUM, 1, V>), grid, blk, 0, s, a);
+}
+
+void SGP_CAT(launch_col_, SGP_L)(int mode, int conj, int v, dim3 grid, const Args& a, hipStream_t s) {
+  if constexpr (kColV1) {
+    if (v == 1) return launch_col_v<1>(mode, conj, grid, a, s);
+  }
+  launch_col_v<0>(mode, conj, grid, a, s);
+}
+
+int SGP_CAT(col_width_, SGP_L)(int v) { return v == 1 ? ColCfg<SGP_L, 1>::C : ColCfg<SGP_L, 0>::C; }
+int SGP_CAT(row_threads_, SGP_L)(int v) { return v == 1 ? RowCfg<SGP_L, 1>::NT : RowCfg<SGP_L, 0>::NT; }
+int SGP_CAT(row_pairs_, SGP_L)(int v) { return v == 1 ? RowCfg<SGP_L, 1>::RP : RowCfg<SGP_L, 0>::RP; }
+int SGP_CAT(col_threads_, SGP_L)(int v) { return v == 1 ? ColCfg<SGP_L, 1>::NT : ColCfg<SGP_L, 0>::NT; }
 
 }  // namespace sgp

@@ -436,23 +436,28 @@ __device__ __forceinline__ int xcd_remap(int w, int n, int g) {
 
 // ------------------------------------------------------------------ rows
 // RP row pairs (2 RP rows) per workgroup; 4 / RP workgroups share a block.
+// Tile variant V = 0 takes as many row pairs as fit 1024 threads (at most
+// the 8-row block); V = 1 half as many, when that still fills a wavefront
+// (otherwise it equals V = 0).  The per-row transforms and pointwise work are
+// the same in both; the autotuner picks one per row length.
 #ifndef SGP_ROW_THREADS
 #define SGP_ROW_THREADS 1024
 #endif
-template <int L> struct RowCfg {
+template <int L, int V = 0> struct RowCfg {
   static constexpr int TF = FftPlan<L>::TF;
   static constexpr int RP0 = SGP_ROW_THREADS / TF;
-  static constexpr int RP = RP0 < 1 ? 1 : (RP0 > kRP ? kRP : RP0);
+  static constexpr int RPD = RP0 < 1 ? 1 : (RP0 > kRP ? kRP : RP0);
+  static constexpr int RP = (V == 1 && RPD >= 2 && (RPD / 2) * TF >= 64) ? RPD / 2 : RPD;
   static constexpr int NT = RP * TF;
 };
 
-template <int L, int OP>
-__global__ __launch_bounds__(RowCfg<L>::NT) void row_kernel(Args a_in) {
+template <int L, int OP, int V = 0>
+__global__ __launch_bounds__((RowCfg<L, V>::NT)) void row_kernel(Args a_in) {
   Args a = batch_view(a_in);
   using P = FftPlan<L>;
   constexpr int TF = P::TF;
-  constexpr int RP = RowCfg<L>::RP;
-  constexpr int NT = RowCfg<L>::NT;
+  constexpr int RP = RowCfg<L, V>::RP;
+  constexpr int NT = RowCfg<L, V>::NT;
   constexpr int HALF = L / 2;
   constexpr int NS = row_nslots(OP);
   __shared__ float2 buf[RP][L];
@@ -597,20 +602,27 @@ __global__ __launch_bounds__(RowCfg<L>::NT) void row_kernel(Args a_in) {
 }
 
 // --------------------------------------------------------------- columns
-template <int LY> struct ColCfg {
+// C columns per workgroup.  Tile variant V = 0: as many as fit 256 threads
+// and 40 KB of column data; V = 1: twice as many when 512 threads and the
+// doubled LDS tile still fit, else half as many when that still fills a
+// wavefront (otherwise it equals V = 0).
+template <int LY, int V = 0> struct ColCfg {
   static constexpr int TF = FftPlan<LY>::TF;
   static constexpr int C1 = 256 / TF;
   static constexpr int C2 = 40960 / (LY * 8);
-  static constexpr int C = (C1 < C2 ? C1 : C2) < 1 ? 1 : (C1 < C2 ? C1 : C2);
+  static constexpr int CD = (C1 < C2 ? C1 : C2) < 1 ? 1 : (C1 < C2 ? C1 : C2);
+  static constexpr bool DBL = 2 * CD <= C2 && 2 * CD * TF <= 512;
+  static constexpr bool HLV = CD >= 2 && (CD / 2) * TF >= 64;
+  static constexpr int C = V == 0 ? CD : DBL ? 2 * CD : HLV ? CD / 2 : CD;
   static constexpr int NT = C * TF;
 };
 
-template <int LY, int MODE, int CONJ>
-__global__ __launch_bounds__(ColCfg<LY>::NT) void col_kernel(Args a_in) {
+template <int LY, int MODE, int CONJ, int V = 0>
+__global__ __launch_bounds__((ColCfg<LY, V>::NT)) void col_kernel(Args a_in) {
   const Args a = batch_view(a_in);
   constexpr int TF = FftPlan<LY>::TF;
-  constexpr int C = ColCfg<LY>::C;
-  constexpr int NT = ColCfg<LY>::NT;
+  constexpr int C = ColCfg<LY, V>::C;
+  constexpr int NT = ColCfg<LY, V>::NT;
   constexpr int E = LY * C / NT;  // units per thread
   __shared__ float2 buf[C][LY];
   __shared__ float2 twl[LY];  // twiddles staged in LDS in pass order

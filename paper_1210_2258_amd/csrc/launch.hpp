@@ -5,14 +5,16 @@
 namespace sgp {
 
 bool size_supported(int L);
-// columns handled by one column-kernel workgroup for FFT length L
-int col_width(int L);
-int row_threads(int L);
-// row pairs handled by one row-kernel workgroup for row length L
-int row_pairs(int L);
-int col_threads(int L);
-void launch_row(int L, int op, dim3 grid, const Args& a, hipStream_t s);
-void launch_col(int L, int mode, int conj, dim3 grid, const Args& a, hipStream_t s);
+// Tile variant v (0 or 1) of the row / column kernels of FFT length L: the
+// workgroup shape, chosen per length by the autotuner (variant 0 by default).
+// columns handled by one column-kernel workgroup
+int col_width(int L, int v);
+int row_threads(int L, int v);
+// row pairs handled by one row-kernel workgroup
+int row_pairs(int L, int v);
+int col_threads(int L, int v);
+void launch_row(int L, int v, int op, dim3 grid, const Args& a, hipStream_t s);
+void launch_col(int L, int v, int mode, int conj, dim3 grid, const Args& a, hipStream_t s);
 void launch_pix(int op, dim3 grid, const Args& a, hipStream_t s);
 // second reduction stage of the row iteration kernels (one workgroup per item)
 void launch_row_fin(int op, int nz, const Args& a, hipStream_t s);

@@ -11,6 +11,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <map>
 #include <memory>
@@ -281,11 +282,34 @@ static int current_device(int* dev) {
   return 0;
 }
 
+// Tile schedule: the workgroup-shape variant of the row and column kernels
+// of each FFT length, process-wide (every device is the same part).  A solver
+// reads it when it is created and keeps its variants for its lifetime.
+struct TileChoice {
+  int row = 0, col = 0;
+};
+static std::mutex g_tile_mutex;
+static std::map<int, TileChoice> g_tile;
+
+static void tile_schedule(int L, int* row, int* col) {
+  std::lock_guard<std::mutex> lock(g_tile_mutex);
+  auto it = g_tile.find(L);
+  const TileChoice c = it == g_tile.end() ? TileChoice{} : it->second;
+  if (row) *row = c.row;
+  if (col) *col = c.col;
+}
+
+static void set_tile_schedule(int L, int row, int col) {
+  std::lock_guard<std::mutex> lock(g_tile_mutex);
+  g_tile[L] = TileChoice{row, col};
+}
+
 // Launch helper; optionally brackets every launch with HIP events.
 struct Launcher {
   Args base;
   hipStream_t s = nullptr;
   int NY = 0, NX = 0;
+  int vrow = 0, vcol = 0;  // tile variants of the row (length NX) and column (length NY) kernels
   int nz = 1;  // batched items (grid z)
   bool timing = false;
   struct Mark { hipEvent_t a, b; int cls; };
@@ -320,14 +344,14 @@ struct Launcher {
   // next col() / pix() launch must be given the op as fin_op.
   void row(int op, int jc, int iter, int flag = 0, int cls = -1, bool fin = false) {
     Args a = base;
-    const int gx = NY / (2 * row_pairs(NX));
+    const int gx = NY / (2 * row_pairs(NX, vrow));
     a.nblk = gx * jc;
     row_nblk = a.nblk;
     a.iter = iter;
     a.flag = flag;
     hipEvent_t e0 = nullptr;
     begin(cls, e0);
-    launch_row(NX, op, dim3(gx, jc, nz), a, s);
+    launch_row(NX, vrow, op, dim3(gx, jc, nz), a, s);
     end(cls, e0);
     if (fin) {
       begin(cls >= 0 ? SGP_KCLASS_ROW_FIN : -1, e0);
@@ -337,13 +361,13 @@ struct Launcher {
   }
   void col(int mode, int conj, int jc, int iter, int cls = -1, int fin_op = -1) {
     Args a = base;
-    const int C = col_width(NY);
+    const int C = col_width(NY, vcol);
     a.fin_op = fin_op + 1;
     a.fin_nblk = row_nblk;
     a.iter = iter;
     hipEvent_t e0 = nullptr;
     begin(cls, e0);
-    launch_col(NY, mode, conj, dim3((NX / 2 + C - 1) / C, jc, nz), a, s);
+    launch_col(NY, vcol, mode, conj, dim3((NX / 2 + C - 1) / C, jc, nz), a, s);
     end(cls, e0);
   }
   void pix(int op, long long n, int iter, int jsel = 0, int cls = -1, int fin_op = -1) {
@@ -850,6 +874,8 @@ static int create_items(int kind, const std::vector<Problem>& items, const std::
     a.item_part = (long long)part_capacity(k1);
   }
   L.s = S->s; L.NY = pb.NY; L.NX = pb.NX; L.nz = n;
+  tile_schedule(pb.NX, &L.vrow, nullptr);
+  tile_schedule(pb.NY, nullptr, &L.vcol);
   if ((rc = setup(S.get()))) return rc;
   out = std::move(S);
   return 0;
@@ -1030,6 +1056,8 @@ static int apply_operator(const float* psf, const float* x, int ny, int nx, int 
   a.tw_row = pl->tw_row; a.tw_col = pl->tw_col; a.part = pl->part; a.counter = pl->counter; a.st = pl->st;
   a.invw_s = 1.f;
   L.s = s; L.NY = ny; L.NX = nx;
+  tile_schedule(nx, &L.vrow, nullptr);
+  tile_schedule(ny, nullptr, &L.vcol);
   L.pix(PIX_PSFSUM, (long long)ny * nx, 0, 0);
   SGP_HIP(hipMemcpyAsync(pl->host_st, pl->st, sizeof(DevState), hipMemcpyDeviceToHost, s));
   SGP_HIP(hipStreamSynchronize(s));
@@ -1334,6 +1362,159 @@ int sgp_steplength_rule(const sgp_params* prm, int k, double alpha, double tau, 
   out[7] = st.nQ;
   for (int i = 0; i < 8; ++i) out[8 + i] = i < st.nQ ? st.Q[i] : 0.0;
   return 0;
+}
+
+// ------------------------------------------------------------ tile schedule
+int sgp_tile_info(int L, int variant, int* row_threads_out, int* row_pairs_out, int* col_threads_out,
+                  int* col_width_out) {
+  if (!size_supported(L)) return fail(SGP_E_UNSUPPORTED_SIZE, "unsupported FFT length " + std::to_string(L));
+  if (variant != 0 && variant != 1) return fail(SGP_E_INVALID_ARG, "tile variant must be 0 or 1");
+  if (row_threads_out) *row_threads_out = row_threads(L, variant);
+  if (row_pairs_out) *row_pairs_out = row_pairs(L, variant);
+  if (col_threads_out) *col_threads_out = col_threads(L, variant);
+  if (col_width_out) *col_width_out = col_width(L, variant);
+  return SGP_OK;
+}
+
+int sgp_set_tile_schedule(int L, int row_variant, int col_variant) {
+  if (!size_supported(L)) return fail(SGP_E_UNSUPPORTED_SIZE, "unsupported FFT length " + std::to_string(L));
+  if ((row_variant != 0 && row_variant != 1) || (col_variant != 0 && col_variant != 1))
+    return fail(SGP_E_INVALID_ARG, "tile variants must be 0 or 1");
+  set_tile_schedule(L, row_variant, col_variant);
+  return SGP_OK;
+}
+
+int sgp_get_tile_schedule(int L, int* row_variant, int* col_variant) {
+  if (!size_supported(L)) return fail(SGP_E_UNSUPPORTED_SIZE, "unsupported FFT length " + std::to_string(L));
+  tile_schedule(L, row_variant, col_variant);
+  return SGP_OK;
+}
+
+static const char* kTileHeader = "# sgpdeconv tile schedule v1: length row_variant col_variant";
+
+int sgp_save_tile_schedule(const char* path) {
+  if (!path) return fail(SGP_E_INVALID_ARG, "null path");
+  std::map<int, TileChoice> copy;
+  {
+    std::lock_guard<std::mutex> lock(g_tile_mutex);
+    copy = g_tile;
+  }
+  FILE* fp = std::fopen(path, "w");
+  if (!fp) return fail(SGP_E_INVALID_ARG, std::string("cannot write ") + path);
+  std::fprintf(fp, "%s\n", kTileHeader);
+  for (const auto& kv : copy) std::fprintf(fp, "%d %d %d\n", kv.first, kv.second.row, kv.second.col);
+  const bool ok = std::fclose(fp) == 0;
+  return ok ? SGP_OK : fail(SGP_E_INVALID_ARG, std::string("cannot write ") + path);
+}
+
+int sgp_load_tile_schedule(const char* path) {
+  if (!path) return fail(SGP_E_INVALID_ARG, "null path");
+  FILE* fp = std::fopen(path, "r");
+  if (!fp) return fail(SGP_E_INVALID_ARG, std::string("cannot read ") + path);
+  std::map<int, TileChoice> parsed;
+  char line[256];
+  int lineno = 0, rc = SGP_OK;
+  while (std::fgets(line, sizeof line, fp)) {
+    ++lineno;
+    const char* q = line;
+    while (*q == ' ' || *q == '\t') ++q;
+    if (*q == '#' || *q == '\n' || *q == '\r' || *q == 0) continue;
+    int L, r, c;
+    char extra;
+    if (std::sscanf(q, "%d %d %d %c", &L, &r, &c, &extra) != 3 || !size_supported(L) || (r != 0 && r != 1) ||
+        (c != 0 && c != 1)) {
+      rc = fail(SGP_E_INVALID_ARG, std::string(path) + ":" + std::to_string(lineno) +
+                                       ": expected 'length row_variant col_variant' with a supported length "
+                                       "and variants 0 or 1");
+      break;
+    }
+    parsed[L] = TileChoice{r, c};
+  }
+  std::fclose(fp);
+  if (rc) return rc;  // nothing applied
+  for (const auto& kv : parsed) set_tile_schedule(kv.first, kv.second.row, kv.second.col);
+  return SGP_OK;
+}
+
+// Times `iters` SGP iterations of the caller's problem under one tile
+// combination: a warm-up call (graph capture), then `reps` timed calls;
+// returns the median milliseconds per iteration.
+static int time_combo(const sgp_problem* prob, float* f, int iters, int reps, void* stream, double* ms) {
+  sgp_params prm;
+  defaults(&prm);
+  prm.stop = SGP_STOP_FIXED;
+  prm.max_iter = iters * (reps + 1);
+  sgp_solver* S = nullptr;
+  int rc = solver_create(KIND_SGP, prob, &prm, f, stream, &S);
+  if (rc < 0) return rc;
+  std::unique_ptr<sgp_solver, int (*)(sgp_solver*)> guard(S, sgp_solver_destroy);
+  int done = 0;
+  if ((rc = step(S, iters, &done)) < 0) return rc;
+  std::vector<double> t;
+  for (int r = 0; r < reps && !done; ++r) {
+    const auto t0 = std::chrono::steady_clock::now();
+    if ((rc = step(S, iters, &done)) < 0) return rc;
+    const auto t1 = std::chrono::steady_clock::now();
+    t.push_back(std::chrono::duration<double, std::milli>(t1 - t0).count() / iters);
+  }
+  sgp_report rep;
+  if ((rc = report(S, &rep)) < 0) return rc;
+  if (rep.iters != iters * (reps + 1))
+    return fail(SGP_E_INVALID_ARG, "the problem stopped after " + std::to_string(rep.iters) +
+                                       " iterations while being timed (tune on a problem that runs " +
+                                       std::to_string(iters * (reps + 1)) + " SGP iterations)");
+  std::sort(t.begin(), t.end());
+  *ms = t[t.size() / 2];
+  return SGP_OK;
+}
+
+static int autotune(const sgp_problem* prob, float* f, int iters, int* row_variant, int* col_variant, double* ms,
+                    void* hip_stream) {
+  if (!prob || !f) return fail(SGP_E_INVALID_ARG, "null problem or f");
+  if (iters < 1 || iters > 100000) return fail(SGP_E_INVALID_ARG, "iters must be in [1, 100000]");
+  const int LX = prob->boundary ? prob->NX : prob->nx;
+  const int LY = prob->boundary ? prob->NY : prob->ny;
+  if (!size_supported(LX) || !size_supported(LY))
+    return fail(SGP_E_UNSUPPORTED_SIZE, "unsupported FFT size " + std::to_string(LY) + " x " + std::to_string(LX));
+  int prev_row, prev_col;  // restored if a timing run fails
+  tile_schedule(LX, &prev_row, nullptr);
+  tile_schedule(LY, nullptr, &prev_col);
+  const bool row_alt = row_pairs(LX, 1) != row_pairs(LX, 0);
+  const bool col_alt = col_width(LY, 1) != col_width(LY, 0);
+  double t[4] = {-1.0, -1.0, -1.0, -1.0};
+  int best = -1, rc = SGP_OK;
+  for (int combo = 0; combo < 4; ++combo) {
+    const int vr = combo >> 1, vc = combo & 1;
+    if ((vr && !row_alt) || (vc && !col_alt)) continue;  // equal to a combination already timed
+    {
+      std::lock_guard<std::mutex> lock(g_tile_mutex);
+      g_tile[LX].row = vr;
+      g_tile[LY].col = vc;
+    }
+    if ((rc = time_combo(prob, f, iters, 3, hip_stream, &t[combo])) < 0) break;
+    if (best < 0 || t[combo] < t[best]) best = combo;
+  }
+  {
+    std::lock_guard<std::mutex> lock(g_tile_mutex);
+    if (rc < 0) {
+      g_tile[LX].row = prev_row;
+      g_tile[LY].col = prev_col;
+    } else {
+      g_tile[LX].row = best >> 1;
+      g_tile[LY].col = best & 1;
+    }
+  }
+  if (rc < 0) return rc;
+  if (row_variant) *row_variant = best >> 1;
+  if (col_variant) *col_variant = best & 1;
+  if (ms)
+    for (int i = 0; i < 4; ++i) ms[i] = t[i];
+  return SGP_OK;
+}
+
+int sgp_autotune(const sgp_problem* prob, float* f, int iters, int* row_variant, int* col_variant, double* ms,
+                 void* hip_stream) {
+  SGP_GUARD(autotune(prob, f, iters, row_variant, col_variant, ms, hip_stream));
 }
 
 int sgp_release_cache(void) {

@@ -1,0 +1,142 @@
+"""Tile variants of the FFT kernels and the autotuner on the GPU: every
+variant combination against the oracle to the parity bar (single, multi,
+boundary, full size), a batch under a non-default schedule equal to its
+single runs, and the autotuner's choice landing in the table."""
+import numpy as np
+import pytest
+
+from oracle import sgp as O
+from synth import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+SIZES = [16, 32, 64, 128, 256, 512, 1024, 2048, 80, 160, 320, 640, 1280]
+COMBOS = [(0, 1), (1, 0), (1, 1)]
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1210_2258_amd as m
+    m.load()
+    return torch
+
+
+@pytest.fixture(autouse=True)
+def _restore_defaults():
+    yield
+    import paper_1210_2258_amd as m
+    for L in SIZES:
+        m.set_tile_schedule(L, 0, 0)
+
+
+def _dev(torch, a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(np.asarray(a, np.float64) - b) / np.linalg.norm(b))
+
+
+def _solve(torch, w, n):
+    import paper_1210_2258_amd as m
+    if w.domain is not None:
+        return m.sgp_boundary_deconv(_dev(torch, w.g), _dev(torch, w.psf), w.b, w.domain, max_iter=n, trace=True)
+    if w.p > 1:
+        return m.sgp_multi_deconv(_dev(torch, w.g), _dev(torch, w.psf), w.b, max_iter=n, trace=True)
+    return m.sgp_deconv(_dev(torch, w.g[0]), _dev(torch, w.psf[0]), float(w.b[0]), max_iter=n, trace=True)
+
+
+CASES = {
+    "single_c0_256": (W.config0, 20),
+    "single_64x80": (lambda: W.small_single(64, 80), 6),
+    "multi_3x64": (lambda: W.small_multi(64, 64), 4),
+    "boundary_64x48_in_80x64": (lambda: W.small_boundary(80, 64, 64, 48, 8, 8), 4),
+}
+
+
+@pytest.mark.parametrize("combo", COMBOS)
+@pytest.mark.parametrize("case", list(CASES))
+def test_variant_parity(torch_dev, case, combo):
+    import paper_1210_2258_amd as m
+    make, n = CASES[case]
+    w = make()
+    NY, NX = (w.domain[0], w.domain[1]) if w.domain is not None else w.g.shape[-2:]
+    m.set_tile_schedule(NX, combo[0], m.get_tile_schedule(NX)[1])
+    m.set_tile_schedule(NY, m.get_tile_schedule(NY)[0], combo[1])
+    f, rep = _solve(torch_dev, w, n)
+    m.set_tile_schedule(NX, 0, 0)
+    m.set_tile_schedule(NY, 0, 0)
+    f0, rep0 = _solve(torch_dev, w, n)
+    P = O.Problem(w.g, w.psf, w.b, domain=w.domain)
+    fo, io = P.sgp(P.start("flat"), O.Params(max_iter=n))
+    assert rep["iters"] == n
+    for k in range(n):
+        assert int(rep["trace"]["backtracks"][k]) == io["log"][k]["backtracks"], k
+    assert _rel(f.cpu().numpy(), fo) <= 1e-4
+    assert abs(rep["kl"] - io["kl"]) <= 1e-6 * io["kl"]
+    # the variants share the per-pixel arithmetic: only the grouping of the
+    # FP64 partial sums may differ
+    assert _rel(f.cpu().numpy(), f0.cpu().numpy().astype(np.float64)) <= 1e-6
+    assert abs(rep["kl"] - rep0["kl"]) <= 1e-9 * rep0["kl"]
+
+
+def test_variant_parity_full_size(torch_dev):
+    """2048x2048 under 512-thread row workgroups and two-column workgroups."""
+    import paper_1210_2258_amd as m
+    w = W.config1()
+    m.set_tile_schedule(2048, 1, 1)
+    f, rep = _solve(torch_dev, w, 10)
+    P = O.Problem(w.g, w.psf, w.b)
+    fo, io = P.sgp(P.start("flat"), O.Params(max_iter=10))
+    assert _rel(f.cpu().numpy(), fo) <= 1e-4
+    assert abs(rep["kl"] - io["kl"]) <= 1e-6 * io["kl"]
+
+
+def test_batch_under_variants_equals_single_runs(torch_dev):
+    """A batch of uneven sizes under variant 1 everywhere: each item equals
+    its own single run under the same schedule bit for bit."""
+    import paper_1210_2258_amd as m
+    torch = torch_dev
+    for L in (64, 80, 128, 160, 256):
+        m.set_tile_schedule(L, 1, 1)
+    ws = [W.star_field(200, i, ny, nx, 30, 1.0 + 0.4 * i, 5.0 + 5 * i)
+          for i, (ny, nx) in enumerate([(64, 64), (128, 128), (80, 160), (256, 256)])]
+    gs = [_dev(torch, w.g[0]) for w in ws]
+    ps = [_dev(torch, w.psf[0]) for w in ws]
+    bs = [float(w.b[0]) for w in ws]
+    fb, reps = m.batch_deconv(gs, ps, bs, max_iter=12)
+    for i in range(len(ws)):
+        f1, r1 = m.sgp_deconv(gs[i], ps[i], bs[i], max_iter=12)
+        assert torch.equal(fb[i], f1), i
+        assert reps[i]["kl"] == r1["kl"]
+
+
+def test_autotune_sets_the_table(torch_dev):
+    import paper_1210_2258_amd as m
+    torch = torch_dev
+    w = W.config0()
+    g, psf = _dev(torch, w.g[0]), _dev(torch, w.psf[0])
+    r, c, ms = m.autotune(g, psf, float(w.b[0]), iters=10)
+    assert (r, c) in ms and set(ms) == {(0, 0), (0, 1), (1, 0), (1, 1)}
+    assert all(t > 0 for t in ms.values())
+    assert ms[(r, c)] == min(ms.values())
+    assert m.get_tile_schedule(256) == (r, c)
+    # a solve under the tuned schedule is still the oracle's
+    f, rep = m.sgp_deconv(g, psf, float(w.b[0]), max_iter=20)
+    P = O.Problem(w.g, w.psf, w.b)
+    fo, io = P.sgp(P.start("flat"), O.Params(max_iter=20))
+    assert _rel(f.cpu().numpy(), fo) <= 1e-4
+
+
+def test_autotune_rejects_bad_arguments(torch_dev):
+    import paper_1210_2258_amd as m
+    torch = torch_dev
+    w = W.small_single(64, 80)
+    g, psf = _dev(torch, w.g[0]), _dev(torch, w.psf[0])
+    m.set_tile_schedule(80, 1, 0)
+    with pytest.raises(m.SgpError):
+        m.autotune(g, psf, float(w.b[0]), iters=0)
+    assert m.get_tile_schedule(80) == (1, 0)  # unchanged on error
