@@ -65,6 +65,8 @@ def parse():
     ap.add_argument("--no-mosaic", action="store_true", help="skip the mosaic leg")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep tile variant 0 instead of timing the tile variants per FFT length")
+    ap.add_argument("--tiles", type=int, nargs=2, metavar=("ROW", "COL"),
+                    help="tile variants of the main image size, set instead of tuned (as in profiled runs)")
     ap.add_argument("--sweep", action="store_true",
                     help="also run the Fourier re-binning size sweep 256..2048 (RL and SGP, GPU and oracle)")
     return ap.parse_args()
@@ -346,9 +348,13 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
-    tiles = None
-    if not args.no_autotune:
-        tiles = {}
+    tiles = {}
+    if args.tiles:
+        m.set_tile_schedule(nx, args.tiles[0], m.get_tile_schedule(nx)[1])
+        m.set_tile_schedule(ny, m.get_tile_schedule(ny)[0], args.tiles[1])
+        tiles[f"{ny}x{nx}"] = {"rows_variant": args.tiles[0], "cols_variant": args.tiles[1],
+                               "ms_per_iter": None, "set_by": "--tiles"}
+    elif not args.no_autotune:
         tune(m, g, psf, b, 40, tiles)
 
     # ---- throughput: W warm-up iterations, then exactly K timed iterations
@@ -411,8 +417,8 @@ def main():
         **out_ttd,
     }
     if batch_items is not None:
-        out["batch_512"] = batch_legs(torch, m, batch_items, tiles)
-    if tiles is not None:
+        out["batch_512"] = batch_legs(torch, m, batch_items, None if args.no_autotune else tiles)
+    if tiles:
         out["tile_schedule"] = tiles
     if not args.no_multi:
         out["multi_image_3x1024"] = multi_image_legs(torch, m, W.config2())
