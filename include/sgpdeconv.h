@@ -330,8 +330,10 @@ int sgp_load_tile_schedule(const char* path);
  * under every distinct combination of row variant (length NX) and column
  * variant (length NY): one untimed call that captures the graph, then three
  * timed calls of `iters` iterations each, whose median wall time per
- * iteration is the combination's time.  The fastest combination is set in
- * the table and returned in *row_variant / *col_variant (optional).
+ * iteration is the combination's time.  Combinations are timed in the order
+ * (0,0), (0,1), (1,0), (1,1) and one replaces the current choice only when
+ * it is more than 1% faster; the choice is set in the table and returned in
+ * *row_variant / *col_variant (optional).
  * ms (optional, 4 doubles): ms per iteration of (row, column) = (0,0),
  * (0,1), (1,0), (1,1); -1 for a combination equal to one already timed.
  * f: device [NY][NX], caller-owned scratch that is overwritten.  The problem

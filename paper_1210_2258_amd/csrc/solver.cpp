@@ -1492,7 +1492,9 @@ static int autotune(const sgp_problem* prob, float* f, int iters, int* row_varia
       g_tile[LY].col = vc;
     }
     if ((rc = time_combo(prob, f, iters, 3, hip_stream, &t[combo])) < 0) break;
-    if (best < 0 || t[combo] < t[best]) best = combo;
+    // a later combination must be 1% faster to displace the current choice,
+    // so that timing noise between near-equal shapes keeps the lower variants
+    if (best < 0 || t[combo] < 0.99 * t[best]) best = combo;
   }
   {
     std::lock_guard<std::mutex> lock(g_tile_mutex);

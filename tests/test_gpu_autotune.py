@@ -122,7 +122,10 @@ def test_autotune_sets_the_table(torch_dev):
     r, c, ms = m.autotune(g, psf, float(w.b[0]), iters=10)
     assert (r, c) in ms and set(ms) == {(0, 0), (0, 1), (1, 0), (1, 1)}
     assert all(t > 0 for t in ms.values())
-    assert ms[(r, c)] == min(ms.values())
+    # a later combination displaces the current choice only when 1% faster
+    assert ms[(r, c)] <= min(ms.values()) / 0.99
+    if (r, c) != (0, 0):
+        assert ms[(r, c)] < 0.99 * ms[(0, 0)], ms
     assert m.get_tile_schedule(256) == (r, c)
     # a solve under the tuned schedule is still the oracle's
     f, rep = m.sgp_deconv(g, psf, float(w.b[0]), max_iter=20)
