@@ -191,7 +191,7 @@ def multi_image_legs(torch, m, w):
     return out
 
 
-def mosaic_leg(torch, m, w, g, psf, f_full):
+def mosaic_leg(torch, m, w, g, psf, f_full, tiles=None):
     """The 2048^2 galaxy field as a mosaic of four 1024^2 cores seen through
     windows with 128-pixel margins on 1280^2 domains (one batch of boundary
     problems), SGP to the discrepancy stop of every window; compared with the
@@ -199,6 +199,12 @@ def mosaic_leg(torch, m, w, g, psf, f_full):
     N, core, margin = 1280, 1024, 128
     c0 = (psf.shape[0] - N) // 2
     psf_N = psf[c0:c0 + N, c0:c0 + N].contiguous()
+    if tiles is not None:  # tile schedule of the 1280 domain, on a corner window (core + one margin)
+        win = core + margin
+        gw = g[:win, :win].contiguous()
+        r, c, ms = m.autotune(gw, psf_N, float(w.b[0]), domain=(N, N, (N - win) // 2, (N - win) // 2), iters=30)
+        tiles[f"{N}x{N} boundary"] = {"rows_variant": r, "cols_variant": c,
+                                      "ms_per_iter": {f"{k[0]}{k[1]}": v for k, v in ms.items()}}
     m.mosaic_deconv(g, psf_N, float(w.b[0]), core, margin, max_iter=2)  # workspaces
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -423,7 +429,7 @@ def main():
     if not args.no_multi:
         out["multi_image_3x1024"] = multi_image_legs(torch, m, W.config2())
     if not args.no_mosaic and f_full is not None:
-        out["mosaic_2048"] = mosaic_leg(torch, m, w, g, psf, f_full)
+        out["mosaic_2048"] = mosaic_leg(torch, m, w, g, psf, f_full, None if args.no_autotune else tiles)
     if args.sweep:
         out["rebin_sweep"] = rebin_sweep(torch, m, with_oracle=not args.no_cpu)
     if not args.no_cpu:

@@ -339,7 +339,10 @@ int sgp_load_tile_schedule(const char* path);
  * f: device [NY][NX], caller-owned scratch that is overwritten.  The problem
  * must run 4 iters iterations without a stop (fixed-count SGP: only a
  * numerical failure stops it), otherwise SGP_E_INVALID_ARG.  On any error
- * the table is left as it was.  Synchronous on return. */
+ * the table is left as it was.  While it runs, the table holds the
+ * combination being timed: solvers that other threads create meanwhile get
+ * that combination (correct results, possibly not the fastest shape).
+ * Synchronous on return. */
 int sgp_autotune(const sgp_problem* prob, float* f, int iters, int* row_variant, int* col_variant, double* ms,
                  void* hip_stream);
 

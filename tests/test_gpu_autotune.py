@@ -83,14 +83,22 @@ def test_variant_parity(torch_dev, case, combo):
     assert abs(rep["kl"] - rep0["kl"]) <= 1e-9 * rep0["kl"]
 
 
-def test_variant_parity_full_size(torch_dev):
-    """2048x2048 under 512-thread row workgroups and two-column workgroups."""
-    import paper_1210_2258_amd as m
+@pytest.fixture(scope="module")
+def c1_oracle():
     w = W.config1()
-    m.set_tile_schedule(2048, 1, 1)
-    f, rep = _solve(torch_dev, w, 10)
     P = O.Problem(w.g, w.psf, w.b)
-    fo, io = P.sgp(P.start("flat"), O.Params(max_iter=10))
+    return w, P.sgp(P.start("flat"), O.Params(max_iter=10))
+
+
+@pytest.mark.parametrize("combo", COMBOS)
+def test_variant_parity_full_size(torch_dev, c1_oracle, combo):
+    """2048x2048 under 512-thread row workgroups and/or two-column workgroups."""
+    import paper_1210_2258_amd as m
+    w, (fo, io) = c1_oracle
+    m.set_tile_schedule(2048, *combo)
+    f, rep = _solve(torch_dev, w, 10)
+    for k in range(10):
+        assert int(rep["trace"]["backtracks"][k]) == io["log"][k]["backtracks"], k
     assert _rel(f.cpu().numpy(), fo) <= 1e-4
     assert abs(rep["kl"] - io["kl"]) <= 1e-6 * io["kl"]
 
