@@ -63,6 +63,7 @@ def parse():
     ap.add_argument("--batch-images", type=int, default=512)
     ap.add_argument("--no-multi", action="store_true", help="skip the multi-image RL / OSEM / SGP comparison")
     ap.add_argument("--no-mosaic", action="store_true", help="skip the mosaic leg")
+    ap.add_argument("--no-mall", action="store_true", help="skip the 4 x 2048^2 batch beyond the Infinity Cache")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep tile variant 0 instead of timing the tile variants per FFT length")
     ap.add_argument("--tiles", type=int, nargs=2, metavar=("ROW", "COL"),
@@ -215,6 +216,31 @@ def mosaic_leg(torch, m, w, g, psf, f_full, tiles=None):
     return {"tiles": 4, "core": core, "margin": margin, "fft_domain": N, "seconds": secs,
             "iterations_longest_tile": rep["iters"], "max_tile_discrepancy": rep["discrepancy"],
             "rel_l2_vs_full_image": diff}
+
+
+def beyond_mall_leg(torch, m, g, psf, b, n=4, iters=40):
+    """n copies of the 2048^2 problem in one batched run (about 130 MB of
+    fields and spectra per image, so n = 4 exceeds the 256 MB Infinity Cache):
+    per-iteration time from two fixed-count runs (their difference cancels
+    the setup), as pixel throughput and as a fraction of the HBM roofline at
+    80 B/px."""
+    gs, ps, bs = [g] * n, [psf] * n, [b] * n
+    fs = [torch.empty_like(g) for _ in range(n)]
+    m.batch_deconv(gs, ps, bs, fs=fs, max_iter=2)  # workspaces
+    t = []
+    for k in (iters, 2 * iters):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, reps = m.batch_deconv(gs, ps, bs, fs=fs, max_iter=k, stop=m.STOP_FIXED)
+        torch.cuda.synchronize()
+        t.append(time.perf_counter() - t0)
+        assert all(r["iters"] == k for r in reps)
+    per_iter = (t[1] - t[0]) / iters
+    npx = n * g.numel()
+    gbs = ITER_BYTES_PER_PX * npx / per_iter / 1e9
+    return {"images": n, "image": list(g.shape), "ms_per_iteration": 1e3 * per_iter,
+            "ms_per_image_iteration": 1e3 * per_iter / n, "pixel_iterations_per_s": npx / per_iter,
+            "iteration_GBs_at_80_B_per_px": gbs, "frac": gbs / HBM_PEAK_GBS}
 
 
 def rebin_sweep(torch, m, with_oracle):
@@ -430,6 +456,8 @@ def main():
         out["multi_image_3x1024"] = multi_image_legs(torch, m, W.config2())
     if not args.no_mosaic and f_full is not None:
         out["mosaic_2048"] = mosaic_leg(torch, m, w, g, psf, f_full, None if args.no_autotune else tiles)
+    if not args.no_mall and args.size == 2048:
+        out["beyond_mall_4x2048"] = beyond_mall_leg(torch, m, g, psf, b)
     if args.sweep:
         out["rebin_sweep"] = rebin_sweep(torch, m, with_oracle=not args.no_cpu)
     if not args.no_cpu:
