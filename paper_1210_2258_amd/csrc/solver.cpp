@@ -115,7 +115,10 @@ static int shared_stream(int dev, SharedStream** out) {
 }
 
 // workgroups of the Armijo kernel (its rare candidate pass)
-constexpr int kArmBlocks = 512;
+#ifndef SGP_ARM_BLOCKS
+#define SGP_ARM_BLOCKS 512
+#endif
+constexpr int kArmBlocks = SGP_ARM_BLOCKS;
 
 static size_t part_capacity(const PlanKey& k) {
   // row kernels: at most NY / 2 workgroups per image and 4 slots; the Armijo
