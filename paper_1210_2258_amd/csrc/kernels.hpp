@@ -740,59 +740,75 @@ __global__ __launch_bounds__((ColCfg<LY, V>::NT)) void col_kernel(Args a_in) {
       }
       __syncthreads();
     }
-  } else if constexpr ((MODE == COL_CORR1 || MODE == COL_CONV1) && C == 1 && E <= 8) {
-    // one column per workgroup: thread tid holds rows tid + TF e in
+  } else if constexpr ((MODE == COL_CORR1 || MODE == COL_CONV1) && C <= 2 && E <= 8) {
+    // one or two columns per workgroup: thread tid works on column
+    // kx0 + tid / TF and holds its rows lane + TF e (lane = tid % TF) in
     // registers from the load to the store, the points its first and last
-    // FFT passes touch; only the workgroup of column 0 stages the forward
-    // transform in LDS, for the mirrored points of its even / odd split
+    // FFT passes touch; only column 0 stages its forward transform in LDS,
+    // for the mirrored points of its even / odd split
     if (kx0 >= NXh) return;  // uniform over the workgroup
+    const int c = tid / TF, lane = tid % TF;
+    const bool live = kx0 + c < NXh;  // uniform over the column's threads; all take the barriers
+    auto runit = [&](int e, int& y, long long& off) {
+      y = lane + TF * e;
+      off = ((long long)(y >> 3) * NXh + kx0 + c) * 8 + (y & 7);
+    };
     const int jo = MODE == COL_CONV1 ? a.j0 : 0;
     const float2* K = a.khat + jo * sstride;
     const float2* KN = a.knyq + (long long)jo * LY;
     float2 xr[E], kpre[E];
 #pragma unroll
     for (int e = 0; e < E; ++e) {
-      int c, y; long long off;
-      unit(e, c, y, off);
-      xr[e] = a.spec[off];
+      int y; long long off;
+      runit(e, y, off);
+      xr[e] = live ? a.spec[off] : make_float2(0.f, 0.f);
     }
 #pragma unroll
     for (int e = 0; e < E; ++e) {
-      int c, y; long long off;
-      unit(e, c, y, off);
-      kpre[e] = K[off];
+      int y; long long off;
+      runit(e, y, off);
+      kpre[e] = live ? K[off] : make_float2(0.f, 0.f);
     }
-    fft_lds_x<LY, true, true>(buf[0], tid, tw, xr);
-    if (has_col0) {
+    fft_lds_x<LY, true, true>(buf[c], lane, tw, xr);
+    if (has_col0) {  // uniform over the workgroup
+      if (c == 0) {
 #pragma unroll
-      for (int e = 0; e < E; ++e) {
-        int c, y; long long off;
-        unit(e, c, y, off);
-        buf[0][lds_idx<LY>(y)] = xr[e];
+        for (int e = 0; e < E; ++e) {
+          int y; long long off;
+          runit(e, y, off);
+          buf[0][lds_idx<LY>(y)] = xr[e];
+        }
       }
       __syncthreads();
+      if (c == 0) {
 #pragma unroll
-      for (int e = 0; e < E; ++e) {
-        int c, y; long long off;
-        unit(e, c, y, off);
-        const float2 v = xr[e];
-        const float2 m = cconj(buf[0][lds_idx<LY>((LY - y) % LY)]);
-        const float2 ev = cscale(cadd(v, m), 0.5f);
-        const float2 od = cscale(mul_mi(csub(v, m)), 0.5f);
-        const float2 kn = KN[y];
-        xr[e] = cconj(cadd(CONJ ? cmulc(ev, kpre[e]) : cmul(ev, kpre[e]), mul_pi(CONJ ? cmulc(od, kn) : cmul(od, kn))));
+        for (int e = 0; e < E; ++e) {
+          int y; long long off;
+          runit(e, y, off);
+          const float2 v = xr[e];
+          const float2 m = cconj(buf[0][lds_idx<LY>((LY - y) % LY)]);
+          const float2 ev = cscale(cadd(v, m), 0.5f);
+          const float2 od = cscale(mul_mi(csub(v, m)), 0.5f);
+          const float2 kn = KN[y];
+          xr[e] = cconj(cadd(CONJ ? cmulc(ev, kpre[e]) : cmul(ev, kpre[e]), mul_pi(CONJ ? cmulc(od, kn) : cmul(od, kn))));
+        }
+      } else {
+#pragma unroll
+        for (int e = 0; e < E; ++e) xr[e] = cconj(CONJ ? cmulc(xr[e], kpre[e]) : cmul(xr[e], kpre[e]));
       }
       __syncthreads();  // mirrored reads done before the next transform writes buf
     } else {
 #pragma unroll
       for (int e = 0; e < E; ++e) xr[e] = cconj(CONJ ? cmulc(xr[e], kpre[e]) : cmul(xr[e], kpre[e]));
     }
-    fft_lds_x<LY, true, true>(buf[0], tid, tw, xr);
+    fft_lds_x<LY, true, true>(buf[c], lane, tw, xr);
+    if (live) {
 #pragma unroll
-    for (int e = 0; e < E; ++e) {
-      int c, y; long long off;
-      unit(e, c, y, off);
-      a.spec[jo * sstride + off] = cconj(xr[e]);
+      for (int e = 0; e < E; ++e) {
+        int y; long long off;
+        runit(e, y, off);
+        a.spec[jo * sstride + off] = cconj(xr[e]);
+      }
     }
   } else if constexpr (MODE == COL_CORR1 || MODE == COL_CONV1) {
     // one image jo: spec[0] -> spec[jo] = K_jo x (or conj K_jo x); the

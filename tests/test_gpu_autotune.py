@@ -103,6 +103,40 @@ def test_variant_parity_full_size(torch_dev, c1_oracle, combo):
     assert abs(rep["kl"] - io["kl"]) <= 1e-6 * io["kl"]
 
 
+@pytest.mark.parametrize("shape", [(2048, 2048), (2048, 160), (1024, 80)])
+@pytest.mark.parametrize("combo", COMBOS)
+def test_operator_under_variants(torch_dev, shape, combo):
+    """A and A^T under every tile combination (two-column register path at
+    2048, four columns at 1024) against the oracle's FFT convolution."""
+    import paper_1210_2258_amd as m
+    torch = torch_dev
+    ny, nx = shape
+    rng = np.random.default_rng(ny + nx)
+    psf = rng.random((ny, nx)) * W.gaussian_psf(ny, nx, 3.0)
+    psf[ny // 2 + 1, nx // 2 - 2] += 0.3 * psf.max()   # asymmetric
+    x = (rng.random((ny, nx)) * 100).astype(np.float32).astype(np.float64)
+    P = O.Problem(np.ones((ny, nx)), psf.astype(np.float32), 1.0)
+    m.set_tile_schedule(nx, combo[0], m.get_tile_schedule(nx)[1])
+    m.set_tile_schedule(ny, m.get_tile_schedule(ny)[0], combo[1])
+    for adj in (False, True):
+        out = m.apply_operator(_dev(torch, psf), _dev(torch, x), adjoint=adj).cpu().numpy()
+        ref = P.AT(0, x) if adj else P.A(0, x)
+        assert _rel(out, ref) < 2e-6, (shape, combo, adj, _rel(out, ref))
+
+
+def test_single_1024_parity(torch_dev):
+    """A 1024x1024 star field (two columns per workgroup on the register
+    path by default), 10 SGP iterations against the oracle."""
+    w = W.star_field(300, 1024, 1024, 1024, 100, 2.0, 10.0)
+    f, rep = _solve(torch_dev, w, 10)
+    P = O.Problem(w.g, w.psf, w.b)
+    fo, io = P.sgp(P.start("flat"), O.Params(max_iter=10))
+    for k in range(10):
+        assert int(rep["trace"]["backtracks"][k]) == io["log"][k]["backtracks"], k
+    assert _rel(f.cpu().numpy(), fo) <= 1e-4
+    assert abs(rep["kl"] - io["kl"]) <= 1e-6 * io["kl"]
+
+
 def test_batch_under_variants_equals_single_runs(torch_dev):
     """A batch of uneven sizes under variant 1 everywhere: each item equals
     its own single run under the same schedule bit for bit."""
