@@ -111,7 +111,7 @@ def batch_legs(torch, m, items, tiles=None):
         seen.setdefault(tuple(g.shape), i)
     if tiles is not None:  # tile schedule of every size in the batch, before any timed leg
         for i in seen.values():
-            tune(m, gs[i], ps[i], bs[i], 50, tiles)
+            tune(m, gs[i], ps[i], bs[i], 128, tiles)
     # warm-up: workspaces of every shape and group size, network buffers
     for i in seen.values():
         m.sgp_deconv(gs[i], ps[i], bs[i], max_iter=2)
@@ -203,7 +203,7 @@ def mosaic_leg(torch, m, w, g, psf, f_full, tiles=None):
     if tiles is not None:  # tile schedule of the 1280 domain, on a corner window (core + one margin)
         win = core + margin
         gw = g[:win, :win].contiguous()
-        r, c, ms = m.autotune(gw, psf_N, float(w.b[0]), domain=(N, N, (N - win) // 2, (N - win) // 2), iters=30)
+        r, c, ms = m.autotune(gw, psf_N, float(w.b[0]), domain=(N, N, (N - win) // 2, (N - win) // 2), iters=64)
         tiles[f"{N}x{N} boundary"] = {"rows_variant": r, "cols_variant": c,
                                       "ms_per_iter": {f"{k[0]}{k[1]}": v for k, v in ms.items()}}
     m.mosaic_deconv(g, psf_N, float(w.b[0]), core, margin, max_iter=2)  # workspaces
@@ -387,7 +387,7 @@ def main():
         tiles[f"{ny}x{nx}"] = {"rows_variant": args.tiles[0], "cols_variant": args.tiles[1],
                                "ms_per_iter": None, "set_by": "--tiles"}
     elif not args.no_autotune:
-        tune(m, g, psf, b, 40, tiles)
+        tune(m, g, psf, b, 96, tiles)
 
     # ---- throughput: W warm-up iterations, then exactly K timed iterations
     total = args.warmup + args.steps

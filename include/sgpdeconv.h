@@ -329,11 +329,11 @@ int sgp_load_tile_schedule(const char* path);
  * multi-image or boundary, as for sgp_solver_create; 1 <= iters <= 100000)
  * under every distinct combination of row variant (length NX) and column
  * variant (length NY): one untimed call that captures the graph, then three
- * timed calls of `iters` iterations each, whose median wall time per
- * iteration is the combination's time.  Combinations are timed in the order
- * (0,0), (0,1), (1,0), (1,1) and one replaces the current choice only when
- * it is more than 1% faster; the choice is set in the table and returned in
- * *row_variant / *col_variant (optional).
+ * timed calls of `iters` iterations each, whose least wall time per
+ * iteration is the combination's time (a multiple of 32 iterations, the
+ * graph block, times whole graph replays).  The fastest combination is
+ * chosen unless it is within 1% of (0,0), which then stays; the choice is
+ * set in the table and returned in *row_variant / *col_variant (optional).
  * ms (optional, 4 doubles): ms per iteration of (row, column) = (0,0),
  * (0,1), (1,0), (1,1); -1 for a combination equal to one already timed.
  * f: device [NY][NX], caller-owned scratch that is overwritten.  The problem

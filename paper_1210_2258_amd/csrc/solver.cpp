@@ -1441,7 +1441,7 @@ int sgp_load_tile_schedule(const char* path) {
 
 // Times `iters` SGP iterations of the caller's problem under one tile
 // combination: a warm-up call (graph capture), then `reps` timed calls;
-// returns the median milliseconds per iteration.
+// returns the least milliseconds per iteration (the run least disturbed).
 static int time_combo(const sgp_problem* prob, float* f, int iters, int reps, void* stream, double* ms) {
   sgp_params prm;
   defaults(&prm);
@@ -1466,8 +1466,7 @@ static int time_combo(const sgp_problem* prob, float* f, int iters, int reps, vo
     return fail(SGP_E_INVALID_ARG, "the problem stopped after " + std::to_string(rep.iters) +
                                        " iterations while being timed (tune on a problem that runs " +
                                        std::to_string(iters * (reps + 1)) + " SGP iterations)");
-  std::sort(t.begin(), t.end());
-  *ms = t[t.size() / 2];
+  *ms = *std::min_element(t.begin(), t.end());
   return SGP_OK;
 }
 
@@ -1495,10 +1494,11 @@ static int autotune(const sgp_problem* prob, float* f, int iters, int* row_varia
       g_tile[LY].col = vc;
     }
     if ((rc = time_combo(prob, f, iters, 3, hip_stream, &t[combo])) < 0) break;
-    // a later combination must be 1% faster to displace the current choice,
-    // so that timing noise between near-equal shapes keeps the lower variants
-    if (best < 0 || t[combo] < 0.99 * t[best]) best = combo;
+    if (best < 0 || t[combo] < t[best]) best = combo;
   }
+  // the default shape stays unless the fastest is more than 1% faster, so
+  // that timing noise between near-equal shapes keeps variant 0
+  if (rc >= 0 && t[best] > 0.99 * t[0]) best = 0;
   {
     std::lock_guard<std::mutex> lock(g_tile_mutex);
     if (rc < 0) {

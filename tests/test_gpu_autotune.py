@@ -161,13 +161,14 @@ def test_autotune_sets_the_table(torch_dev):
     torch = torch_dev
     w = W.config0()
     g, psf = _dev(torch, w.g[0]), _dev(torch, w.psf[0])
-    r, c, ms = m.autotune(g, psf, float(w.b[0]), iters=10)
+    r, c, ms = m.autotune(g, psf, float(w.b[0]), iters=32)
     assert (r, c) in ms and set(ms) == {(0, 0), (0, 1), (1, 0), (1, 1)}
     assert all(t > 0 for t in ms.values())
-    # a later combination displaces the current choice only when 1% faster
-    assert ms[(r, c)] <= min(ms.values()) / 0.99
-    if (r, c) != (0, 0):
-        assert ms[(r, c)] < 0.99 * ms[(0, 0)], ms
+    # the fastest, unless within 1% of the default shape
+    if (r, c) == (0, 0):
+        assert min(ms.values()) >= 0.99 * ms[(0, 0)], ms
+    else:
+        assert ms[(r, c)] == min(ms.values()) and ms[(r, c)] < 0.99 * ms[(0, 0)], ms
     assert m.get_tile_schedule(256) == (r, c)
     # a solve under the tuned schedule is still the oracle's
     f, rep = m.sgp_deconv(g, psf, float(w.b[0]), max_iter=20)
