@@ -86,3 +86,25 @@ def test_malformed_file_applies_nothing(tmp_path, bad):
 def test_missing_file():
     with pytest.raises(m.SgpError):
         m.load_tile_schedule(os.path.join("/nonexistent", "tiles.txt"))
+
+
+def test_autotune_argument_checks_before_any_device_work():
+    """The autotuner rejects a null problem, an iteration count out of range
+    and an unsupported FFT size before touching a device, and leaves the
+    table as it was."""
+    import ctypes
+
+    from paper_1210_2258_amd import _lib as L
+    lib = m.load()
+    m.set_tile_schedule(256, 1, 0)
+    dummy = ctypes.c_void_p(1)  # never dereferenced: every call below fails its checks first
+
+    def run(ny, nx, iters, prob=True):
+        pr = L._Problem(dummy.value, dummy.value, None, dummy.value, 1, ny, nx, ny, nx, 0, 0, 0)
+        return lib.sgp_autotune(ctypes.byref(pr) if prob else None, dummy if prob else None, iters,
+                                None, None, None, None)
+
+    assert run(256, 256, 10, prob=False) == -1
+    assert run(256, 256, 0) == -1 and run(256, 256, 100001) == -1
+    assert run(96, 256, 10) == -2
+    assert m.get_tile_schedule(256) == (1, 0)
