@@ -1,4 +1,4 @@
-"""The round-end smoke entry point runs and passes on the GPU."""
+"""The smoke entry point (one small SGP solve checked against the oracle) runs and passes on the GPU."""
 import pytest
 
 pytestmark = pytest.mark.gpu
