@@ -48,6 +48,26 @@ BYTES_PER_PX = {"row_dir": 12, "col_conv": 12, "row_ad": 24, "row_upd": 20, "col
 ITER_BYTES_PER_PX = sum(v for k, v in BYTES_PER_PX.items() if k != "row_upd")  # 80
 
 
+def iter_bytes(p, NY, NX, ny, nx, boundary):
+    """Algorithmic bytes of one SGP iteration in the usual case (lambda = 1
+    accepted) for p images observed on ny x nx inside the NY x NX FFT domain:
+    per FFT-domain pixel the direction pass reads f, grad (+ the weights
+    M_R / alpha of a boundary problem) and writes one spectrum; the forward
+    column pass reads that spectrum once and K_j, writes p spectra; the A d
+    pass reads spectrum j, and on S A_j f and g_j, writes on S A_j d and the
+    new A_j f, and spectrum j; the adjoint column pass reads p spectra and K_j,
+    writes one; the gradient pass reads the spectrum, grad, f (+ weights),
+    writes grad and f."""
+    F, Sx = NY * NX, ny * nx
+    w = 4 if boundary else 0
+    row_dir = (8 + w + 4) * F
+    col_conv = (4 + 8 * p) * F
+    row_ad = p * (8 * F + 16 * Sx)
+    col_corr = (4 + 8 * p) * F
+    row_grad = (16 + w + 4) * F
+    return row_dir + col_conv + row_ad + col_corr + row_grad
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -63,6 +83,8 @@ def parse():
     ap.add_argument("--batch-images", type=int, default=512)
     ap.add_argument("--no-multi", action="store_true", help="skip the multi-image RL / OSEM / SGP comparison")
     ap.add_argument("--no-mosaic", action="store_true", help="skip the mosaic leg")
+    ap.add_argument("--no-configs", action="store_true",
+                    help="skip the per-iteration rates of the multi-image and boundary workloads")
     ap.add_argument("--no-mall", action="store_true", help="skip the 4 x 2048^2 batch beyond the Infinity Cache")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep tile variant 0 instead of timing the tile variants per FFT length")
@@ -323,24 +345,84 @@ def counter_traffic(kernel, npx):
     return None if k is None else k["traffic_bytes"]
 
 
-def cpu_baseline(w, iters):
-    """The FP64 oracle on the host: s/iteration from SGP runs with 0 and
-    `iters` iterations (setup cancels)."""
-    import numpy as np
+def oracle_rate(w, iters, workers=None):
+    """The FP64 oracle on the host: (setup seconds, seconds per SGP iteration)
+    from runs with 0 and `iters` iterations (setup cancels).  workers: None
+    runs numpy.fft (one thread), n runs the same transforms through scipy.fft
+    with n threads (the elementwise work stays on one thread)."""
     from oracle import sgp as O
-    P = O.Problem(w.g, w.psf, w.b)
-    f0 = P.start("flat")
-    t0 = time.perf_counter()
-    P.sgp(f0, O.Params(max_iter=0))
-    t1 = time.perf_counter()
-    P.sgp(f0, O.Params(max_iter=iters))
-    t2 = time.perf_counter()
-    per_iter = max((t2 - t1) - (t1 - t0), 1e-9) / iters
-    cores = 1  # numpy.fft (pocketfft) runs single-threaded
-    return {"value": 1.0 / per_iter, "unit": "iter/s", "cores": cores, "kind": "oracle",
-            "sample": f"{iters} SGP iterations of the {w.g.shape[-2]}x{w.g.shape[-1]} workload "
-                      f"(oracle setup time subtracted; {t2 - t0:.1f} s of CPU work); host has "
-                      f"{os.cpu_count()} logical CPUs"}
+    O.FFT_WORKERS = workers
+    try:
+        P = O.Problem(w.g, w.psf, w.b, domain=w.domain)
+        f0 = P.start("flat")
+        t0 = time.perf_counter()
+        P.sgp(f0, O.Params(max_iter=0))
+        t1 = time.perf_counter()
+        P.sgp(f0, O.Params(max_iter=iters))
+        t2 = time.perf_counter()
+    finally:
+        O.FFT_WORKERS = None
+    return t1 - t0, max((t2 - t1) - (t1 - t0), 1e-9) / iters
+
+
+def cpu_baseline(w, iters, gpu_iters_to_disc=None):
+    """The FP64 oracle on the host cores, on the 2048^2 workload: SGP
+    iterations per second on one core (numpy.fft) and with the transforms on
+    every core (scipy.fft workers = os.cpu_count())."""
+    cores = os.cpu_count() or 1
+    t_0 = time.perf_counter()
+    setup1, per1 = oracle_rate(w, iters)
+    setupn, pern = oracle_rate(w, iters, workers=cores)
+    spent = time.perf_counter() - t_0
+    out = {"value": 1.0 / per1, "unit": "iter/s", "cores": 1, "kind": "oracle",
+           "sample": f"{iters} SGP iterations of the {w.g.shape[-2]}x{w.g.shape[-1]} workload, "
+                     f"oracle setup time subtracted ({spent:.1f} s of CPU work for both legs); "
+                     f"host has {cores} logical CPUs",
+           "all_cores": {"value": 1.0 / pern, "unit": "iter/s", "cores": cores,
+                         "fft": f"scipy.fft, workers={cores}"}}
+    if gpu_iters_to_disc:
+        out["time_to_discrepancy_s_estimated"] = {
+            "one_core": setup1 + per1 * gpu_iters_to_disc, "all_cores": setupn + pern * gpu_iters_to_disc,
+            "iterations": gpu_iters_to_disc,
+            "how": "oracle setup + s/iteration x the iteration count the GPU run needed"}
+    return out
+
+
+def config_rates(torch, m, steps, warmup, with_oracle):
+    """SGP iterations per second on the multi-image (3 x 1024^2) and the
+    boundary-corrected (1024^2 window in a 1280^2 domain) workloads, each
+    with its bytes model and fraction of the HBM roofline; with the oracle,
+    its seconds per iteration on the same input (2 timed iterations, one core)."""
+    from synth import workloads as W
+    out = {}
+    for name, w in (("multi_3x1024", W.config2()), ("boundary_1280", W.config3())):
+        g = torch.from_numpy(w.g).cuda()
+        psf = torch.from_numpy(w.psf).cuda()
+        p, ny, nx = w.g.shape
+        if w.domain is not None:
+            NY, NX = w.domain[0], w.domain[1]
+        else:
+            NY, NX = ny, nx
+        S = m.Solver(m.KIND_SGP, g, psf, w.b, domain=w.domain, max_iter=steps + warmup + 10)
+        S.prepare(steps)
+        S.step(warmup)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        S.step(steps)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / steps
+        rep = S.report()
+        S.close()
+        assert rep["iters"] == steps + warmup, rep["iters"]
+        nb = iter_bytes(p, NY, NX, ny, nx, w.domain is not None)
+        row = {"images": p, "window": [ny, nx], "fft_domain": [NY, NX], "iter_per_s": 1.0 / dt,
+               "ms_per_iteration": 1e3 * dt, "bytes_per_iteration": nb,
+               "achieved_GBs": nb / dt / 1e9, "frac": nb / dt / 1e9 / HBM_PEAK_GBS}
+        if with_oracle:
+            _, per = oracle_rate(w, 2)
+            row["oracle_s_per_iteration_one_core"] = per
+        out[name] = row
+    return out
 
 
 def main():
@@ -390,8 +472,10 @@ def main():
         tune(m, g, psf, b, 96, tiles)
 
     # ---- throughput: W warm-up iterations, then exactly K timed iterations
+    # (the graphs the timed call replays are captured before it)
     total = args.warmup + args.steps
     S = m.Solver(m.KIND_SGP, g, psf, b, max_iter=total + 10)
+    S.prepare(args.steps)
     S.step(args.warmup)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -460,8 +544,10 @@ def main():
         out["beyond_mall_4x2048"] = beyond_mall_leg(torch, m, g, psf, b)
     if args.sweep:
         out["rebin_sweep"] = rebin_sweep(torch, m, with_oracle=not args.no_cpu)
+    if not args.no_configs:
+        out["configs"] = config_rates(torch, m, 100, 10, not args.no_cpu)
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(w, args.cpu_iters)
+        out["cpu_baseline"] = cpu_baseline(w, args.cpu_iters, out_ttd.get("iters_to_discrepancy"))
     print(json.dumps(out))
 
 

@@ -49,6 +49,10 @@ extern "C" {
 #define SGP_W_MAXITER 1            /* max_iter reached before the requested stop rule */
 #define SGP_W_ARMIJO_EXHAUSTED 2   /* backtracking cap hit (Algorithm 1, step 5) */
 #define SGP_W_STATIONARY 3         /* grad^T d = 0: f is stationary */
+#define SGP_W_FLUX_UNCONVERGED 4   /* flux constraint: in some iteration the Newton passes for the
+                                      projection multiplier ended before its root, so that direction
+                                      was projected with sum above the prescribed flux (count in
+                                      sgp_report.flux_unconverged) */
 #define SGP_E_INVALID_ARG -1
 #define SGP_E_UNSUPPORTED_SIZE -2
 #define SGP_E_BAD_PSF -3
@@ -125,6 +129,9 @@ typedef struct sgp_report {
   double flux;           /* sum of f */
   double L1, L2;         /* scaling bounds used */
   double seconds;        /* wall time of the call */
+  int flux_unconverged;  /* flux constraint: iterations whose multiplier had not converged after
+                            the Newton passes (then the return code is at least
+                            SGP_W_FLUX_UNCONVERGED) */
 } sgp_report;
 
 /* Fills *p with the defaults above.  Returns SGP_E_INVALID_ARG on NULL. */
@@ -230,6 +237,11 @@ int sgp_solver_create(int kind, const sgp_problem* prob, const sgp_params* prm, 
 /* Runs up to n more iterations; *done (optional) becomes 1 once a stop rule
  * or max_iter has ended the run.  Synchronous on return. */
 int sgp_solver_step(sgp_solver* s, int n, int* done);
+/* Captures (without running any iteration) the HIP graphs that a later
+ * sgp_solver_step(s, n, ...) replays: a latency-sensitive caller moves the
+ * capture out of that call.  step() captures them itself when absent; a
+ * solver keeps every graph it has captured until it is destroyed. */
+int sgp_solver_prepare(sgp_solver* s, int n);
 int sgp_solver_report(sgp_solver* s, sgp_report* rep);
 /* Kernel timing of later step() calls (HIP events around every launch on the
  * solver's stream; graphs are not used while enabled).  ms[i] receives the
@@ -290,6 +302,21 @@ int sgp_mosaic_deconv(int kind, const float* g, int H, int W, const float* psf, 
  * BB1 branch, BB2 branch, nQ, then the updated Q. */
 int sgp_steplength_rule(const sgp_params* prm, int k, double alpha, double tau, const double* Q,
                         int nQ, double a, double c1, double c2, double e, double* out);
+
+/* The multiplier of the flux-constrained projection (the constraint set
+ * {x >= 0, sum x = c} of Sect. 2, projected in the D^-1 metric:
+ * x_i = max(0, z_i - mu D_i) with sum x = c) found exactly as the device finds
+ * it, callable on the host for validation: the all-active step, then up to
+ * max_steps Newton steps on phi(mu) = sum_i max(0, z_i - mu D_i) - c, each
+ * with the device's FP64 sums and finalisers.  z, D: HOST arrays of n
+ * doubles (D >= 0; pixels with D = 0 are held at max(0, z)).  *mu receives
+ * the multiplier, *steps (optional) the Newton steps taken, *converged
+ * (optional) 1 if the active set stopped changing (mu is then the root).
+ * Returns SGP_W_FLUX_UNCONVERGED when the last allowed step ended before the
+ * root (the solver allows 8 per iteration), SGP_E_NUMERIC on a non-finite
+ * multiplier, SGP_E_INVALID_ARG on bad arguments. */
+int sgp_flux_multiplier(const double* z, const double* D, long long n, double c, int max_steps, double* mu,
+                        int* steps, int* converged);
 
 /* ---------------------------------------------------------------------------
  * FFT tile schedule and its autotuner.  The FFTs are the main cost of an

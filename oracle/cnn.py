@@ -4,8 +4,8 @@ TEST INFRASTRUCTURE ONLY: imported by tests/ and bench.py's cpu leg; shares
 no code with the HIP kernels.
 
 The network maps an observed image g (background b) to a start image f0 for
-SGP (the "any input image provided by the user" start of Sect. 3.1 of the
-paper; the network itself is not part of the paper):
+SGP (Sect. 3.1 of the paper admits any caller-supplied positive start; the
+network itself is not part of the paper):
 
     s  = max(mean(g - b), 1e-3)                  per-image scale
     x  = (g - b) / s

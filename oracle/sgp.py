@@ -73,6 +73,26 @@ REASON_STATIONARY = 4
 REASON_ARMIJO = 5
 
 
+# Threads of the 2D transforms.  None: numpy.fft (one thread, what every pin
+# runs); an integer n: scipy.fft with n workers, the same discrete Fourier
+# transform, used only to time the oracle on several host cores.
+FFT_WORKERS = None
+
+
+def _fft2(x):
+    if FFT_WORKERS:
+        import scipy.fft
+        return scipy.fft.fft2(x, workers=FFT_WORKERS)
+    return np.fft.fft2(x)
+
+
+def _ifft2(x):
+    if FFT_WORKERS:
+        import scipy.fft
+        return scipy.fft.ifft2(x, workers=FFT_WORKERS)
+    return np.fft.ifft2(x)
+
+
 @dataclass
 class Params:
     """Sect. 3.2 defaults (beta, theta, alpha0, tau1, alpha_max, M_alpha,
@@ -156,10 +176,10 @@ class Problem:
 
     # ---------------------------------------------------------------- operators
     def _conv(self, j, x):
-        return np.real(np.fft.ifft2(self.Khat[j] * np.fft.fft2(x)))
+        return np.real(_ifft2(self.Khat[j] * _fft2(x)))
 
     def _corr(self, j, x):
-        return np.real(np.fft.ifft2(np.conj(self.Khat[j]) * np.fft.fft2(x)))
+        return np.real(_ifft2(np.conj(self.Khat[j]) * _fft2(x)))
 
     def embed(self, x_S):
         """Zero-pad an array on S into Sbar (the M_S o . of Eq. backprojection)."""

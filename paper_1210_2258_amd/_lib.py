@@ -49,7 +49,7 @@ class _Report(ctypes.Structure):
         ("iters", ctypes.c_int), ("stop_reason", ctypes.c_int), ("backtracks", ctypes.c_int),
         ("used_fallback", ctypes.c_int), ("kl", ctypes.c_double), ("discrepancy", ctypes.c_double),
         ("flux", ctypes.c_double), ("L1", ctypes.c_double), ("L2", ctypes.c_double),
-        ("seconds", ctypes.c_double),
+        ("seconds", ctypes.c_double), ("flux_unconverged", ctypes.c_int),
     ]
 
 
@@ -69,13 +69,14 @@ KCLASSES = ["row_dir", "col_conv", "row_ad", "armijo_more", "row_upd", "col_corr
 EXPORTS = [
     "sgp_params_init", "rl_deconv", "sgp_deconv", "sgp_multi_deconv", "rl_multi_deconv",
     "sgp_boundary_deconv", "rl_boundary_deconv", "sgp_apply_operator", "sgp_release_cache",
-    "sgp_strerror", "sgp_last_error", "sgp_solver_create", "sgp_solver_step", "sgp_solver_report",
+    "sgp_strerror", "sgp_last_error", "sgp_solver_create", "sgp_solver_step", "sgp_solver_prepare",
+    "sgp_solver_report",
     "sgp_solver_set_timing", "sgp_solver_set_graph", "sgp_solver_timing", "sgp_solver_destroy",
     "sgp_steplength_rule", "sgp_batch_deconv", "osem_deconv", "osem_boundary_deconv", "sgp_mosaic_deconv",
     "sgp_cnn_num_params", "sgp_cnn_create", "sgp_cnn_get_params", "sgp_cnn_infer", "sgp_cnn_loss_grad",
     "sgp_cnn_adam_step", "sgp_cnn_train_step", "sgp_cnn_destroy",
     "sgp_tile_info", "sgp_set_tile_schedule", "sgp_get_tile_schedule", "sgp_save_tile_schedule",
-    "sgp_load_tile_schedule", "sgp_autotune",
+    "sgp_load_tile_schedule", "sgp_autotune", "sgp_flux_multiplier",
 ]
 
 _lib = None
@@ -101,6 +102,7 @@ def load():
     lib.sgp_apply_operator.argtypes = [vp, vp, i, i, i, vp, vp]
     lib.sgp_solver_create.argtypes = [i, ctypes.POINTER(_Problem), P, vp, vp, ctypes.POINTER(vp)]
     lib.sgp_solver_step.argtypes = [vp, i, ctypes.POINTER(i)]
+    lib.sgp_solver_prepare.argtypes = [vp, i]
     lib.sgp_solver_report.argtypes = [vp, R]
     lib.sgp_solver_set_timing.argtypes = [vp, i]
     lib.sgp_solver_set_graph.argtypes = [vp, i]
@@ -128,6 +130,8 @@ def load():
     lib.sgp_save_tile_schedule.argtypes = [ctypes.c_char_p]
     lib.sgp_load_tile_schedule.argtypes = [ctypes.c_char_p]
     lib.sgp_autotune.argtypes = [ctypes.POINTER(_Problem), vp, i, ip, ip, ctypes.POINTER(d), vp]
+    dp = ctypes.POINTER(d)
+    lib.sgp_flux_multiplier.argtypes = [dp, dp, ctypes.c_longlong, d, i, dp, ip, ip]
     lib.sgp_strerror.restype = ctypes.c_char_p
     lib.sgp_strerror.argtypes = [i]
     lib.sgp_last_error.restype = ctypes.c_char_p
@@ -145,7 +149,7 @@ def default_params() -> dict:
     return {name: getattr(p, name) for name, _ in _Params._fields_ if name not in ("f0", "trace")}
 
 
-def _make_params(kw: dict, trace_rows: int | None):
+def _make_params(kw: dict, trace_rows: int | None, fshape=None):
     lib = load()
     p = _Params()
     lib.sgp_params_init(ctypes.byref(p))
@@ -153,6 +157,8 @@ def _make_params(kw: dict, trace_rows: int | None):
     for k, v in kw.items():
         if k == "f0":
             _check_dev(v, "f0")
+            if fshape is not None:
+                _check_shape(v, fshape, "f0")
             p.f0 = v.data_ptr()
             keep.append(v)
         elif k == "trace":
@@ -178,6 +184,14 @@ def _check_dev(t, name):
         raise TypeError(f"{name} must be contiguous float32")
 
 
+def _check_shape(t, shape, name):
+    """The library takes every size from its integer arguments and reads or
+    writes that many elements: a tensor of another shape would be accessed
+    out of bounds on the device, so it is refused here."""
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+
+
 def _stream(stream):
     import torch
     s = stream if stream is not None else torch.cuda.current_stream()
@@ -200,9 +214,17 @@ def _report(rep: _Report, rc: int, trace):
     return out
 
 
+MAX_IMAGES = 8  # images per problem the library accepts (1 <= p <= 8)
+
+
 def _bconst(b, p):
-    arr = (ctypes.c_float * 8)()
-    vals = np.broadcast_to(np.asarray(b, dtype=np.float32).ravel() if np.ndim(b) else np.float32(b), (p,))
+    if not 1 <= p <= MAX_IMAGES:
+        raise ValueError(f"p = {p} images; the library takes 1..{MAX_IMAGES}")
+    arr = (ctypes.c_float * MAX_IMAGES)()
+    bv = np.asarray(b, dtype=np.float32).ravel() if np.ndim(b) else np.float32(b)
+    if np.ndim(bv) and bv.size not in (1, p):
+        raise ValueError(f"{bv.size} backgrounds given for {p} images")
+    vals = np.broadcast_to(bv, (p,))
     for j in range(p):
         arr[j] = float(vals[j])
     return arr
@@ -212,13 +234,18 @@ def _solve_single(fn, g, psf, b, b_map, f, stream, trace, kw):
     import torch
     _check_dev(g, "g")
     _check_dev(psf, "psf")
-    ny, nx = g.shape[-2], g.shape[-1]
+    if g.dim() != 2:
+        raise ValueError(f"g must be 2D [ny, nx], got shape {tuple(g.shape)}")
+    ny, nx = g.shape
+    _check_shape(psf, (ny, nx), "psf")
     if b_map is not None:
         _check_dev(b_map, "b_map")
+        _check_shape(b_map, (ny, nx), "b_map")
     if f is None:
         f = torch.empty((ny, nx), dtype=torch.float32, device=g.device)
     _check_dev(f, "f")
-    prm, tr, keep = _make_params(kw, (kw.get("max_iter", 1000) + 1) if trace else None)
+    _check_shape(f, (ny, nx), "f")
+    prm, tr, keep = _make_params(kw, (kw.get("max_iter", 1000) + 1) if trace else None, (ny, nx))
     rep = _Report()
     rc = fn(ctypes.c_void_p(g.data_ptr()), ctypes.c_void_p(psf.data_ptr()),
             ctypes.c_void_p(b_map.data_ptr() if b_map is not None else 0), ctypes.c_float(float(b)),
@@ -238,22 +265,41 @@ def rl_deconv(g, psf, b=0.0, *, b_map=None, f=None, stream=None, trace=False, **
     return _solve_single(load().rl_deconv, g, psf, b, b_map, f, stream, trace, params)
 
 
+def _stack_shapes(g, psf, b_map, domain):
+    """Checks a [p, ny, nx] image stack (2D for p = 1), its [p, NY, NX] PSFs
+    and background maps against each other and the domain; returns the 3D
+    views and (p, ny, nx, NY, NX, oy, ox)."""
+    if g.dim() == 2:
+        g = g.unsqueeze(0)
+    if g.dim() != 3:
+        raise ValueError(f"g must be [p, ny, nx] or [ny, nx], got shape {tuple(g.shape)}")
+    p, ny, nx = g.shape
+    if not 1 <= p <= MAX_IMAGES:
+        raise ValueError(f"p = {p} images; the library takes 1..{MAX_IMAGES}")
+    NY, NX, oy, ox = (int(v) for v in domain) if domain is not None else (ny, nx, 0, 0)
+    if domain is not None and not (0 <= oy and 0 <= ox and oy + ny <= NY and ox + nx <= NX):
+        raise ValueError(f"window {ny}x{nx} at ({oy}, {ox}) does not lie inside the {NY}x{NX} domain")
+    if psf.dim() == 2 and p == 1:
+        psf = psf.unsqueeze(0)
+    _check_shape(psf, (p, NY, NX), "psf")
+    if b_map is not None:
+        _check_dev(b_map, "b_map")
+        if b_map.dim() == 2 and p == 1:
+            b_map = b_map.unsqueeze(0)
+        _check_shape(b_map, (p, ny, nx), "b_map")
+    return g, psf, b_map, (p, ny, nx, NY, NX, oy, ox)
+
+
 def _solve_stack(fn, g, psf, b, b_map, f, stream, trace, kw, domain=None):
     import torch
     _check_dev(g, "g")
     _check_dev(psf, "psf")
-    if g.dim() == 2:
-        g = g.unsqueeze(0)
-    if psf.dim() == 2:
-        psf = psf.unsqueeze(0)
-    p, ny, nx = g.shape
-    if b_map is not None:
-        _check_dev(b_map, "b_map")
-    NY, NX, oy, ox = domain if domain is not None else (ny, nx, 0, 0)
+    g, psf, b_map, (p, ny, nx, NY, NX, oy, ox) = _stack_shapes(g, psf, b_map, domain)
     if f is None:
         f = torch.empty((NY, NX), dtype=torch.float32, device=g.device)
     _check_dev(f, "f")
-    prm, tr, keep = _make_params(kw, (kw.get("max_iter", 1000) + 1) if trace else None)
+    _check_shape(f, (NY, NX), "f")
+    prm, tr, keep = _make_params(kw, (kw.get("max_iter", 1000) + 1) if trace else None, (NY, NX))
     rep = _Report()
     bc = _bconst(b, p)
     args = [ctypes.c_void_p(g.data_ptr()), ctypes.c_void_p(psf.data_ptr()),
@@ -302,6 +348,8 @@ def mosaic_deconv(g, psf, b, core, margin, *, kind=KIND_SGP, f=None, stream=None
     import torch
     _check_dev(g, "g")
     _check_dev(psf, "psf")
+    if g.dim() != 2:
+        raise ValueError(f"g must be 2D [H, W], got shape {tuple(g.shape)}")
     H, W = g.shape
     N = psf.shape[-1]
     if psf.shape != (N, N):
@@ -309,6 +357,7 @@ def mosaic_deconv(g, psf, b, core, margin, *, kind=KIND_SGP, f=None, stream=None
     if f is None:
         f = torch.empty_like(g)
     _check_dev(f, "f")
+    _check_shape(f, (H, W), "f")
     prm, _, _ = _make_params(params, None)
     rep = _Report()
     rc = load().sgp_mosaic_deconv(int(kind), ctypes.c_void_p(g.data_ptr()), H, W, ctypes.c_void_p(psf.data_ptr()),
@@ -323,9 +372,14 @@ def apply_operator(psf, x, adjoint=False, out=None, stream=None):
     import torch
     _check_dev(psf, "psf")
     _check_dev(x, "x")
+    if x.dim() != 2:
+        raise ValueError(f"x must be 2D [ny, nx], got shape {tuple(x.shape)}")
     ny, nx = x.shape
+    _check_shape(psf, (ny, nx), "psf")
     if out is None:
         out = torch.empty_like(x)
+    _check_dev(out, "out")
+    _check_shape(out, (ny, nx), "out")
     rc = load().sgp_apply_operator(ctypes.c_void_p(psf.data_ptr()), ctypes.c_void_p(x.data_ptr()),
                                    ny, nx, 1 if adjoint else 0, ctypes.c_void_p(out.data_ptr()),
                                    _stream(stream))
@@ -374,10 +428,7 @@ def autotune(g, psf, b, *, domain=None, iters=20, stream=None):
     lib = load()
     _check_dev(g, "g")
     _check_dev(psf, "psf")
-    g3 = g.unsqueeze(0) if g.dim() == 2 else g
-    psf3 = psf.unsqueeze(0) if psf.dim() == 2 else psf
-    p, ny, nx = g3.shape
-    NY, NX, oy, ox = domain if domain is not None else (ny, nx, 0, 0)
+    g3, psf3, _, (p, ny, nx, NY, NX, oy, ox) = _stack_shapes(g, psf, None, domain)
     bc = _bconst(b, p)
     pr = _Problem(g3.data_ptr(), psf3.data_ptr(), None, ctypes.cast(bc, ctypes.c_void_p), p, ny, nx, NY, NX,
                   oy, ox, 1 if domain is not None else 0)
@@ -402,21 +453,17 @@ class Solver:
         lib = load()
         _check_dev(g, "g")
         _check_dev(psf, "psf")
-        g3 = g.unsqueeze(0) if g.dim() == 2 else g
-        psf3 = psf.unsqueeze(0) if psf.dim() == 2 else psf
-        p, ny, nx = g3.shape
-        NY, NX, oy, ox = domain if domain is not None else (ny, nx, 0, 0)
+        g3, psf3, b_map, (p, ny, nx, NY, NX, oy, ox) = _stack_shapes(g, psf, b_map, domain)
         if f is None:
             f = torch.empty((NY, NX), dtype=torch.float32, device=g.device)
         _check_dev(f, "f")
-        if b_map is not None:
-            _check_dev(b_map, "b_map")
+        _check_shape(f, (NY, NX), "f")
         self._bc = _bconst(b, p)
         pr = _Problem(g3.data_ptr(), psf3.data_ptr(), b_map.data_ptr() if b_map is not None else None,
                       ctypes.cast(self._bc, ctypes.c_void_p), p, ny, nx, NY, NX, oy, ox,
                       1 if domain is not None else 0)
         self._prm, self._trace, self._keep = _make_params(
-            params, (params.get("max_iter", 1000) + 1) if trace else None)
+            params, (params.get("max_iter", 1000) + 1) if trace else None, (NY, NX))
         self._keep += [g3, psf3, b_map, f]
         self.f = f
         self._h = ctypes.c_void_p()
@@ -428,6 +475,10 @@ class Solver:
         done = ctypes.c_int(0)
         _raise(load().sgp_solver_step(self._h, int(n), ctypes.byref(done)))
         return bool(done.value)
+
+    def prepare(self, n):
+        """Captures the graphs a later step(n) replays (no iteration runs)."""
+        _raise(load().sgp_solver_prepare(self._h, int(n)))
 
     def report(self):
         rep = _Report()
@@ -473,15 +524,37 @@ def steplength_rule(k, alpha, tau, Q, a, c1, c2, e, **params):
                 br1=int(out[5]), br2=int(out[6]), Q=[out[8 + i] for i in range(nq)])
 
 
-def batch_deconv(gs, psfs, bs, *, kind=KIND_SGP, f0s=None, fs=None, stream=None, **params):
+def flux_multiplier(z, D, c, max_steps=8):
+    """The device's search for the flux-projection multiplier run on the host
+    (validation): returns (mu, Newton steps, converged, return code)."""
+    z = np.ascontiguousarray(z, dtype=np.float64).ravel()
+    D = np.ascontiguousarray(D, dtype=np.float64).ravel()
+    if z.size != D.size:
+        raise ValueError("z and D must have the same size")
+    mu, steps, conv = ctypes.c_double(), ctypes.c_int(), ctypes.c_int()
+    dp = ctypes.POINTER(ctypes.c_double)
+    rc = load().sgp_flux_multiplier(z.ctypes.data_as(dp), D.ctypes.data_as(dp), z.size, float(c), int(max_steps),
+                                    ctypes.byref(mu), ctypes.byref(steps), ctypes.byref(conv))
+    _raise(rc)
+    return mu.value, steps.value, bool(conv.value), rc
+
+
+def batch_deconv(gs, psfs, bs, *, kind=KIND_SGP, f0s=None, fs=None, domains=None, stream=None, **params):
     """Many single-image problems (uneven sizes) in one batched run.
     gs, psfs: lists of 2D CUDA tensors; bs: constant backgrounds; f0s: optional
-    starts (init=INIT_USER or INIT_WARM).  Returns (list of f, list of reports)."""
+    starts (init=INIT_USER or INIT_WARM); domains: optional list with, per
+    problem, None (periodic) or (NY, NX, oy, ox) for boundary-effect
+    correction (its PSF, f and f0 are then NY x NX).  Returns (list of f,
+    list of reports)."""
     import torch
     lib = load()
     n = len(gs)
+    if len(psfs) != n or len(bs) != n or any(x is not None and len(x) != n for x in (fs, f0s, domains)):
+        raise ValueError("gs, psfs, bs (and fs, f0s, domains when given) must have one entry per problem")
+    doms = [None] * n if domains is None else [None if d is None else tuple(int(v) for v in d) for d in domains]
     if fs is None:
-        fs = [torch.empty_like(g) for g in gs]
+        fs = [torch.empty((d[0], d[1]) if d else tuple(g.shape), dtype=torch.float32, device=g.device)
+              for g, d in zip(gs, doms)]
     probs = (_Problem * n)()
     keep = [gs, psfs, fs, f0s]
     bcs = []
@@ -489,11 +562,20 @@ def batch_deconv(gs, psfs, bs, *, kind=KIND_SGP, f0s=None, fs=None, stream=None,
         _check_dev(gs[i], "g")
         _check_dev(psfs[i], "psf")
         _check_dev(fs[i], "f")
+        if gs[i].dim() != 2:
+            raise ValueError(f"g[{i}] must be 2D [ny, nx], got shape {tuple(gs[i].shape)}")
         ny, nx = gs[i].shape
+        NY, NX, oy, ox = doms[i] if doms[i] else (ny, nx, 0, 0)
+        if doms[i] and not (0 <= oy and 0 <= ox and oy + ny <= NY and ox + nx <= NX):
+            raise ValueError(f"problem {i}: window {ny}x{nx} at ({oy}, {ox}) outside the {NY}x{NX} domain")
+        _check_shape(psfs[i], (NY, NX), f"psf[{i}]")
+        _check_shape(fs[i], (NY, NX), f"f[{i}]")
+        if f0s is not None:
+            _check_shape(f0s[i], (NY, NX), f"f0[{i}]")
         bc = (ctypes.c_float * 1)(float(bs[i]))
         bcs.append(bc)
         probs[i] = _Problem(gs[i].data_ptr(), psfs[i].data_ptr(), None, ctypes.cast(bc, ctypes.c_void_p),
-                            1, ny, nx, ny, nx, 0, 0, 0)
+                            1, ny, nx, NY, NX, oy, ox, 1 if doms[i] else 0)
     fp = (ctypes.c_void_p * n)(*[f.data_ptr() for f in fs])
     f0p = None
     if f0s is not None:
@@ -539,6 +621,18 @@ class CnnNet:
             raise ValueError("one call takes 2D images of one shape")
         return next(iter(shapes))
 
+    @staticmethod
+    def _same(gs, others, name):
+        if len(others) != len(gs):
+            raise ValueError(f"{len(others)} {name} tensors for {len(gs)} images")
+        for i, t in enumerate(others):
+            _check_shape(t, gs[0].shape, f"{name}[{i}]")
+
+    @staticmethod
+    def _backgrounds(bs, n):
+        b = np.ascontiguousarray(np.broadcast_to(np.asarray(bs, dtype=np.float32).ravel(), (n,)))
+        return b
+
     def params(self):
         out = np.empty(self.n_params, dtype=np.float32)
         _raise(load().sgp_cnn_get_params(self._h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
@@ -551,7 +645,8 @@ class CnnNet:
         ny, nx = self._shape(gs)
         if out is None:
             out = [torch.empty_like(g) for g in gs]
-        b = np.ascontiguousarray(bs, dtype=np.float32)
+        self._same(gs, out, "f0")
+        b = self._backgrounds(bs, len(gs))
         _raise(load().sgp_cnn_infer(self._h, len(gs), _ptrs(gs, "g"),
                                     b.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), ny, nx,
                                     _ptrs(out, "f0"), _stream(stream)))
@@ -560,7 +655,8 @@ class CnnNet:
     def loss_grad(self, gs, bs, targets, stream=None):
         """(mean loss, gradient as float32 numpy) of one batch."""
         ny, nx = self._shape(gs)
-        b = np.ascontiguousarray(bs, dtype=np.float32)
+        self._same(gs, targets, "target")
+        b = self._backgrounds(bs, len(gs))
         loss = ctypes.c_double()
         grad = np.empty(self.n_params, dtype=np.float32)
         _raise(load().sgp_cnn_loss_grad(self._h, len(gs), _ptrs(gs, "g"),
@@ -575,7 +671,8 @@ class CnnNet:
     def train_step(self, gs, bs, targets, lr, stream=None):
         """Loss, gradient and Adam step on one batch; returns the loss."""
         ny, nx = self._shape(gs)
-        b = np.ascontiguousarray(bs, dtype=np.float32)
+        self._same(gs, targets, "target")
+        b = self._backgrounds(bs, len(gs))
         loss = ctypes.c_double()
         _raise(load().sgp_cnn_train_step(self._h, len(gs), _ptrs(gs, "g"),
                                          b.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),

@@ -51,6 +51,7 @@ struct DevState {
   double flux_fixed; // sum of max(0, z) over pixels with D = 0
   double flux_cnt;   // active-set size at the current mu
   int flux_done;     // Newton iteration for mu has converged
+  int flux_unconv;   // iterations whose multiplier had not converged after the last Newton pass
   double* trace;     // [max_iter + 1][kTraceCols] or null
   double rl_alpha;   // exponent of the relaxed RL step, Eq. (RL1) (1: RL)
   int f_pending;     // an accepted step waits for f += lam d (taken by the

@@ -240,7 +240,10 @@ __host__ __device__ inline void fin_flux_init(DevState* st, const double* t) {
 // t = {sum_{active} z, sum_{active} D, #active} with active = {z - mu D > 0}
 // at the current mu.  An unchanged active set means the step returns the
 // current mu: the root.
-__host__ __device__ inline void fin_flux_newton(DevState* st, const double* t) {
+// last: this is the last Newton pass of the iteration; if mu has still not
+// converged, the direction is projected with a mu left of the root (sum of
+// the projection above c), which is counted in flux_unconv and reported.
+__host__ __device__ inline void fin_flux_newton(DevState* st, const double* t, bool last = false) {
   if (!(t[1] > 0.0)) {  // nothing active: c' <= 0, the projection is x = 0 on D > 0
     st->flux_done = 1;
     return;
@@ -252,6 +255,8 @@ __host__ __device__ inline void fin_flux_newton(DevState* st, const double* t) {
   if (!__builtin_isfinite(mu)) {
     st->done = 1;
     st->reason = REASON_NUMERIC;
+  } else if (last && !st->flux_done) {
+    st->flux_unconv += 1;
   }
 }
 

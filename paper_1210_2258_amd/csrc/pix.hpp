@@ -149,8 +149,8 @@ __global__ __launch_bounds__(kPixThreads) void pix_kernel(Args a_in) {
       a.f[i] = v;
     }
   } else if constexpr (OP == PIX_CHOOSE) {
-    // Sect. 3.1 start "provided by the user", kept only if its KL is not
-    // larger than that of the flat start
+    // Sect. 3.1: a caller-supplied start, kept only if its KL is not larger
+    // than that of the flat start
     if (st->J > st->J_alt) {
       for (long long i = i0; i < nF; i += stride) {
         const float w = a.invw ? a.invw[i] : a.invw_s;
@@ -258,7 +258,7 @@ __global__ __launch_bounds__(kPixThreads) void pix_kernel(Args a_in) {
       } else if constexpr (OP == PIX_FLUX_INIT) {
         fin_flux_init(st, tot);
       } else if constexpr (OP == PIX_FLUX_NEWTON) {
-        fin_flux_newton(st, tot);
+        fin_flux_newton(st, tot, (a.flag & 1) != 0);
       } else if constexpr (OP == PIX_FSUM) {
         st->fsum = tot[0];
       }

@@ -444,9 +444,9 @@ struct sgp_solver {
   sgp::Plan* pl = nullptr;
   std::unique_ptr<sgp::Plan> owned;
   sgp::Launcher L;
-  hipGraphExec_t graph = nullptr;
-  hipGraph_t graph_def = nullptr;
-  int graph_block = 0;
+  // captured iteration blocks, by length: full blocks and the remainder of
+  // a step() call each replay a graph of exactly their iteration count
+  std::map<int, std::pair<hipGraph_t, hipGraphExec_t>> graphs;
   bool use_graph = true;
   bool done = false;
   int nitems = 1;  // batched problems (same shape), item i's iterate is fs[i]
@@ -457,8 +457,10 @@ struct sgp_solver {
 
   bool own_stream = true;   // false: the per-device stream of the one-shot calls
   ~sgp_solver() {
-    if (graph) (void)hipGraphExecDestroy(graph);
-    if (graph_def) (void)hipGraphDestroy(graph_def);
+    for (auto& kv : graphs) {
+      (void)hipGraphExecDestroy(kv.second.second);
+      (void)hipGraphDestroy(kv.second.first);
+    }
     if (s && own_stream) (void)hipStreamDestroy(s);
   }
 };
@@ -501,7 +503,13 @@ static void enqueue_iteration(sgp_solver* S) {
     if (S->prm.flux_constraint) {
       const long long nF = (long long)S->pb.NY * S->pb.NX;
       L.pix(PIX_FLUX_INIT, nF, 1, 0, SGP_KCLASS_ROW_DIR);
-      for (int t = 0; t < kFluxNewton; ++t) L.pix(PIX_FLUX_NEWTON, nF, 1, 0, SGP_KCLASS_ROW_DIR);
+      for (int t = 0; t < kFluxNewton; ++t) {
+        // the last pass counts an iteration whose multiplier is still not at the root
+        const int save = L.base.flag;
+        L.base.flag = t == kFluxNewton - 1 ? 1 : 0;
+        L.pix(PIX_FLUX_NEWTON, nF, 1, 0, SGP_KCLASS_ROW_DIR);
+        L.base.flag = save;
+      }
     }
     // each row kernel's reduction is finished at the start of the next launch
     // (the direction and update sums by the column kernels, the Armijo test by
@@ -622,23 +630,56 @@ static int setup(sgp_solver* S) {
   return 0;
 }
 
-static int capture_graph(sgp_solver* S, int block) {
-  if (S->graph) {
-    (void)hipGraphExecDestroy(S->graph);
-    S->graph = nullptr;
-  }
-  if (S->graph_def) {
-    (void)hipGraphDestroy(S->graph_def);
-    S->graph_def = nullptr;
+// The graph of `block` iterations, captured on first use and kept.
+static int block_graph(sgp_solver* S, int block, hipGraphExec_t* out) {
+  auto it = S->graphs.find(block);
+  if (it != S->graphs.end()) {
+    *out = it->second.second;
+    return 0;
   }
   SGP_HIP(hipStreamBeginCapture(S->s, hipStreamCaptureModeThreadLocal));
   for (int b = 0; b < block; ++b) enqueue_iteration(S);
   hipGraph_t g = nullptr;
   hipError_t e = hipStreamEndCapture(S->s, &g);
   if (e != hipSuccess) return fail(SGP_E_HIP, std::string("graph capture: ") + hipGetErrorString(e));
-  S->graph_def = g;
-  SGP_HIP(hipGraphInstantiate(&S->graph, g, nullptr, nullptr, 0));
-  S->graph_block = block;
+  hipGraphExec_t x = nullptr;
+  e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    (void)hipGraphDestroy(g);
+    return fail(SGP_E_HIP, std::string("graph instantiation: ") + hipGetErrorString(e));
+  }
+  S->graphs[block] = {g, x};
+  *out = x;
+  return 0;
+}
+
+// Iterations of a step(n) call and how they are replayed: blocks of 32 (16
+// with an early stop rule, so that the state is read often enough), then
+// one block of the remainder.
+struct StepPlan {
+  int iters, block, full, rem;
+  bool early;
+};
+static StepPlan step_plan(const sgp_solver* S, int n) {
+  StepPlan p;
+  p.early = (S->prm.stop & (SGP_STOP_CONV | SGP_STOP_DISCREPANCY)) != 0;
+  p.iters = em_kind(S->kind) ? n + 1 : n;  // RL / OSEM evaluate J once more before pausing
+  p.block = std::min(p.iters, p.early ? 16 : 32);
+  p.full = p.block > 0 ? p.iters / p.block : 0;
+  p.rem = p.block > 0 ? p.iters % p.block : 0;
+  return p;
+}
+
+// Captures the graphs a later step(n) call replays, so that no capture falls
+// inside that call.
+static int prepare(sgp_solver* S, int n) {
+  if (n < 0) return fail(SGP_E_INVALID_ARG, "n must be >= 0");
+  const StepPlan p = step_plan(S, n);
+  if (!S->use_graph || p.iters == 0) return 0;
+  hipGraphExec_t x;
+  int rc;
+  if ((rc = block_graph(S, p.block, &x))) return rc;
+  if (p.rem && (rc = block_graph(S, p.rem, &x))) return rc;
   return 0;
 }
 
@@ -655,8 +696,9 @@ static int step(sgp_solver* S, int n, int* done_out) {
     src_iterate(S);
     S->L.row(ROW_FIELD, 1, 0);
   }
-  const bool early = (S->prm.stop & (SGP_STOP_CONV | SGP_STOP_DISCREPANCY)) != 0;
-  const int iters = em_kind(S->kind) ? n + 1 : n;  // RL / OSEM evaluate J once more before pausing
+  const StepPlan sp = step_plan(S, n);
+  const bool early = sp.early;
+  const int iters = sp.iters;
   if (S->L.timing || !S->use_graph) {
     for (int it = 0; it < iters; ++it) {
       enqueue_iteration(S);
@@ -679,13 +721,12 @@ static int step(sgp_solver* S, int n, int* done_out) {
     // a run with an early stop replays blocks of 16 iterations and reads the
     // state after each of the first four (a short run then ends with no
     // replay of iterations that only exit), later after every second one
-    const int block = std::min(iters, early ? 16 : 32);
-    if (!S->graph || S->graph_block != block) {
-      if ((rc = capture_graph(S, block))) return rc;
-    }
-    const int reps = (iters + block - 1) / block;
+    hipGraphExec_t gfull = nullptr, grem = nullptr;
+    if ((rc = block_graph(S, sp.block, &gfull))) return rc;
+    if (sp.rem && (rc = block_graph(S, sp.rem, &grem))) return rc;
+    const int reps = sp.full + (sp.rem ? 1 : 0);
     for (int r = 0; r < reps; ++r) {
-      SGP_HIP(hipGraphLaunch(S->graph, S->s));
+      SGP_HIP(hipGraphLaunch(r < sp.full ? gfull : grem, S->s));
       if (early && r + 1 < reps && (r < 4 || (r % 2) == 1)) {
         if ((rc = read_state(S))) return rc;
         if (all_done(S)) break;
@@ -699,15 +740,20 @@ static int step(sgp_solver* S, int n, int* done_out) {
 }
 
 static int item_code(const sgp_solver* S, const DevState& h) {
-  if (!h.done) return SGP_OK;
-  switch (h.reason) {
-    case REASON_NUMERIC: return fail(SGP_E_NUMERIC, "non-finite value during the iteration");
-    case REASON_ARMIJO: return SGP_W_ARMIJO_EXHAUSTED;
-    case REASON_STATIONARY: return SGP_W_STATIONARY;
-    case REASON_MAXITER:
-      return (S->prm.stop & (SGP_STOP_CONV | SGP_STOP_DISCREPANCY)) ? SGP_W_MAXITER : SGP_OK;
-    default: return SGP_OK;
+  int code = SGP_OK;
+  if (h.done) {
+    switch (h.reason) {
+      case REASON_NUMERIC: return fail(SGP_E_NUMERIC, "non-finite value during the iteration");
+      case REASON_ARMIJO: code = SGP_W_ARMIJO_EXHAUSTED; break;
+      case REASON_STATIONARY: code = SGP_W_STATIONARY; break;
+      case REASON_MAXITER:
+        code = (S->prm.stop & (SGP_STOP_CONV | SGP_STOP_DISCREPANCY)) ? SGP_W_MAXITER : SGP_OK;
+        break;
+      default: break;
+    }
   }
+  if (h.flux_unconv > 0) code = std::max(code, (int)SGP_W_FLUX_UNCONVERGED);
+  return code;
 }
 
 static void fill_report(const sgp_solver* S, const DevState& h, sgp_report* rep) {
@@ -720,6 +766,7 @@ static void fill_report(const sgp_solver* S, const DevState& h, sgp_report* rep)
   rep->flux = h.fsum;
   rep->L1 = h.L1;
   rep->L2 = h.L2;
+  rep->flux_unconverged = h.flux_unconv;
   rep->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - S->t0).count();
 }
 
@@ -1293,6 +1340,11 @@ int sgp_solver_step(sgp_solver* s, int n, int* done) {
   SGP_GUARD(step(s, n, done));
 }
 
+int sgp_solver_prepare(sgp_solver* s, int n) {
+  if (!s) return fail(SGP_E_INVALID_ARG, "null solver");
+  SGP_GUARD(prepare(s, n));
+}
+
 int sgp_solver_report(sgp_solver* s, sgp_report* rep) {
   if (!s) return fail(SGP_E_INVALID_ARG, "null solver");
   SGP_GUARD(report(s, rep));
@@ -1365,6 +1417,44 @@ int sgp_steplength_rule(const sgp_params* prm, int k, double alpha, double tau, 
   out[7] = st.nQ;
   for (int i = 0; i < 8; ++i) out[8 + i] = i < st.nQ ? st.Q[i] : 0.0;
   return 0;
+}
+
+int sgp_flux_multiplier(const double* z, const double* D, long long n, double c, int max_steps, double* mu,
+                        int* steps, int* converged) {
+  if (!z || !D || n < 1 || max_steps < 0 || !mu) return fail(SGP_E_INVALID_ARG, "bad arguments");
+  DevState st;
+  std::memset(&st, 0, sizeof(st));
+  st.flux_c = c;
+  // the sums of the all-active pass (PIX_FLUX_INIT), in the same order and precision
+  double t[5] = {0.0, 0.0, __builtin_inf(), 0.0, 0.0};
+  for (long long i = 0; i < n; ++i) {
+    if (D[i] > 0.0) {
+      t[0] += z[i];
+      t[1] += D[i];
+      t[2] = std::fmin(t[2], z[i] / D[i]);
+      t[4] += 1.0;
+    } else {
+      t[3] += std::fmax(0.0, z[i]);
+    }
+  }
+  fin_flux_init(&st, t);
+  int k = 0;
+  for (; k < max_steps && !st.flux_done && !st.done; ++k) {  // the Newton passes (PIX_FLUX_NEWTON)
+    double u[3] = {0.0, 0.0, 0.0};
+    for (long long i = 0; i < n; ++i) {
+      if (D[i] > 0.0 && z[i] - st.mu * D[i] > 0.0) {
+        u[0] += z[i];
+        u[1] += D[i];
+        u[2] += 1.0;
+      }
+    }
+    fin_flux_newton(&st, u, k == max_steps - 1);
+  }
+  *mu = st.mu;
+  if (steps) *steps = k;
+  if (converged) *converged = st.flux_done;
+  if (st.done) return fail(SGP_E_NUMERIC, "non-finite multiplier");
+  return st.flux_unconv > 0 ? SGP_W_FLUX_UNCONVERGED : SGP_OK;
 }
 
 // ------------------------------------------------------------ tile schedule
@@ -1540,6 +1630,7 @@ const char* sgp_strerror(int code) {
     case SGP_W_MAXITER: return "warning: iteration cap reached before the stop rule";
     case SGP_W_ARMIJO_EXHAUSTED: return "warning: Armijo backtracking exhausted";
     case SGP_W_STATIONARY: return "warning: stationary point (grad^T d = 0)";
+    case SGP_W_FLUX_UNCONVERGED: return "warning: flux-projection multiplier not converged in some iteration";
     case SGP_E_INVALID_ARG: return "invalid argument";
     case SGP_E_UNSUPPORTED_SIZE: return "unsupported FFT size";
     case SGP_E_BAD_PSF: return "bad PSF";

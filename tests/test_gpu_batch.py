@@ -80,3 +80,28 @@ def test_warm_start_fallback(torch_dev):
     f_flat, r_flat = m.sgp_deconv(g, psf, b, max_iter=5)
     assert torch.equal(fs[1], f_flat)
     assert reps[0]["kl"] < r_flat["kl"]
+
+
+def test_batch_equals_single_large_and_boundary(torch_dev):
+    """Batch items at the sizes of the 512-image benchmark batch (512^2,
+    1024^2) and a boundary-corrected item on a 1280^2 domain (its 1024^2
+    window at offset 128) equal their single runs bit for bit."""
+    import paper_1210_2258_amd as m
+    torch = torch_dev
+    items = [W.star_field(201, 0, 512, 512, 100, 2.0, 20.0), W.star_field(201, 1, 1024, 1024, 100, 3.0, 10.0),
+             W.config3(), W.star_field(201, 2, 256, 256, 100, 1.5, 40.0)]
+    gs = [_dev(torch, w.g[0]) for w in items]
+    ps = [_dev(torch, w.psf[0]) for w in items]
+    bs = [float(w.b[0]) for w in items]
+    doms = [w.domain for w in items]
+    kw = dict(max_iter=20)
+    fs, reps = m.batch_deconv(gs, ps, bs, domains=doms, **kw)
+    for i, w in enumerate(items):
+        if w.domain is None:
+            f1, r1 = m.sgp_deconv(gs[i], ps[i], bs[i], **kw)
+        else:
+            f1, r1 = m.sgp_boundary_deconv(gs[i][None], ps[i][None], [bs[i]], w.domain, **kw)
+        print(f"item {i} {tuple(gs[i].shape)} domain {w.domain}: iters {reps[i]['iters']}", flush=True)
+        assert r1["iters"] == reps[i]["iters"] == 20, (i, r1["iters"], reps[i]["iters"])
+        assert torch.equal(f1, fs[i]), i
+        assert r1["kl"] == reps[i]["kl"], i

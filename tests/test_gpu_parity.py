@@ -348,22 +348,48 @@ def test_gpu_errors(torch_dev):
 
 
 # the flux-constrained runs drift a little faster than the plain ones
-FLUX_K = {"single_64x80": 6, "single_c0_256": 12, "multi_3x64": 4}
+FLUX_K = {"single_64x80": 6, "single_c0_256": 12, "multi_3x64": 4, "boundary_64x48_in_80x64": 4}
 
 
 @pytest.mark.parametrize("case", list(FLUX_K))
 def test_sgp_flux_constraint(torch_dev, case):
     """Flux-constrained SGP (projection onto {f >= 0, sum f = c} in the
-    D^-1 metric): GPU Newton multiplier vs the oracle's breakpoint scan."""
+    D^-1 metric): GPU Newton multiplier vs the oracle's breakpoint scan; the
+    multiplier converged in every iteration (no warning)."""
     w = CASES[case]()
     n = FLUX_K[case]
-    fn = "sgp_deconv" if w.p == 1 else "sgp_multi_deconv"
+    fn = "sgp_deconv" if (w.domain is None and w.p == 1) else (
+        "sgp_multi_deconv" if w.domain is None else "sgp_boundary_deconv")
     f, rep = _run_gpu(torch_dev, fn, w, max_iter=n, flux_constraint=1)
+    assert rep["rc"] == 0 and rep["flux_unconverged"] == 0, (rep["rc"], rep["flux_unconverged"])
     P = _oracle(w)
     prm = O.Params(max_iter=n, flux_constraint=True)
     fo, io = P.sgp(P.start("flat"), prm)
     c = P.flux_value(prm)
     assert abs(rep["flux"] - c) <= 1e-5 * c, (rep["flux"], c)
     _check_log(rep["trace"], io["log"], n)
+    assert _rel(f.cpu().numpy(), fo) <= F_TOL, _rel(f.cpu().numpy(), fo)
+    assert abs(rep["kl"] - io["kl"]) <= KL_TOL * io["kl"], (rep["kl"], io["kl"])
+
+
+@pytest.mark.parametrize("kind,case,tol", [("rl", "single_64x80", 1e-3), ("sgp", "single_64x80", 2e-2),
+                                          ("osem", "multi_3x64", 1e-3), ("rl", "multi_3x64", 1e-3)])
+def test_convergence_stop_matches(torch_dev, kind, case, tol):
+    """Eq. (convergence) |J(k) - J(k-1)| <= tol J(k-1): the run stops at the
+    oracle's index and returns its iterate (for SGP at a tolerance the
+    parity window reaches: the relative KL change first falls below 2e-2 at
+    k = 2 on the 64x80 field)."""
+    import paper_1210_2258_amd as m
+    w = CASES[case]()
+    fn = {("rl", 1): "rl_deconv", ("rl", 3): "rl_multi_deconv", ("sgp", 1): "sgp_deconv",
+          ("osem", 3): "osem_deconv"}[(kind, w.p)]
+    f, rep = _run_gpu(torch_dev, fn, w, max_iter=3000, stop=m.STOP_CONV, tol=tol)
+    P = _oracle(w)
+    prm = O.Params(max_iter=3000, stop=O.STOP_CONV, tol=tol)
+    run = {"rl": lambda: P.rl(P.start("flat"), 3000, prm), "osem": lambda: P.osem(P.start("flat"), 3000, prm),
+           "sgp": lambda: P.sgp(P.start("flat"), prm)}[kind]
+    fo, io = run()
+    assert io["reason"] == O.REASON_CONV and rep["reason"] == "convergence"
+    assert rep["iters"] == io["iters"], (rep["iters"], io["iters"])
     assert _rel(f.cpu().numpy(), fo) <= F_TOL, _rel(f.cpu().numpy(), fo)
     assert abs(rep["kl"] - io["kl"]) <= KL_TOL * io["kl"], (rep["kl"], io["kl"])
