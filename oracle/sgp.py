@@ -301,7 +301,7 @@ class Problem:
                 reason = REASON_DISCREPANCY
                 J = Jn
                 break
-            if (prm.stop & STOP_CONV) and abs(Jn - J) <= prm.tol * J:
+            if (prm.stop & STOP_CONV) and converged(Jn, J, prm.tol):
                 reason = REASON_CONV
                 J = Jn
                 break
@@ -340,7 +340,7 @@ class Problem:
             if (prm.stop & STOP_DISCREPANCY) and self.discrepancy(Jn) <= prm.disc_target:
                 reason, J = REASON_DISCREPANCY, Jn
                 break
-            if (prm.stop & STOP_CONV) and abs(Jn - J) <= prm.tol * J:
+            if (prm.stop & STOP_CONV) and converged(Jn, J, prm.tol):
                 reason, J = REASON_CONV, Jn
                 break
             J = Jn
@@ -350,6 +350,22 @@ class Problem:
     def scaling(self, f, L1, L2):
         """Eqs. (Dk), (Dkbound): D = (M_R / alpha) o min[L2, max{L1, f}]."""
         return self.invw * np.minimum(L2, np.maximum(L1, f))
+
+    def bb_sums(self, f, f_new, G, G_new, L1, L2):
+        """The four sums of Eqs. (BB1), (BB2) after the step f -> f_new:
+        s = f_new - f, z = grad(f_new) - grad(f), D the scaling of the new
+        iterate, over the pixels with D > 0.  Returns
+        (s'D^-1 D^-1 s, s'D^-1 z, s'D z, z'D D z)."""
+        s = f_new - f
+        z = G_new - G
+        Dn = self.scaling(f_new, L1, L2)
+        m = Dn > 0
+        sm, zm, Dm = s[m], z[m], Dn[m]
+        a_num = float(np.sum(sm * sm / (Dm * Dm)))
+        c1 = float(np.sum(sm * zm / Dm))
+        c2 = float(np.sum(sm * zm * Dm))
+        e_den = float(np.sum(zm * zm * Dm * Dm))
+        return a_num, c1, c2, e_den
 
     def flux_value(self, prm: Params):
         if prm.flux >= 0:
@@ -371,18 +387,21 @@ class Problem:
         the RL identity of Eq. (RL2) with lambda = 1).
         Returns (f, info) where info carries the per-iteration decision log."""
         prm = params or Params()
-        if bounds is not None:
-            L1, L2 = bounds
-        elif prm.auto_bounds:
-            L1, L2 = self.bounds(f0)
-        else:
-            L1, L2 = prm.L1, prm.L2
         c = self.flux_value(prm) if prm.flux_constraint else None
         f = f0.copy()
         if prm.flux_constraint:
+            # the start is put on the constraint set {f >= 0, sum f = c}
             tot = f.sum()
             if tot > 0:
                 f *= c / tot
+        # Sect. 3.2: the bounds come from one RL step from the starting
+        # point, the start on the constraint set when the flux is constrained
+        if bounds is not None:
+            L1, L2 = bounds
+        elif prm.auto_bounds:
+            L1, L2 = self.bounds(f)
+        else:
+            L1, L2 = prm.L1, prm.L2
         J = self.kl(f)
         G = self.grad(f)
         alpha = prm.alpha0
@@ -431,16 +450,7 @@ class Problem:
                 break
             # step 6: update
             G_new = self.grad(f_new)
-            s = f_new - f
-            z = G_new - G
-            # Eqs. (BB1), (BB2) with D of the new iterate, over pixels with D > 0
-            Dn = self.scaling(f_new, L1, L2)
-            m = Dn > 0
-            sm, zm, Dm = s[m], z[m], Dn[m]
-            a_num = float(np.sum(sm * sm / (Dm * Dm)))
-            c1 = float(np.sum(sm * zm / Dm))
-            c2 = float(np.sum(sm * zm * Dm))
-            e_den = float(np.sum(zm * zm * Dm * Dm))
+            a_num, c1, c2, e_den = self.bb_sums(f, f_new, G, G_new, L1, L2)
             a1, a2, br1, br2, alpha_next, tau, Q, alt = steplength_update(
                 alpha, tau, Q, k, a_num, c1, c2, e_den, prm)
             log.append(dict(k=k, alpha=alpha, gd=gd, backtracks=nback, lam=lam,
@@ -454,7 +464,7 @@ class Problem:
             if (prm.stop & STOP_DISCREPANCY) and self.discrepancy(J) <= prm.disc_target:
                 reason = REASON_DISCREPANCY
                 break
-            if (prm.stop & STOP_CONV) and abs(J - J_prev) <= prm.tol * J_prev:
+            if (prm.stop & STOP_CONV) and converged(J, J_prev, prm.tol):
                 reason = REASON_CONV
                 break
             if (prm.stop & STOP_RMSE) and prm.f_true is not None:
@@ -466,6 +476,11 @@ class Problem:
                 rmse_prev = rmse
         return f, dict(iters=k, kl=J, history=hist, log=log, L1=L1, L2=L2,
                        reason=reason, alpha=alpha)
+
+
+def converged(J_new, J_old, tol):
+    """Eq. (convergence): |J(f^(k+1)) - J(f^(k))| <= tol J(f^(k))."""
+    return abs(J_new - J_old) <= tol * J_old
 
 
 def steplength_update(alpha, tau, Q, k, a_num, c1, c2, e_den, prm: Params):
