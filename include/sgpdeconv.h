@@ -151,6 +151,22 @@ int sgp_deconv(const float* g, const float* psf, const float* b_map, float b_con
                int ny, int nx, const sgp_params* prm, float* f, sgp_report* rep,
                void* hip_stream);
 
+/* sgp_deconv for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same problem, arguments, iteration and results as sgp_deconv, but every
+ * workspace buffer lives in one static device array of 64 MiB that the
+ * library holds on each GPU it runs on until the process ends (enough for
+ * about 2 million pixels: up to 2048 x 1024 or 1024 x 1024; larger sizes give
+ * SGP_E_INVALID_ARG with the size needed).  The call allocates no device or
+ * pinned host memory, creates no stream or graph (each iteration is launched
+ * on hip_stream) and is synchronous on return.  prm->trace must be NULL.
+ * Every call on a GPU shares that GPU's array, which keeps the previous
+ * call's contents; calls from one process are serialised, but calls that
+ * overlap on one GPU (e.g. from several processes) race. */
+int sgp_deconv_noalloc(const float* g, const float* psf, const float* b_map, float b_const,
+                       int ny, int nx, const sgp_params* prm, float* f, sgp_report* rep,
+                       void* hip_stream);
+
 /* SGP for p images of one object (Sect. 2.3 Eqs. (multipleKL),
  * (multiplegradient); scaling f/p).  g, psf, b_map: [p][ny][nx];
  * b_const: HOST array of p constants (used when b_map is NULL); f: [ny][nx].

@@ -12,5 +12,5 @@ from ._lib import (  # noqa: F401
     rl_boundary_deconv, rl_deconv, rl_multi_deconv, sgp_boundary_deconv, sgp_deconv,
     sgp_multi_deconv, Solver, steplength_rule, KIND_RL, KIND_SGP, KCLASSES, batch_deconv, INIT_WARM, CnnNet, KIND_OSEM,
     osem_deconv, osem_boundary_deconv, mosaic_deconv, tile_info, set_tile_schedule, get_tile_schedule,
-    save_tile_schedule, load_tile_schedule, autotune, flux_multiplier,
+    save_tile_schedule, load_tile_schedule, autotune, flux_multiplier, sgp_deconv_noalloc,
 )

@@ -67,7 +67,7 @@ KCLASSES = ["row_dir", "col_conv", "row_ad", "armijo_more", "row_upd", "col_corr
             "row_ratio", "row_rlupd", "row_fin"]
 
 EXPORTS = [
-    "sgp_params_init", "rl_deconv", "sgp_deconv", "sgp_multi_deconv", "rl_multi_deconv",
+    "sgp_params_init", "rl_deconv", "sgp_deconv", "sgp_deconv_noalloc", "sgp_multi_deconv", "rl_multi_deconv",
     "sgp_boundary_deconv", "rl_boundary_deconv", "sgp_apply_operator", "sgp_release_cache",
     "sgp_strerror", "sgp_last_error", "sgp_solver_create", "sgp_solver_step", "sgp_solver_prepare",
     "sgp_solver_report",
@@ -93,7 +93,7 @@ def load():
     P, R, vp, i, f, d = (ctypes.POINTER(_Params), ctypes.POINTER(_Report), ctypes.c_void_p,
                          ctypes.c_int, ctypes.c_float, ctypes.c_double)
     lib.sgp_params_init.argtypes = [P]
-    for name in ("rl_deconv", "sgp_deconv"):
+    for name in ("rl_deconv", "sgp_deconv", "sgp_deconv_noalloc"):
         getattr(lib, name).argtypes = [vp, vp, vp, f, i, i, P, vp, R, vp]
     for name in ("sgp_multi_deconv", "rl_multi_deconv", "osem_deconv"):
         getattr(lib, name).argtypes = [vp, vp, vp, vp, i, i, i, P, vp, R, vp]
@@ -257,6 +257,14 @@ def _solve_single(fn, g, psf, b, b_map, f, stream, trace, kw):
 def sgp_deconv(g, psf, b=0.0, *, b_map=None, f=None, stream=None, trace=False, **params):
     """SGP single-image deconvolution; returns (f, report)."""
     return _solve_single(load().sgp_deconv, g, psf, b, b_map, f, stream, trace, params)
+
+
+def sgp_deconv_noalloc(g, psf, b=0.0, *, f, b_map=None, stream=None, **params):
+    """sgp_deconv on the library's static device workspace (no allocation by
+    the library; the caller passes f).  Returns (f, report)."""
+    if "trace" in params:
+        raise ValueError("sgp_deconv_noalloc keeps no trace")
+    return _solve_single(load().sgp_deconv_noalloc, g, psf, b, b_map, f, stream, False, params)
 
 
 def rl_deconv(g, psf, b=0.0, *, b_map=None, f=None, stream=None, trace=False, **params):

@@ -18,6 +18,7 @@
 #include <mutex>
 #include <string>
 #include <tuple>
+#include <type_traits>
 #include <array>
 #include <vector>
 
@@ -86,7 +87,10 @@ struct Plan {
   float* btab = nullptr;
   int* zmap = nullptr;
 
+  bool external = false;  // carved from the static workspace: nothing to free
+
   ~Plan() {
+    if (external) return;
     void* ptrs[] = {grad, d, invw, invwj, Af, Af2, Ad, aux, spec, khat, knyq, tw_row, tw_col, part, counter, st, trace,
                     (void*)gtab, (void*)ftab, (void*)psftab, (void*)srctab, btab, zmap};
     for (void* q : ptrs)
@@ -178,6 +182,61 @@ static int make_plan(const PlanKey& key, hipStream_t s, std::unique_ptr<Plan>& p
   launch_twiddle(pl->tw_col, key.NY, s);
   SGP_HIP(hipGetLastError());
   return 0;
+}
+
+// ------------------------------------------------ static workspace
+// Workspace of the entry point that allocates nothing (sgp_deconv_noalloc):
+// one file-scope device array, one copy per GPU, kept until the process ends.
+// Host code never passes the array's name to a kernel (on the host it names
+// a stand-in, not device memory); it uses the device address that
+// hipGetSymbolAddress returns for the current device.
+constexpr size_t kScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+constexpr int kMaxDevices = 64;
+static char* g_scratch_ptr[kMaxDevices];  // device address of scratch, per device
+static std::mutex g_scratch_mutex;          // one call on the static workspace at a time
+
+static int scratch_address(int dev, char** out) {
+  if (dev < 0 || dev >= kMaxDevices) return fail(SGP_E_INVALID_ARG, "device index beyond the static workspace table");
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      return fail(SGP_E_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch_ptr[dev] = (char*)ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return 0;
+}
+
+// Lays out the workspace of one single-image periodic problem (the fields of
+// make_plan with nitems = 1) from base; returns the bytes used.  With base
+// null only the size is computed.
+static size_t carve_plan(const PlanKey& key, char* base, Plan& pl) {
+  size_t off = 0;
+  auto take = [&](auto** p, size_t n) {
+    using T = std::remove_reference_t<decltype(**p)>;
+    off = (off + 255) & ~size_t(255);
+    if (base) *p = (T*)(base + off);
+    off += std::max<size_t>(n, 1) * sizeof(T);
+  };
+  const size_t nF = (size_t)key.NY * key.NX, nS = (size_t)key.ny * key.nx;
+  const size_t nSpec = (size_t)spec_elems(key.NY, key.NX);
+  take(&pl.grad, nF);
+  take(&pl.d, nF);
+  take(&pl.Af, nS * key.p);
+  take(&pl.Ad, nS * key.p);
+  take(&pl.Af2, nS * key.p);
+  take(&pl.spec, nSpec * key.p);
+  take(&pl.khat, nSpec * key.p);
+  take(&pl.knyq, (size_t)key.NY * key.p);
+  take(&pl.tw_row, (size_t)key.NX);
+  take(&pl.tw_col, (size_t)key.NY);
+  take(&pl.part, part_capacity(key));
+  take(&pl.counter, 1);
+  take(&pl.st, 1);
+  take(&pl.btab, (size_t)kMaxP);
+  return off;
 }
 
 static int cached_plan(const PlanKey& key, hipStream_t s, Plan** out) {
@@ -812,7 +871,8 @@ static int to_problem(const sgp_problem* pr, Problem& pb) {
 // caller), otherwise the solver owns it.
 static int create_items(int kind, const std::vector<Problem>& items, const std::vector<float*>& fs,
                         const std::vector<const float*>& f0s, const sgp_params* prm_in, void* stream,
-                        bool cached, std::unique_ptr<sgp_solver>& out, bool shared = false) {
+                        bool cached, std::unique_ptr<sgp_solver>& out, bool shared = false,
+                        Plan* ext = nullptr) {
   auto S = std::make_unique<sgp_solver>();
   S->t0 = std::chrono::steady_clock::now();
   if (prm_in) S->prm = *prm_in;
@@ -844,7 +904,10 @@ static int create_items(int kind, const std::vector<Problem>& items, const std::
   S->fs = fs;
   S->user = (hipStream_t)stream;
   // order the internal stream after the caller's stream
-  if (shared) {
+  if (ext) {  // the static workspace: every launch goes on the caller's stream
+    S->s = S->user;
+    S->own_stream = false;
+  } else if (shared) {
     SharedStream* ss;
     if ((rc = shared_stream(dev, &ss))) return rc;
     S->s = ss->s;
@@ -861,7 +924,9 @@ static int create_items(int kind, const std::vector<Problem>& items, const std::
   }
   PlanKey key{kind, pb.p, pb.NY, pb.NX, pb.ny, pb.nx, pb.oy, pb.ox, pb.boundary ? 1 : 0, dev};
   key.nitems = n;
-  if (cached) {
+  if (ext) {
+    S->pl = ext;
+  } else if (cached) {
     if ((rc = cached_plan(key, S->s, &S->pl))) return rc;
   } else {
     if ((rc = make_plan(key, S->s, S->owned))) return rc;
@@ -1078,6 +1143,55 @@ static int one_shot(int kind, const Problem& pb, const sgp_params* prm, float* f
   return report(S.get(), rep);
 }
 
+// sgp_deconv on the static workspace: no device or pinned-host allocation,
+// no graph (every iteration is launched on the caller's stream), no
+// internal stream.
+static int deconv_noalloc(const float* g, const float* psf, const float* b_map, float b_const, int ny, int nx,
+                          const sgp_params* prm, float* f, sgp_report* rep, void* stream) {
+  Problem pb;
+  pb.g = g; pb.psf = psf; pb.bmap = b_map; pb.b[0] = b_const;
+  pb.p = 1; pb.ny = pb.NY = ny; pb.nx = pb.NX = nx;
+  int rc;
+  if ((rc = check_problem(pb))) return rc;
+  if (prm && prm->trace) return fail(SGP_E_INVALID_ARG, "sgp_deconv_noalloc keeps no trace (prm->trace must be NULL)");
+  int dev;
+  if ((rc = current_device(&dev))) return rc;
+  PlanKey key{KIND_SGP, 1, ny, nx, ny, nx, 0, 0, 0, dev};
+  Plan sizing;
+  sizing.external = true;
+  const size_t need = carve_plan(key, nullptr, sizing);
+  if (need > kScratchBytes)
+    return fail(SGP_E_INVALID_ARG, "a " + std::to_string(ny) + " x " + std::to_string(nx) + " problem needs " +
+                                       std::to_string((need + (1 << 20) - 1) >> 20) + " MiB of workspace; the static "
+                                       "workspace of sgp_deconv_noalloc holds " +
+                                       std::to_string(kScratchBytes >> 20) + " MiB (about 2 million pixels)");
+  std::lock_guard<std::mutex> lock(g_scratch_mutex);
+  char* base = nullptr;
+  if ((rc = scratch_address(dev, &base))) return rc;
+  Plan pl;
+  pl.external = true;
+  pl.key = key;
+  carve_plan(key, base, pl);
+  DevState host_state;
+  pl.host_st = &host_state;
+  hipStream_t s = (hipStream_t)stream;
+  // the workspace keeps the previous call's contents: the reduction counter
+  // must start at zero (every other buffer is written before it is read)
+  SGP_HIP(hipMemsetAsync(pl.counter, 0, sizeof(unsigned), s));
+  launch_twiddle(pl.tw_row, nx, s);
+  launch_twiddle(pl.tw_col, ny, s);
+  SGP_HIP(hipGetLastError());
+  std::unique_ptr<sgp_solver> S;
+  rc = create_items(KIND_SGP, std::vector<Problem>{pb}, std::vector<float*>{f},
+                    std::vector<const float*>{prm ? prm->f0 : nullptr}, prm, stream, false, S, false, &pl);
+  if (rc) return rc;
+  S->use_graph = false;
+  if ((rc = step(S.get(), S->prm.max_iter, nullptr))) return rc;
+  rc = report(S.get(), rep);
+  S->pl = nullptr;
+  return rc;
+}
+
 static int apply_operator(const float* psf, const float* x, int ny, int nx, int adjoint, float* out,
                           void* stream) {
   if (!psf || !x || !out) return fail(SGP_E_INVALID_ARG, "null pointer");
@@ -1277,6 +1391,11 @@ static int stack(int kind, const float* g, const float* psf, const float* b_map,
   int rc = to_problem(&pr, pb);
   if (rc) return rc;
   return one_shot(kind, pb, prm, f, rep, stream);
+}
+
+int sgp_deconv_noalloc(const float* g, const float* psf, const float* b_map, float b_const, int ny, int nx,
+                       const sgp_params* prm, float* f, sgp_report* rep, void* hip_stream) {
+  SGP_GUARD(deconv_noalloc(g, psf, b_map, b_const, ny, nx, prm, f, rep, hip_stream));
 }
 
 int sgp_multi_deconv(const float* g, const float* psf, const float* b_map, const float* b_const, int p,
