@@ -47,6 +47,12 @@ documented choice, shared with the HIP library by specification, not by code):
 * multi-image scaling D = clip(f, L1, L2) / p;
 * flat start = mean_j sum_S (g_j - b_j) / |S|, put on R only;
 * discrepancy stop at the first k with 2 J / (p |S|) <= b_D; KL summed over S;
+* reconstruction-error stop (Sect. 3.3, needs the true object): rho^(k) is
+  taken for k = 0, 1, ... as each iterate is formed; at the first k with
+  rho^(k) > rho^(k-1) the run returns f^(k-1), the minimum (for SGP this
+  rule is tested after the discrepancy and convergence rules of the same
+  iterate; for RL and OSEM before them, since the error is known before the
+  iterate's KL);
 * backtracking capped at ``max_backtracks``; d = 0 stops as stationary;
 * BB sums taken over pixels with D > 0 (D^{-1} is undefined off R);
 * relaxed RL for several images or a boundary problem: Eq. (RL1) is written
@@ -292,8 +298,19 @@ class Problem:
         k = 0
         if (prm.stop & STOP_DISCREPANCY) and self.discrepancy(J) <= prm.disc_target:
             return f, dict(iters=0, kl=J, history=hist, reason=REASON_DISCREPANCY)
+        rho = rel_error(f, prm.f_true) if rmse_active(prm) else None
         while k < n_iter:
-            f = self.rl_step(f, prm.rl_alpha)
+            f_new = self.rl_step(f, prm.rl_alpha)
+            # Sect. 3.3: the error of an iterate is known as soon as it is
+            # formed; once it grows, the previous iterate (the minimum) is
+            # returned
+            if rho is not None:
+                rho_new = rel_error(f_new, prm.f_true)
+                if rho_new > rho:
+                    reason = REASON_RMSE
+                    break
+                rho = rho_new
+            f = f_new
             Jn = self.kl(f)
             k += 1
             hist.append(Jn)
@@ -332,8 +349,16 @@ class Problem:
         if (prm.stop & STOP_DISCREPANCY) and self.discrepancy(J) <= prm.disc_target:
             return f, dict(iters=0, kl=J, history=hist, reason=REASON_DISCREPANCY)
         reason = REASON_MAXITER
+        rho = rel_error(f, prm.f_true) if rmse_active(prm) else None
         while k < n_iter:
-            f = self.osem_cycle(f)
+            f_new = self.osem_cycle(f)
+            if rho is not None:  # Sect. 3.3, as in rl()
+                rho_new = rel_error(f_new, prm.f_true)
+                if rho_new > rho:
+                    reason = REASON_RMSE
+                    break
+                rho = rho_new
+            f = f_new
             Jn = self.kl(f)
             k += 1
             hist.append(Jn)
@@ -414,7 +439,7 @@ class Problem:
         if (prm.stop & STOP_DISCREPANCY) and self.discrepancy(J) <= prm.disc_target:
             return f, dict(iters=0, kl=J, history=hist, log=log, L1=L1, L2=L2,
                            reason=REASON_DISCREPANCY, alpha=alpha)
-        rmse_prev = np.inf
+        rho = rel_error(f, prm.f_true) if rmse_active(prm) else None
         while k < prm.max_iter:
             if force_alpha is not None:
                 alpha = force_alpha
@@ -457,7 +482,7 @@ class Problem:
                             J=J_new, a=a_num, c1=c1, c2=c2, e=e_den,
                             a1=a1, a2=a2, br1=br1, br2=br2, alt=alt, tau=tau,
                             alpha_next=alpha_next))
-            J_prev = J
+            J_prev, f_prev = J, f
             f, J, G, alpha = f_new, J_new, G_new, alpha_next
             k += 1
             hist.append(J)
@@ -467,13 +492,18 @@ class Problem:
             if (prm.stop & STOP_CONV) and converged(J, J_prev, prm.tol):
                 reason = REASON_CONV
                 break
-            if (prm.stop & STOP_RMSE) and prm.f_true is not None:
-                ft = np.asarray(prm.f_true, dtype=np.float64)
-                rmse = np.linalg.norm(f - ft) / np.linalg.norm(ft)
-                if rmse > rmse_prev:
+            if rho is not None:
+                # Sect. 3.3: stop when the reconstruction error has reached
+                # its minimum, i.e. at its first increase, and return the
+                # iterate of the minimum (the one before the step just taken)
+                rho_new = rel_error(f, prm.f_true)
+                if rho_new > rho:
                     reason = REASON_RMSE
+                    f, J, k = f_prev, J_prev, k - 1
+                    hist.pop()
+                    log.pop()
                     break
-                rmse_prev = rmse
+                rho = rho_new
         return f, dict(iters=k, kl=J, history=hist, log=log, L1=L1, L2=L2,
                        reason=reason, alpha=alpha)
 
@@ -481,6 +511,17 @@ class Problem:
 def converged(J_new, J_old, tol):
     """Eq. (convergence): |J(f^(k+1)) - J(f^(k))| <= tol J(f^(k))."""
     return abs(J_new - J_old) <= tol * J_old
+
+
+def rel_error(f, f_true):
+    """Sect. 3.3: relative reconstruction error rho = ||f - f~||_2 / ||f~||_2."""
+    ft = np.asarray(f_true, dtype=np.float64)
+    return float(np.linalg.norm(f - ft) / np.linalg.norm(ft))
+
+
+def rmse_active(prm):
+    """The reconstruction-error stop is on (it needs the true object)."""
+    return bool(prm.stop & STOP_RMSE) and prm.f_true is not None
 
 
 def steplength_update(alpha, tau, Q, k, a_num, c1, c2, e_den, prm: Params):
