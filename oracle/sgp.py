@@ -27,6 +27,7 @@ deconvolution methods for astronomical imaging: algorithms and IDL-GPU codes"
 * flux-constrained projection ............... Sect. 2 intro (constraint set named, algorithm
                                               not given); derived here from the KKT conditions
 * relaxed RL ................................ Sect. 1, Eq. (RL1) (multiplicative relaxation)
+* linearly relaxed RL ....................... Sect. 1, Eq. (RL2) with the Armijo rule
 
 Every array is float64.  Inputs given in float32 are promoted.  The iteration
 is written step by step in the paper's order and notation; library primitives
@@ -123,6 +124,7 @@ class Params:
     max_backtracks: int = 40
     f_true: np.ndarray | None = None
     rl_alpha: float = 1.0   # exponent of Eq. (RL1); 1 is RL
+    rl_lambda_cap: float = 10.0  # Eq. (RL2) line search: largest step tried (with the nonnegativity bound)
 
 
 def _as_stack(a, p=None):
@@ -324,6 +326,68 @@ class Problem:
                 break
             J = Jn
         return f, dict(iters=k, kl=J, history=hist, reason=reason)
+
+    def rl_linear(self, f0, n_iter, params: Params | None = None):
+        """Linear relaxation of RL, Eq. (RL2): f <- f + lam d along the RL
+        direction d = -(M_R / w) o f o grad J (the RL step minus f), with
+        lam >= 1 chosen by the Armijo rule (Sect. 1 names a line search along
+        this direction by the Armijo rule; the rule and its test are those of
+        Algorithm 1, steps 4-5).  Reading: the largest step tried is
+        lam_max = min(rl_lambda_cap, min over d_i < 0 of f_i / (-d_i)), the
+        largest keeping f >= 0; candidates lam_max, theta lam_max, ... while
+        above 1, then lam = 1, the RL step itself, taken when no larger
+        candidate passes (it never increases J).  With the same stopping rules
+        as rl()."""
+        prm = params or Params(max_iter=n_iter)
+        f = f0.copy()
+        J = self.kl(f)
+        hist = [J]
+        lams = []
+        k = 0
+        reason = REASON_MAXITER
+        if (prm.stop & STOP_DISCREPANCY) and self.discrepancy(J) <= prm.disc_target:
+            return f, dict(iters=0, kl=J, history=hist, lam=lams, reason=REASON_DISCREPANCY)
+        rho = rel_error(f, prm.f_true) if rmse_active(prm) else None
+        while k < n_iter:
+            G = self.grad(f)
+            d = -self.invw * f * G
+            gd = float(np.sum(G * d))
+            if gd == 0.0:
+                reason = REASON_STATIONARY
+                break
+            neg = d < 0
+            lam_max = prm.rl_lambda_cap
+            if neg.any():
+                lam_max = min(lam_max, float(np.min(f[neg] / -d[neg])))
+            lam = lam_max
+            while lam > 1.0:
+                f_new = np.maximum(0.0, f + lam * d)
+                J_new = self.kl(f_new)
+                if J_new <= J + prm.beta * lam * gd:
+                    break
+                lam *= prm.theta
+            if lam <= 1.0:
+                lam = 1.0
+                f_new = np.maximum(0.0, f + d)
+                J_new = self.kl(f_new)
+            if rho is not None:  # Sect. 3.3, as in rl()
+                rho_new = rel_error(f_new, prm.f_true)
+                if rho_new > rho:
+                    reason = REASON_RMSE
+                    break
+                rho = rho_new
+            J_prev = J
+            f, J = f_new, J_new
+            k += 1
+            hist.append(J)
+            lams.append(lam)
+            if (prm.stop & STOP_DISCREPANCY) and self.discrepancy(J) <= prm.disc_target:
+                reason = REASON_DISCREPANCY
+                break
+            if (prm.stop & STOP_CONV) and converged(J, J_prev, prm.tol):
+                reason = REASON_CONV
+                break
+        return f, dict(iters=k, kl=J, history=hist, lam=lams, reason=reason)
 
     # -------------------------------------------------------------- OSEM
     def osem_weight(self, j):
