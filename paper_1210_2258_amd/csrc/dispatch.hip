@@ -118,6 +118,10 @@ void launch_resume(DevState* st, int n, int nitems, hipStream_t s) {
   hipLaunchKernelGGL(resume_kernel, dim3((nitems + 63) / 64), dim3(64), 0, s, st, n, nitems);
 }
 
+void launch_zero(unsigned* c, int n, hipStream_t s) {
+  hipLaunchKernelGGL(zero_kernel, dim3((n + 255) / 256), dim3(256), 0, s, c, n);
+}
+
 void launch_twiddle(float2* tw, int L, hipStream_t s) {
   hipLaunchKernelGGL(twiddle_kernel, dim3((L + 255) / 256), dim3(256), 0, s, tw, L);
 }

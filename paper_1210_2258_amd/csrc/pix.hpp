@@ -296,6 +296,13 @@ __global__ void resume_kernel(DevState* st, int n, int nitems) {
   }
 }
 
+// Clears n counters (a fill kernel rather than a memset node, so that the
+// calls that may run under a caller's graph capture record kernels only).
+__global__ void zero_kernel(unsigned* c, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) c[i] = 0u;
+}
+
 // exp(-2 pi i m / L) for m < L, in double precision, rounded to float.
 __global__ void twiddle_kernel(float2* tw, int L) {
   const int m = blockIdx.x * blockDim.x + threadIdx.x;

@@ -1176,8 +1176,9 @@ static int deconv_noalloc(const float* g, const float* psf, const float* b_map, 
   pl.host_st = &host_state;
   hipStream_t s = (hipStream_t)stream;
   // the workspace keeps the previous call's contents: the reduction counter
-  // must start at zero (every other buffer is written before it is read)
-  SGP_HIP(hipMemsetAsync(pl.counter, 0, sizeof(unsigned), s));
+  // must start at zero (every other buffer is written before it is read);
+  // cleared by a fill kernel, so the call records no memset node
+  launch_zero(pl.counter, 1, s);
   launch_twiddle(pl.tw_row, nx, s);
   launch_twiddle(pl.tw_col, ny, s);
   SGP_HIP(hipGetLastError());
