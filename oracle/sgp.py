@@ -336,8 +336,12 @@ class Problem:
         lam_max = min(rl_lambda_cap, min over d_i < 0 of f_i / (-d_i)), the
         largest keeping f >= 0; candidates lam_max, theta lam_max, ... while
         above 1, then lam = 1, the RL step itself, taken when no larger
-        candidate passes (it never increases J).  With the same stopping rules
-        as rl()."""
+        candidate passes (it never increases J).  A step taken at the
+        nonnegativity bound sets the pixels that bound it to exactly 0, as
+        exact arithmetic does (rounding would leave them at a tiny positive
+        or negative fraction of their value, alive or clipped by chance, and
+        a live one would bound every later step).  With the same stopping
+        rules as rl()."""
         prm = params or Params(max_iter=n_iter)
         f = f0.copy()
         J = self.kl(f)
@@ -356,12 +360,15 @@ class Problem:
                 reason = REASON_STATIONARY
                 break
             neg = d < 0
-            lam_max = prm.rl_lambda_cap
-            if neg.any():
-                lam_max = min(lam_max, float(np.min(f[neg] / -d[neg])))
+            ratio = np.full(f.shape, np.inf)
+            ratio[neg] = f[neg] / -d[neg]
+            bound = float(ratio.min())
+            lam_max = min(prm.rl_lambda_cap, bound)
             lam = lam_max
             while lam > 1.0:
                 f_new = np.maximum(0.0, f + lam * d)
+                if lam == bound:
+                    f_new[ratio <= bound] = 0.0
                 J_new = self.kl(f_new)
                 if J_new <= J + prm.beta * lam * gd:
                     break

@@ -66,6 +66,11 @@ def pin_steps(P, n=8):
         assert lam >= 1.0
         assert fk1.min() >= 0.0
         np.testing.assert_allclose(fk1, np.maximum(0.0, f + lam * d), rtol=0, atol=1e-12 * f.max())
+        # a step at the nonnegativity bound zeroes the pixel that bounds it
+        ng = d < 0
+        if ng.any() and lam == float(np.min(f[ng] / -d[ng])):
+            i = np.argmin(np.where(ng, f / np.where(ng, -d, 1.0), np.inf))
+            assert fk1.flat[i] == 0.0
         Jn = _kl_independent(P, fk1)
         assert Jn <= J + prm.beta * lam * gd + 1e-9 * J, (k, lam)
         neg = d < 0
