@@ -90,8 +90,8 @@ def parse():
                     help="keep tile variant 0 instead of timing the tile variants per FFT length")
     ap.add_argument("--tiles", type=int, nargs=2, metavar=("ROW", "COL"),
                     help="tile variants of the main image size, set instead of tuned (as in profiled runs)")
-    ap.add_argument("--sweep", action="store_true",
-                    help="also run the Fourier re-binning size sweep 256..2048 (RL and SGP, GPU and oracle)")
+    ap.add_argument("--no-sweep", action="store_true",
+                    help="skip the Fourier re-binning size sweep 256..2048 (RL and SGP, GPU and oracle)")
     return ap.parse_args()
 
 
@@ -542,7 +542,7 @@ def main():
         out["mosaic_2048"] = mosaic_leg(torch, m, w, g, psf, f_full, None if args.no_autotune else tiles)
     if not args.no_mall and args.size == 2048:
         out["beyond_mall_4x2048"] = beyond_mall_leg(torch, m, g, psf, b)
-    if args.sweep:
+    if not args.no_sweep:
         out["rebin_sweep"] = rebin_sweep(torch, m, with_oracle=not args.no_cpu)
     if not args.no_configs:
         out["configs"] = config_rates(torch, m, 100, 10, not args.no_cpu)

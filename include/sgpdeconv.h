@@ -65,11 +65,18 @@ extern "C" {
 #define SGP_STOP_FIXED 1           /* max_iter iterations */
 #define SGP_STOP_CONV 2            /* Eq. (convergence): |J(k+1) - J(k)| <= tol J(k) */
 #define SGP_STOP_DISCREPANCY 4     /* Eq. (discrepancy): 2 J / (p ny nx) <= disc_target */
+#define SGP_STOP_RMSE 8            /* Sect. 3.3, minimum of the relative reconstruction error
+                                      rho = ||f - f_true||_2 / ||f_true||_2 (simulation studies; needs
+                                      f_true): rho is evaluated as each iterate is formed, over the
+                                      object domain, and at its first increase the previous iterate,
+                                      the minimum, is returned (with its KL and iteration count).
+                                      Single problems only (not sgp_batch_deconv / the mosaic). */
 
 /* stop reasons reported in sgp_report.stop_reason */
 #define SGP_REASON_MAXITER 0
 #define SGP_REASON_CONV 1
 #define SGP_REASON_DISCREPANCY 2
+#define SGP_REASON_RMSE 3
 #define SGP_REASON_STATIONARY 4
 #define SGP_REASON_ARMIJO 5
 #define SGP_REASON_NUMERIC 6
@@ -117,6 +124,16 @@ typedef struct sgp_params {
                             (multipleRL), (boundaryRL); in (0, 8], default 1 (plain RL;
                             the paper cites convergence for a < 2).  Other values are
                             rejected with SGP_E_INVALID_ARG, as is a != 1 for SGP / OSEM. */
+  const float* f_true;   /* SGP_STOP_RMSE: the true object, device pointer [NY][NX] (the
+                            object domain; [ny][nx] for periodic problems); else unused */
+  int rl_line_search;    /* RL only: 1 = the linear relaxation of Sect. 1 Eq. (RL2),
+                            f <- f + lam d along the RL direction d = -(M_R / w) o f o grad J
+                            (the RL step minus f) with lam >= 1 by the Armijo rule of
+                            Algorithm 1 (beta, theta): the first step tried is the largest
+                            keeping f >= 0, at most rl_lambda_cap, then theta times the last
+                            while above 1; lam = 1 (the RL step) when none passes.  0 (default):
+                            the RL iteration.  Not with rl_alpha != 1. */
+  double rl_lambda_cap;  /* largest step of that line search, >= 1 (default 10) */
 } sgp_params;
 
 typedef struct sgp_report {

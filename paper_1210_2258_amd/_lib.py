@@ -20,9 +20,10 @@ TRACE_COLS = 20
 TRACE_FIELDS = ["k", "alpha", "gd", "backtracks", "lam", "J", "a", "c1", "c2", "e",
                 "a1", "a2", "br1", "br2", "alt", "tau", "alpha_next", "flux_mu"]
 
-STOP_FIXED, STOP_CONV, STOP_DISCREPANCY = 1, 2, 4
+STOP_FIXED, STOP_CONV, STOP_DISCREPANCY, STOP_RMSE = 1, 2, 4, 8
 INIT_FLAT, INIT_ZERO, INIT_DATA, INIT_USER, INIT_WARM = 0, 1, 2, 3, 4
-REASONS = {0: "maxiter", 1: "convergence", 2: "discrepancy", 4: "stationary", 5: "armijo", 6: "numeric"}
+REASONS = {0: "maxiter", 1: "convergence", 2: "discrepancy", 3: "rmse", 4: "stationary", 5: "armijo",
+           6: "numeric"}
 
 
 class SgpError(RuntimeError):
@@ -40,7 +41,8 @@ class _Params(ctypes.Structure):
         ("m_alpha", ctypes.c_int), ("n_bb2_only", ctypes.c_int), ("auto_bounds", ctypes.c_int),
         ("L1", ctypes.c_double), ("L2", ctypes.c_double), ("flux_constraint", ctypes.c_int),
         ("flux", ctypes.c_double), ("sigma_R", ctypes.c_double), ("max_backtracks", ctypes.c_int),
-        ("trace", ctypes.c_void_p), ("rl_alpha", ctypes.c_double),
+        ("trace", ctypes.c_void_p), ("rl_alpha", ctypes.c_double), ("f_true", ctypes.c_void_p),
+        ("rl_line_search", ctypes.c_int), ("rl_lambda_cap", ctypes.c_double),
     ]
 
 
@@ -146,7 +148,7 @@ def default_params() -> dict:
     lib = load()
     p = _Params()
     lib.sgp_params_init(ctypes.byref(p))
-    return {name: getattr(p, name) for name, _ in _Params._fields_ if name not in ("f0", "trace")}
+    return {name: getattr(p, name) for name, _ in _Params._fields_ if name not in ("f0", "trace", "f_true")}
 
 
 def _make_params(kw: dict, trace_rows: int | None, fshape=None):
@@ -155,11 +157,11 @@ def _make_params(kw: dict, trace_rows: int | None, fshape=None):
     lib.sgp_params_init(ctypes.byref(p))
     keep = []
     for k, v in kw.items():
-        if k == "f0":
-            _check_dev(v, "f0")
+        if k in ("f0", "f_true"):
+            _check_dev(v, k)
             if fshape is not None:
-                _check_shape(v, fshape, "f0")
-            p.f0 = v.data_ptr()
+                _check_shape(v, fshape, k)
+            setattr(p, k, v.data_ptr())
             keep.append(v)
         elif k == "trace":
             continue
@@ -269,7 +271,9 @@ def sgp_deconv_noalloc(g, psf, b=0.0, *, f, b_map=None, stream=None, **params):
 
 def rl_deconv(g, psf, b=0.0, *, b_map=None, f=None, stream=None, trace=False, **params):
     """Richardson-Lucy single-image deconvolution (Eq. (RL); with rl_alpha != 1
-    the multiplicative relaxation of Eq. (RL1)); returns (f, report)."""
+    the multiplicative relaxation of Eq. (RL1); with rl_line_search=1 the
+    linear relaxation of Eq. (RL2), an Armijo line search along the RL
+    direction with steps up to rl_lambda_cap); returns (f, report)."""
     return _solve_single(load().rl_deconv, g, psf, b, b_map, f, stream, trace, params)
 
 

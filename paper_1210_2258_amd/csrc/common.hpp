@@ -57,6 +57,16 @@ struct DevState {
   int f_pending;     // an accepted step waits for f += lam d (taken by the
                      // gradient pass, also after a stop; cleared after it)
   int spec_ok;       // lambda = 1 accepted: the update the A d pass made for it stands
+  // reconstruction-error stop (Sect. 3.3)
+  double rms_prev;   // rho of the last iterate evaluated
+  int rms_k;         // iteration count at which rho was last evaluated (-1: none)
+  int rms_back;      // the run ended past the minimum: the previous iterate is returned
+  // linear relaxation of RL, Eq. (RL2): the SGP iteration with alpha = 1,
+  // D = (M_R / w) f, no steplength rule, and an Armijo search from the
+  // largest step keeping f >= 0 down to 1
+  int rl2;
+  double lam_cap;    // largest step tried
+  double lam_bound;  // largest step keeping f >= 0 (min over d < 0 of f / -d)
 };
 
 // Kernel arguments (passed by value).
@@ -86,6 +96,7 @@ struct Args {
   const float* psf;      // [p][NY][NX]
   float* aux;            // [p][NY][NX] scratch field (boundary weights)
   const float* src;      // generic input field
+  const float* ftrue;    // [NY][NX] true object of the reconstruction-error stop, or null
   const float2* tw_row;  // twiddles for length NX
   const float2* tw_col;  // twiddles for length NY
   double* part;          // reduction partials [slot][nblk]
@@ -154,6 +165,10 @@ enum PixOp {
   PIX_FSCALE,       // scale f to the prescribed flux
   PIX_CHOOSE,       // keep the given start or fall back to the flat one (lower KL wins)
   PIX_INVWJ,        // boundary OSEM: per-image weights M_R / alpha_j from aux
+  PIX_FCOPY,        // reconstruction-error stop: f -> d (the iterate before an update)
+  PIX_RMSE,         // reconstruction-error stop: rho of the current f, stop at its first increase
+  PIX_RL2MAX,       // Eq. (RL2): largest step keeping f + lam d >= 0, and the step candidates
+  PIX_RL2ZERO,      // Eq. (RL2): a step at that bound zeroes the pixels that bound it
   PIX_NOPS
 };
 

@@ -96,6 +96,10 @@ void launch_pix(int op, dim3 grid, const Args& a, hipStream_t s) {
     SGP_PIX_CASE(PIX_FSCALE)
     SGP_PIX_CASE(PIX_CHOOSE)
     SGP_PIX_CASE(PIX_INVWJ)
+    SGP_PIX_CASE(PIX_FCOPY)
+    SGP_PIX_CASE(PIX_RMSE)
+    SGP_PIX_CASE(PIX_RL2MAX)
+    SGP_PIX_CASE(PIX_RL2ZERO)
 #undef SGP_PIX_CASE
     default: break;
   }

@@ -48,7 +48,9 @@ __host__ __device__ inline void fin_armijo(DevState* st, const double* dJ, int m
       st->reason = REASON_NUMERIC;
       return;
     }
-    if (dJ[m] <= st->beta * lam * st->gd) {
+    // (the linear relaxation of RL takes its last candidate, lambda = 1,
+    // the RL step, without the test)
+    if (dJ[m] <= st->beta * lam * st->gd || (st->rl2 && mm == st->max_backtracks)) {
       st->lam = lam;
       st->nback = mm;
       st->f_pending = 1;
@@ -72,6 +74,7 @@ __host__ __device__ inline bool armijo_needs_more(const DevState* st, const doub
     if (mm > st->max_backtracks) break;
     if (!__builtin_isfinite(dJ[m])) return false;
     if (dJ[m] <= st->beta * st->lam_tab[mm] * st->gd) return false;
+    if (st->rl2 && mm == st->max_backtracks) return false;
   }
   return m0 + n <= st->max_backtracks;
 }
@@ -97,7 +100,9 @@ __host__ __device__ inline void fin_update(DevState* st, double Jn) {
   } else if ((st->stop & STOP_CONV) && fabs(Jn - st->Jprev) <= st->tol * st->Jprev) {
     st->done = 1;
     st->reason = REASON_CONV;
-  } else if (st->k >= st->max_iter) {
+  } else if (st->k >= st->max_iter && !(st->stop & STOP_RMSE)) {
+    // (with the reconstruction-error stop the last iterate is tested first:
+    // fin_rmse ends the run)
     st->done = 1;
     st->reason = REASON_MAXITER;
   }
@@ -135,6 +140,11 @@ __host__ __device__ inline BBInfo bb_rule(DevState* st, double a, double c1, dou
 }
 
 __host__ __device__ inline void fin_bb(DevState* st, double a, double c1, double c2, double e) {
+  if (st->rl2) {  // Eq. (RL2): the RL direction, no steplength rule
+    st->alpha = 1.0;
+    if (st->k >= st->k_stop) st->pause = 1;
+    return;
+  }
   const BBInfo r = bb_rule(st, a, c1, c2, e);
   double* tr = trace_row(st, st->k - 1);
   if (tr) {
@@ -215,6 +225,55 @@ __host__ __device__ inline void fin_rl(DevState* st, double J) {
   }
   st->Jprev = Jprev;
   st->J = J;
+}
+
+// Sect. 3.3, reconstruction error: t = {sum (f - f~)^2, sum f~^2} of the
+// iterate just formed.  At setup (first) rho^(0) is recorded.  Afterwards an
+// increase over the previous value ends the run, and the previous iterate
+// (kept by PIX_FCOPY) is returned: its iteration count is one less, and its
+// KL is the one held before the step (SGP: Jprev; RL / OSEM have not yet
+// formed the KL of the new iterate, so J already belongs to the previous).
+__host__ __device__ inline void fin_rmse(DevState* st, const double* t, bool first, bool sgp) {
+  const double rho = t[1] > 0.0 ? sqrt(t[0] / t[1]) : sqrt(t[0]);
+  st->rms_k = st->k;
+  if (first) {
+    st->rms_prev = rho;
+    return;
+  }
+  if (!__builtin_isfinite(rho)) {
+    st->done = 1;
+    st->reason = REASON_NUMERIC;
+  } else if (rho > st->rms_prev) {
+    st->done = 1;
+    st->reason = REASON_RMSE;
+    st->rms_back = 1;
+    st->k -= 1;
+    if (sgp) st->J = st->Jprev;
+  } else {
+    st->rms_prev = rho;
+    if (sgp && st->k >= st->max_iter) {  // the cap, deferred by fin_update
+      st->done = 1;
+      st->reason = REASON_MAXITER;
+    }
+  }
+}
+
+// Eq. (RL2) line search: t = min over d_i < 0 of f_i / (-d_i), the largest
+// step keeping f + lam d >= 0 (infinite when no d_i < 0).  Candidates
+// lam_max = min(t, cap), theta lam_max, ... while above 1, then 1; the
+// Armijo test runs over them in that order (max_backtracks = index of the
+// final 1, which fin_armijo accepts without the test).
+__host__ __device__ inline void fin_rl2max(DevState* st, double t) {
+  st->lam_bound = t;
+  double lam = fmin(st->lam_cap, t);
+  int m = 0;
+  while (lam > 1.0 && m < kMaxCand - 1) {
+    st->lam_tab[m++] = lam;
+    lam *= st->theta;
+  }
+  st->lam_tab[m] = 1.0;
+  if (m + 1 < kMaxCand) st->lam_tab[m + 1] = st->theta;  // read by the A d pass, never used
+  st->max_backtracks = m;
 }
 
 // Flux projection (constraint set {x >= 0, sum x = c} of Sect. 2, projection

@@ -359,7 +359,9 @@ __device__ __forceinline__ float row_point(const Args& a, const RowScal& sc, int
     const float dv = dir_value(in.c[3], in.c[1], w, sc);
     const float zf = w > 0.f ? -v : 0.f;
     a.grad[pix] = in.c[1] + zf;
-    const float fn = in.c[3] + sc.lam * dv;
+    // (f + lam d >= 0 holds exactly for lam <= 1; the clamp only guards the
+    // rounding of the longer steps of the linear relaxation of RL)
+    const float fn = fmaxf(0.f, in.c[3] + sc.lam * dv);
     a.f[pix] = fn;
     const double s = sc.lamd * (double)dv;
     const double z = (double)zf;

@@ -13,7 +13,8 @@ constexpr int kArmCand = 8;  // candidates per Armijo pass: theta^2 .. theta^9, 
 __host__ __device__ constexpr int pix_nslots(int op) {
   return op == PIX_VALIDATE ? 3 : op == PIX_PSFSUM ? 3 : op == PIX_FLATSUM ? 2 :
          op == PIX_ARMIJO ? kArmCand :
-         op == PIX_FLUX_INIT ? 5 : op == PIX_FLUX_NEWTON ? 3 : op == PIX_FSUM ? 1 : 0;
+         op == PIX_FLUX_INIT ? 5 : op == PIX_FLUX_NEWTON ? 3 : op == PIX_FSUM ? 1 :
+         op == PIX_RMSE ? 2 : op == PIX_RL2MAX ? 1 : 0;
 }
 
 struct PixKinds {
@@ -22,6 +23,7 @@ struct PixKinds {
     if (op == PIX_VALIDATE) return s == 1 ? RED_SUM : RED_MIN;  // min g, #non-finite, min b
     if (op == PIX_PSFSUM) return s == 1 ? RED_MIN : RED_SUM;    // sum, min, #non-finite
     if (op == PIX_FLUX_INIT) return s == 2 ? RED_MIN : RED_SUM;
+    if (op == PIX_RL2MAX) return RED_MIN;
     return RED_SUM;
   }
 };
@@ -76,7 +78,19 @@ __global__ __launch_bounds__(kPixThreads) void pix_kernel(Args a_in) {
   const Args a = batch_view(a_in);
   constexpr int NS = pix_nslots(OP);
   DevState* st = a.st;
-  if (a.iter && (st->done || st->pause)) return;
+  if constexpr (OP == PIX_RMSE) {
+    // once per formed iterate: also right after the update that completed a
+    // stepping call's last iteration (the solver has paused by then), never
+    // again for the same iteration count
+    if (a.iter && (st->done || st->rms_k == st->k)) return;
+  } else if constexpr (OP == PIX_RL2ZERO) {
+    // before the update of f, which is also taken after a stop (f_pending),
+    // and only for a step at the nonnegativity bound
+    if (a.iter && ((st->done && !st->f_pending) || st->pause)) return;
+    if (!(st->lam >= st->lam_bound)) return;
+  } else {
+    if (a.iter && (st->done || st->pause)) return;
+  }
   if constexpr (OP == PIX_ARMIJO) {
     // Armijo test of lambda = 1 and theta (sums of ROW_AD) taken by every
     // workgroup; the first commits the outcome unless more candidates are
@@ -224,6 +238,37 @@ __global__ __launch_bounds__(kPixThreads) void pix_kernel(Args a_in) {
     }
   } else if constexpr (OP == PIX_FSUM) {
     for (long long i = i0; i < nF; i += stride) acc[0] += a.f[i];
+  } else if constexpr (OP == PIX_RL2MAX) {
+    // d of the direction pass (the same function: alpha = 1, L1 = 0,
+    // L2 huge make it the RL step minus f)
+    const RowScal sc = row_scalars<ROW_DIR>(st, 0);
+    for (long long i = i0; i < nF; i += stride) {
+      const float f = a.f[i];
+      const float w = a.invw ? a.invw[i] : a.invw_s;
+      const float dv = dir_value(f, a.grad[i], w, sc);
+      if (dv < 0.f) acc[0] = fmin(acc[0], (double)f / -(double)dv);
+    }
+  } else if constexpr (OP == PIX_RL2ZERO) {
+    // the pixels whose ratio f / -d attains the bound (the same d and the
+    // same double division as PIX_RL2MAX) become exactly 0, as f + lam d is
+    // in exact arithmetic; the update then keeps them there (d = 0)
+    const RowScal sc = row_scalars<ROW_DIR>(st, 0);
+    const double bound = st->lam_bound;
+    for (long long i = i0; i < nF; i += stride) {
+      const float f = a.f[i];
+      const float w = a.invw ? a.invw[i] : a.invw_s;
+      const float dv = dir_value(f, a.grad[i], w, sc);
+      if (dv < 0.f && (double)f / -(double)dv <= bound) a.f[i] = 0.f;
+    }
+  } else if constexpr (OP == PIX_FCOPY) {
+    for (long long i = i0; i < nF; i += stride) a.d[i] = a.f[i];
+  } else if constexpr (OP == PIX_RMSE) {
+    for (long long i = i0; i < nF; i += stride) {
+      const double t = a.ftrue[i];
+      const double e = (double)a.f[i] - t;
+      acc[0] += e * e;
+      acc[1] += t * t;
+    }
   } else if constexpr (OP == PIX_FSCALE) {
     const double s = st->fsum > 0.0 ? st->flux_c / st->fsum : 1.0;
     for (long long i = i0; i < nF; i += stride) a.f[i] = (float)((double)a.f[i] * s);
@@ -261,6 +306,10 @@ __global__ __launch_bounds__(kPixThreads) void pix_kernel(Args a_in) {
         fin_flux_newton(st, tot, (a.flag & 1) != 0);
       } else if constexpr (OP == PIX_FSUM) {
         st->fsum = tot[0];
+      } else if constexpr (OP == PIX_RMSE) {
+        fin_rmse(st, tot, !a.iter, a.jsel == 1);
+      } else if constexpr (OP == PIX_RL2MAX) {
+        fin_rl2max(st, tot[0]);
       }
     }
   }

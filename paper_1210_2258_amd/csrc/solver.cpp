@@ -239,11 +239,19 @@ static size_t carve_plan(const PlanKey& key, char* base, Plan& pl) {
   return off;
 }
 
+// A plan of the same shape made for at least key.nitems items serves: item
+// strides do not depend on the item count, and a launch covers only the
+// items it is given (the smallest such plan is taken, so repeated batches of
+// varying sizes do not pile up workspaces).
 static int cached_plan(const PlanKey& key, hipStream_t s, Plan** out) {
-  auto it = g_plans.find(key);
+  auto it = g_plans.lower_bound(key);
   if (it != g_plans.end()) {
-    *out = it->second.get();
-    return 0;
+    PlanKey k = it->first;
+    k.nitems = key.nitems;
+    if (!(k < key) && !(key < k)) {
+      *out = it->second.get();
+      return 0;
+    }
   }
   std::unique_ptr<Plan> pl;
   int rc = make_plan(key, s, pl);
@@ -287,12 +295,17 @@ static void defaults(sgp_params* p) {
   p->max_backtracks = 40;
   p->trace = nullptr;
   p->rl_alpha = 1.0;
+  p->f_true = nullptr;
+  p->rl_line_search = 0;
+  p->rl_lambda_cap = 10.0;
 }
 
 static int check_params(const sgp_params& p, int kind) {
   if (p.max_iter < 0) return fail(SGP_E_INVALID_ARG, "max_iter must be >= 0");
-  if (p.stop & ~(SGP_STOP_FIXED | SGP_STOP_CONV | SGP_STOP_DISCREPANCY))
+  if (p.stop & ~(SGP_STOP_FIXED | SGP_STOP_CONV | SGP_STOP_DISCREPANCY | SGP_STOP_RMSE))
     return fail(SGP_E_INVALID_ARG, "unknown stop bits");
+  if ((p.stop & SGP_STOP_RMSE) && !p.f_true)
+    return fail(SGP_E_INVALID_ARG, "SGP_STOP_RMSE needs f_true (the true object)");
   if (!(p.tol >= 0)) return fail(SGP_E_INVALID_ARG, "tol must be >= 0");
   if (!(p.disc_target > 0)) return fail(SGP_E_INVALID_ARG, "disc_target must be > 0");
   if (p.init < SGP_INIT_FLAT || p.init > SGP_INIT_WARM) return fail(SGP_E_INVALID_ARG, "unknown init");
@@ -300,9 +313,17 @@ static int check_params(const sgp_params& p, int kind) {
     return fail(SGP_E_INVALID_ARG, "SGP_INIT_USER / SGP_INIT_WARM need f0");
   if (em_kind(kind) && p.init == SGP_INIT_ZERO)
     return fail(SGP_E_INVALID_ARG, "RL / OSEM cannot start from the zero image");
-  if (kind == KIND_SGP) {
+  if (p.rl_line_search) {
+    if (kind != KIND_RL) return fail(SGP_E_INVALID_ARG, "rl_line_search (Eq. (RL2)) applies to RL only");
+    if (p.rl_alpha != 1.0) return fail(SGP_E_INVALID_ARG, "rl_line_search and rl_alpha != 1 exclude each other");
+    if (!(p.rl_lambda_cap >= 1.0 && p.rl_lambda_cap <= 1e6))
+      return fail(SGP_E_INVALID_ARG, "rl_lambda_cap must be in [1, 1e6]");
+  }
+  if (kind == KIND_SGP || p.rl_line_search) {
     if (!(p.beta > 0 && p.beta < 1)) return fail(SGP_E_INVALID_ARG, "beta must be in (0,1)");
     if (!(p.theta > 0 && p.theta < 1)) return fail(SGP_E_INVALID_ARG, "theta must be in (0,1)");
+  }
+  if (kind == KIND_SGP) {
     if (!(p.alpha_min > 0 && p.alpha_min < p.alpha_max)) return fail(SGP_E_INVALID_ARG, "need 0 < alpha_min < alpha_max");
     if (!(p.alpha0 >= p.alpha_min && p.alpha0 <= p.alpha_max)) return fail(SGP_E_INVALID_ARG, "alpha0 outside [alpha_min, alpha_max]");
     if (!(p.tau1 > 0 && p.tau1 < 1)) return fail(SGP_E_INVALID_ARG, "tau1 must be in (0,1)");
@@ -488,6 +509,19 @@ static void fill_state(DevState& h, const sgp_params& p, const Problem& pb, doub
   h.L1 = p.L1;
   h.L2 = p.L2;
   h.k_stop = 0;
+  h.rms_k = -1;
+  if (p.rl_line_search) {
+    // Eq. (RL2) on the SGP iteration: alpha = 1 and D = (M_R / w) o f
+    // (bounds 0 and a value no float reaches) make the projected step the
+    // RL step, d the RL direction; the candidates come from fin_rl2max
+    h.rl2 = 1;
+    h.lam_cap = p.rl_lambda_cap;
+    h.auto_bounds = 0;
+    h.L1p = 0.0;
+    h.L2p = 3.0e38;
+    h.alpha0 = 1.0;
+    h.alpha = 1.0;
+  }
 }
 
 }  // namespace sgp
@@ -515,6 +549,7 @@ struct sgp_solver {
   long long cnt[SGP_KCLASS_COUNT] = {0};
 
   bool own_stream = true;   // false: the per-device stream of the one-shot calls
+  bool restored = false;    // the reconstruction-error stop's minimum has been put back into f
   ~sgp_solver() {
     for (auto& kv : graphs) {
       (void)hipGraphExecDestroy(kv.second.second);
@@ -558,9 +593,12 @@ static void enqueue_iteration(sgp_solver* S) {
   Launcher& L = S->L;
   const int p = S->pb.p;
   const long long nS = (long long)S->pb.ny * S->pb.nx;
+  const long long nF = (long long)S->pb.NY * S->pb.NX;
+  // Sect. 3.3 reconstruction-error stop: the iterate before each update is
+  // kept, and rho of the new one is tested
+  const bool rms = (S->prm.stop & SGP_STOP_RMSE) != 0;
   if (S->kind == KIND_SGP) {
     if (S->prm.flux_constraint) {
-      const long long nF = (long long)S->pb.NY * S->pb.NX;
       L.pix(PIX_FLUX_INIT, nF, 1, 0, SGP_KCLASS_ROW_DIR);
       for (int t = 0; t < kFluxNewton; ++t) {
         // the last pass counts an iteration whose multiplier is still not at the root
@@ -570,6 +608,8 @@ static void enqueue_iteration(sgp_solver* S) {
         L.base.flag = save;
       }
     }
+    // Eq. (RL2): the step candidates, from the largest keeping f >= 0
+    if (S->prm.rl_line_search) L.pix(PIX_RL2MAX, nF, 1);
     // each row kernel's reduction is finished at the start of the next launch
     // (the direction and update sums by the column kernels, the Armijo test by
     // the Armijo kernel), the BB sums by a one-workgroup launch
@@ -579,12 +619,17 @@ static void enqueue_iteration(sgp_solver* S) {
     L.pix(PIX_ARMIJO, p * nS, 1, 0, SGP_KCLASS_ARMIJO_MORE, ROW_AD);
     L.row(ROW_UPD, p, 1, 0, SGP_KCLASS_ROW_UPD);
     L.col(COL_CORRSUM, 1, 1, 1, SGP_KCLASS_COL_CORR, ROW_UPD);
+    if (rms) L.pix(PIX_FCOPY, nF, 1);  // the iterate before f <- f + lambda d
+    if (S->prm.rl_line_search) L.pix(PIX_RL2ZERO, nF, 1);
     L.row(ROW_GRAD, 1, 1, 0, SGP_KCLASS_ROW_GRAD, true);
+    if (rms) L.pix(PIX_RMSE, nF, 1, 1);
   } else if (S->kind == KIND_RL) {
     L.col(COL_CONV, 0, 1, 1, SGP_KCLASS_COL_CONV);
     L.row(ROW_RATIO, p, 1, 0, SGP_KCLASS_ROW_RATIO);
     L.col(COL_CORRSUM, 1, 1, 1, SGP_KCLASS_COL_CORR);
+    if (rms) L.pix(PIX_FCOPY, nF, 1);
     L.row(ROW_RLUPD, 1, 1, 0, SGP_KCLASS_ROW_RLUPD);
+    if (rms) L.pix(PIX_RMSE, nF, 1, 0);
   } else {
     // OSEM (Algorithm 2): the KL of f^(k) over all images (the stop rules),
     // whose ratio pass also serves the first sub-step; then for each image j
@@ -593,7 +638,6 @@ static void enqueue_iteration(sgp_solver* S) {
     L.col(COL_CONV, 0, 1, 1, SGP_KCLASS_COL_CONV);
     L.row(ROW_RATIO, p, 1, 0, SGP_KCLASS_ROW_RATIO);
     const Args save = L.base;
-    const long long nF = (long long)S->pb.NY * S->pb.NX;
     for (int j = 0; j < p; ++j) {
       L.base.j0 = j;
       L.base.jn = 1;
@@ -606,9 +650,11 @@ static void enqueue_iteration(sgp_solver* S) {
       L.base.jn = 0;
       if (S->pb.boundary) L.base.invw = S->pl->invwj + (long long)j * nF;
       else L.base.invw_s = 1.0f;
+      if (rms && j == 0) L.pix(PIX_FCOPY, nF, 1);  // f^(k) before the first sub-step
       L.row(ROW_RLUPD, 1, 1, 0, SGP_KCLASS_ROW_RLUPD);
       L.base = save;
     }
+    if (rms) L.pix(PIX_RMSE, nF, 1, 0);
   }
 }
 
@@ -676,6 +722,7 @@ static int setup(sgp_solver* S) {
     L.col(COL_CORRSUM, 1, 1, 0);
     L.row(ROW_SETUPGRAD, 1, 0);
   }
+  if (S->prm.stop & SGP_STOP_RMSE) L.pix(PIX_RMSE, nF, 0);  // rho^(0)
   SGP_HIP(hipGetLastError());
   if ((rc = read_state(S))) return rc;
   for (int i = 0; i < S->nitems; ++i) {
@@ -721,7 +768,7 @@ struct StepPlan {
 };
 static StepPlan step_plan(const sgp_solver* S, int n) {
   StepPlan p;
-  p.early = (S->prm.stop & (SGP_STOP_CONV | SGP_STOP_DISCREPANCY)) != 0;
+  p.early = (S->prm.stop & (SGP_STOP_CONV | SGP_STOP_DISCREPANCY | SGP_STOP_RMSE)) != 0;
   p.iters = em_kind(S->kind) ? n + 1 : n;  // RL / OSEM evaluate J once more before pausing
   p.block = std::min(p.iters, p.early ? 16 : 32);
   p.full = p.block > 0 ? p.iters / p.block : 0;
@@ -794,6 +841,14 @@ static int step(sgp_solver* S, int n, int* done_out) {
   }
   if ((rc = read_state(S))) return rc;
   S->done = all_done(S);
+  // Sect. 3.3: a run stopped past the minimum of the reconstruction error
+  // returns the iterate kept before the last update (one problem per solver)
+  if (S->done && !S->restored && S->pl->host_st[0].rms_back) {
+    SGP_HIP(hipMemcpyAsync(S->f, S->pl->d, sizeof(float) * (size_t)S->pb.NY * S->pb.NX, hipMemcpyDeviceToDevice,
+                           S->s));
+    SGP_HIP(hipStreamSynchronize(S->s));
+    S->restored = true;
+  }
   if (done_out) *done_out = S->done ? 1 : 0;
   return 0;
 }
@@ -890,10 +945,14 @@ static int create_items(int kind, const std::vector<Problem>& items, const std::
       for (int i = 0; i < n; ++i)
         if (!f0s[i]) return fail(SGP_E_INVALID_ARG, "SGP_INIT_USER / SGP_INIT_WARM need a start for every item");
     S->prm.trace = nullptr;  // no per-iteration trace for batches
+    if (S->prm.stop & SGP_STOP_RMSE)
+      return fail(SGP_E_INVALID_ARG, "SGP_STOP_RMSE takes one problem (one true object), not a batch");
     if (S->prm.f0 == nullptr && (S->prm.init == SGP_INIT_USER || S->prm.init == SGP_INIT_WARM))
       S->prm.f0 = f0s[0];
   }
   if ((rc = check_params(S->prm, kind))) return rc;
+  // the linear relaxation of RL (Eq. (RL2)) runs the SGP iteration (see fill_state)
+  if (kind == KIND_RL && S->prm.rl_line_search) kind = KIND_SGP;
   int dev;
   if ((rc = current_device(&dev))) return rc;
   const Problem& pb = items[0];
@@ -957,6 +1016,7 @@ static int create_items(int kind, const std::vector<Problem>& items, const std::
   a.invw_s = 1.0f / (float)pb.p;
   a.Af = pl->Af; a.Af2 = pl->Af2; a.Ad = pl->Ad; a.spec = pl->spec; a.khat = pl->khat; a.knyq = pl->knyq;
   a.psf = pb.psf; a.aux = pl->aux; a.src = S->prm.f0;
+  a.ftrue = (S->prm.stop & SGP_STOP_RMSE) ? S->prm.f_true : nullptr;
   a.tw_row = pl->tw_row; a.tw_col = pl->tw_col;
   a.part = pl->part; a.counter = pl->counter; a.st = pl->st;
   a.bvec = pl->btab;
@@ -1259,6 +1319,8 @@ int sgp_params_init(sgp_params* p) {
 static int mosaic_run(int kind, const float* g, int H, int W, const float* psf, int N, float b, int core,
                       int margin, const sgp_params* prm, float* f, sgp_report* rep, void* stream) {
   if (!g || !psf || !f) return fail(SGP_E_INVALID_ARG, "null pointer");
+  if (prm && (prm->stop & SGP_STOP_RMSE))
+    return fail(SGP_E_INVALID_ARG, "SGP_STOP_RMSE takes one problem (one true object), not a mosaic");
   if (core < 1 || margin < 0 || H < core || W < core || H % core || W % core)
     return fail(SGP_E_INVALID_ARG, "H and W must be positive multiples of core, margin >= 0");
   if (core + 2 * margin > N) return fail(SGP_E_INVALID_ARG, "a window (core + 2 margin) must fit in N");

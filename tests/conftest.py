@@ -55,8 +55,31 @@ def one_step_at_depth():
         rel = float(np.linalg.norm(f1.astype(np.float64) - fo) / np.linalg.norm(fo))
         assert rel <= f_tol, rel
         assert abs(rep["kl"] - io["kl"]) <= kl_tol * io["kl"], (rep["kl"], io["kl"])
-        for key in ("a1", "a2"):
-            assert abs(tr[key] - L[key]) <= 1e-2 * abs(L[key]), (key, tr[key], L[key])
+        # alpha1 = a / c1 and alpha2 = c2 / e are ratios of inner products of
+        # the step s, the gradient change z and D.  The GPU carries the
+        # gradient as a running sum of FP32 changes, so at depth its step
+        # direction differs from the one the oracle forms from the exact
+        # gradient of f_k; the relative difference of the two steps, e_s,
+        # enters a (quadratic in s) and c1, c2 (linear) to first order, so
+        # the bar is 4 e_s plus the transform error of z (1e-6 of its largest
+        # entry, 10x the FP32 transform error, times the cancellation of each
+        # sum), and at least 1e-3.
+        G0, G1 = P.grad(fk), P.grad(fo)
+        s_, z_ = fo - fk, G1 - G0
+        e_s = float(np.linalg.norm(f1.astype(np.float64) - fk - s_) / np.linalg.norm(s_))
+        D = P.scaling(fo, rep["L1"], rep["L2"])
+        msk = D > 0
+        s_, z_, D = s_[msk], z_[msk], D[msk]
+        ez = 1e-6 * np.abs(z_).max()
+        c1 = np.sum(s_ * z_ / D)
+        c2, e = np.sum(s_ * z_ * D), np.sum(z_ * z_ * D * D)
+        b1 = ez * np.sum(np.abs(s_ / D)) / abs(c1)
+        b2 = ez * np.sum(np.abs(s_ * D)) / abs(c2) + 2 * ez * np.sum(np.abs(z_) * D * D) / e
+        for key, bnd in (("a1", b1), ("a2", b2)):
+            tol = max(1e-3, 4 * e_s + bnd)
+            print(f"depth {depth} {key}: rel diff {abs(tr[key] / L[key] - 1):.1e}, step diff {e_s:.1e}, "
+                  f"bar {tol:.1e}", flush=True)
+            assert abs(tr[key] - L[key]) <= tol * abs(L[key]), (key, tr[key], L[key], tol)
         return rel
 
     return check

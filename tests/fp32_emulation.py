@@ -29,14 +29,15 @@ import scipy.fft
 from oracle import sgp as O
 
 f32 = np.float32
+c64 = np.complex64   # the complex type of the transforms (float32 pairs)
 
 
 def _fft2(x):
-    return scipy.fft.fft2(x.astype(np.complex64))
+    return scipy.fft.fft2(x.astype(c64))
 
 
 def _ifft2(x):
-    return scipy.fft.ifft2(x.astype(np.complex64))
+    return scipy.fft.ifft2(x.astype(c64))
 
 
 def _h(x):
@@ -75,7 +76,7 @@ class Fp32Problem:
         self.P = P
         self.p = P.p
         K32 = (P.K).astype(f32)
-        self.Khat = np.stack([_fft2(np.fft.ifftshift(K32[j])) for j in range(P.p)]).astype(np.complex64)
+        self.Khat = np.stack([_fft2(np.fft.ifftshift(K32[j])) for j in range(P.p)]).astype(c64)
         if P.boundary:
             MS = P.MS.astype(f32)
             alpha = np.stack([np.real(_ifft2(np.conj(self.Khat[j]) * _fft2(MS))).astype(f32)
@@ -95,7 +96,7 @@ class Fp32Problem:
     def AT_sum(self, rhos):
         """M_R o sum_j A_j^T rho_j, the sum taken in Fourier space."""
         P = self.P
-        acc = np.zeros((P.NY, P.NX), np.complex64)
+        acc = np.zeros((P.NY, P.NX), c64)
         for j in range(self.p):
             e = np.zeros((P.NY, P.NX), f32)
             e[self.S] = rhos[j]

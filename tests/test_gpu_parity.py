@@ -43,7 +43,7 @@ def _check_log(tr, log, n):
     for k in range(n):
         L = log[k]
         assert int(tr["backtracks"][k]) == L["backtracks"], (k, tr["backtracks"][k], L["backtracks"])
-        assert abs(tr["alpha"][k] - L["alpha"]) <= 1e-2 * L["alpha"], (k, tr["alpha"][k], L["alpha"])
+        assert abs(tr["alpha"][k] - L["alpha"]) <= 1e-3 * L["alpha"], (k, tr["alpha"][k], L["alpha"])
         if k < n - 1:
             assert int(tr["br1"][k]) == L["br1"] and int(tr["br2"][k]) == L["br2"], k
             assert int(tr["alt"][k]) == L["alt"], k
@@ -146,19 +146,17 @@ def test_relaxed_rl_rejects_bad_exponents(torch_dev):
         _run_gpu(torch_dev, "sgp_deconv", w, max_iter=2, rl_alpha=1.5)
 
 
-# SGP iterates carried in FP32 drift from the FP64 oracle's.  Two sources:
-# FP32 storage of f and d (rounding them inside the oracle itself moves the
-# KL by ~2e-6 after 20 iterations on the 64x80 case, tests/test_oracle_fp32_floor.py)
-# and the ~1e-7 relative error of FP32 FFTs, which on the 64x80 case already
-# puts ~1e-6 into the BB inner products at k = 3 and grows the KL gap past
-# 1e-6 by k = 8.  How soon it grows depends on rounding choices as small as
-# whether the compiler fuses a twiddle product into the following butterfly
-# add (one such change moved 58 pixels of the 3 x 64 x 64 case by a few ulps
-# after one iteration and its KL gap after 6 iterations from 2e-7 to 1.7e-6).
-# Fixed-count parity is checked where both bars hold with margin: 6
-# iterations on the 64x80 case, 4 on the three-image and boundary cases, 20
-# on the 256x256 field, 10 at full size (tests/test_gpu_fullsize.py).
-SGP_K = {"single_64x80": 6, "single_c0_256": 20, "multi_3x64": 4, "boundary_64x48_in_80x64": 4}
+# Fixed-count SGP windows.  FP32 arithmetic by itself moves an SGP run away
+# from the FP64 one: the CPU model of FP32 rounding (tests/fp32_emulation.py,
+# fields, transforms and pointwise terms in float32, sums in float64) takes
+# the KL gap past 1e-6 at iteration 9 on the 64x80 case, 5 on the three-image
+# case, 6 on the boundary case and 13 on the 256x256 field
+# (tests/test_fp32_model_floor.py); the GPU's own first crossings are 18, 6, 5
+# and 22 (tests/test_gpu_drift.py).  The windows end before the GPU's
+# crossing with a margin: 12, 4, 4 and 20 iterations (full sizes:
+# tests/test_gpu_fullsize.py).  Later iterations are checked one at a time
+# (test_sgp_one_iteration_at_depth) and by their decisions.
+SGP_K = {"single_64x80": 12, "single_c0_256": 20, "multi_3x64": 4, "boundary_64x48_in_80x64": 4}
 
 
 @pytest.mark.parametrize("case", list(CASES))
