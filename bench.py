@@ -193,7 +193,8 @@ def time_to_discrepancy(torch, m, g, psf, b):
 
 
 def multi_image_legs(torch, m, w):
-    """Multiple-image RL (Eq. multipleRL), OSEM (Algorithm 2) and SGP on the
+    """Multiple-image RL (Eq. multipleRL), its linear relaxation with the
+    Armijo line search (Eq. RL2), OSEM (Algorithm 2) and SGP on the
     3 x 1024^2 interferometric workload, each to the discrepancy stop, call to
     return with the inputs resident (the comparison of the paper's Tables 5-8
     on synthetic data)."""
@@ -201,16 +202,19 @@ def multi_image_legs(torch, m, w):
     psf = torch.from_numpy(w.psf).cuda()
     out = {"workload": f"{w.g.shape[0]} x {w.g.shape[1]}x{w.g.shape[2]} fringe-PSF images of one object, b = 20",
            "stop": "discrepancy <= 1 (cap 20000 iterations)"}
-    for name, fn in (("rl", m.rl_multi_deconv), ("osem", m.osem_deconv), ("sgp", m.sgp_multi_deconv)):
-        fn(g, psf, w.b, max_iter=2)  # workspace of this shape and kind
+    legs = (("rl", m.rl_multi_deconv, {}), ("rl_linear", m.rl_multi_deconv, {"rl_line_search": 1}),
+            ("osem", m.osem_deconv, {}), ("sgp", m.sgp_multi_deconv, {}))
+    for name, fn, kw in legs:
+        fn(g, psf, w.b, max_iter=2, **kw)  # workspace of this shape and kind
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        _, rep = fn(g, psf, w.b, max_iter=20000, stop=m.STOP_DISCREPANCY)
+        _, rep = fn(g, psf, w.b, max_iter=20000, stop=m.STOP_DISCREPANCY, **kw)
         torch.cuda.synchronize()
         out[name] = {"seconds": time.perf_counter() - t0, "iterations": rep["iters"], "reason": rep["reason"],
                      "kl": rep["kl"], "discrepancy": rep["discrepancy"]}
     out["speedup_sgp_vs_rl"] = out["rl"]["seconds"] / out["sgp"]["seconds"]
     out["speedup_osem_vs_rl"] = out["rl"]["seconds"] / out["osem"]["seconds"]
+    out["speedup_rl_linear_vs_rl"] = out["rl"]["seconds"] / out["rl_linear"]["seconds"]
     return out
 
 
