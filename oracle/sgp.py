@@ -476,11 +476,14 @@ class Problem:
         return flux_projection(z, D, c)
 
     def sgp(self, f0, params: Params | None = None, force_alpha=None,
-            force_lambda=None, bounds=None):
+            force_lambda=None, bounds=None, grad0=None):
         """Algorithm 1 with the Sect. 2.1 steplength rules and Sect. 3 policies.
 
         ``force_alpha`` / ``force_lambda`` pin alpha_k / lambda_k (tests only:
-        the RL identity of Eq. (RL2) with lambda = 1).
+        the RL identity of Eq. (RL2) with lambda = 1).  ``bounds`` and
+        ``grad0`` supply (L1, L2) and the gradient at f0 instead of computing
+        them (tests only: one iteration re-run from another implementation's
+        state).
         Returns (f, info) where info carries the per-iteration decision log."""
         prm = params or Params()
         c = self.flux_value(prm) if prm.flux_constraint else None
@@ -500,6 +503,12 @@ class Problem:
             L1, L2 = prm.L1, prm.L2
         J = self.kl(f)
         G = self.grad(f)
+        # a supplied gradient is carried as a sum of changes: each step adds
+        # the exact change grad J(f_new) - grad J(f), which is also the z of
+        # Eqs. (BB1), (BB2)
+        Gx = None
+        if grad0 is not None:
+            Gx, G = G, np.asarray(grad0, dtype=np.float64).copy()
         alpha = prm.alpha0
         tau = prm.tau1
         Q: list[float] = []
@@ -546,6 +555,8 @@ class Problem:
                 break
             # step 6: update
             G_new = self.grad(f_new)
+            if Gx is not None:
+                Gx, G_new = G_new, G + (G_new - Gx)
             a_num, c1, c2, e_den = self.bb_sums(f, f_new, G, G_new, L1, L2)
             a1, a2, br1, br2, alpha_next, tau, Q, alt = steplength_update(
                 alpha, tau, Q, k, a_num, c1, c2, e_den, prm)
