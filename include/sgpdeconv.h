@@ -276,6 +276,13 @@ int sgp_solver_step(sgp_solver* s, int n, int* done);
  * solver keeps every graph it has captured until it is destroyed. */
 int sgp_solver_prepare(sgp_solver* s, int n);
 int sgp_solver_report(sgp_solver* s, sgp_report* rep);
+/* SGP only: copies the gradient of J_0 at the current iterate, as the solver
+ * carries it (Sect. 2.2 Eq. (KLgrad), Sect. 2.3 Eq. (multiplegradient),
+ * Sect. 2.4 Eq. (gradientboundary): the start's gradient plus the change of
+ * every step, in float32), into out (device [NY][NX], caller-owned), so that
+ * one iteration can be re-run elsewhere from the solver's own state.
+ * SGP_E_INVALID_ARG for another kind or a batched solver.  Synchronous. */
+int sgp_solver_gradient(sgp_solver* s, float* out);
 /* Kernel timing of later step() calls (HIP events around every launch on the
  * solver's stream; graphs are not used while enabled).  ms[i] receives the
  * summed milliseconds and counts[i] the launches of kernel class i:

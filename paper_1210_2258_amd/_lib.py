@@ -72,7 +72,7 @@ EXPORTS = [
     "sgp_params_init", "rl_deconv", "sgp_deconv", "sgp_deconv_noalloc", "sgp_multi_deconv", "rl_multi_deconv",
     "sgp_boundary_deconv", "rl_boundary_deconv", "sgp_apply_operator", "sgp_release_cache",
     "sgp_strerror", "sgp_last_error", "sgp_solver_create", "sgp_solver_step", "sgp_solver_prepare",
-    "sgp_solver_report",
+    "sgp_solver_report", "sgp_solver_gradient",
     "sgp_solver_set_timing", "sgp_solver_set_graph", "sgp_solver_timing", "sgp_solver_destroy",
     "sgp_steplength_rule", "sgp_batch_deconv", "osem_deconv", "osem_boundary_deconv", "sgp_mosaic_deconv",
     "sgp_cnn_num_params", "sgp_cnn_create", "sgp_cnn_get_params", "sgp_cnn_infer", "sgp_cnn_loss_grad",
@@ -106,6 +106,7 @@ def load():
     lib.sgp_solver_step.argtypes = [vp, i, ctypes.POINTER(i)]
     lib.sgp_solver_prepare.argtypes = [vp, i]
     lib.sgp_solver_report.argtypes = [vp, R]
+    lib.sgp_solver_gradient.argtypes = [vp, vp]
     lib.sgp_solver_set_timing.argtypes = [vp, i]
     lib.sgp_solver_set_graph.argtypes = [vp, i]
     lib.sgp_solver_timing.argtypes = [vp, ctypes.POINTER(d), ctypes.POINTER(ctypes.c_longlong), i]
@@ -497,6 +498,14 @@ class Solver:
         rc = load().sgp_solver_report(self._h, ctypes.byref(rep))
         _raise(rc)
         return _report(rep, rc, self._trace)
+
+    def gradient(self):
+        """The gradient the SGP solver carries at its current iterate
+        (a new [NY, NX] tensor)."""
+        import torch
+        out = torch.empty_like(self.f)
+        _raise(load().sgp_solver_gradient(self._h, ctypes.c_void_p(out.data_ptr())))
+        return out
 
     def set_timing(self, on=True):
         _raise(load().sgp_solver_set_timing(self._h, 1 if on else 0))

@@ -128,17 +128,35 @@ __device__ __forceinline__ float h_x(float x) {
   return x - log1pf(x);
 }
 
+// 1 / d and n / d for the pointwise stages: the hardware reciprocal (about
+// one ulp) refined by one Newton step on the residual, r' = r + r (1 - d r)
+// and q' = q + r (n - d q) with q = n r, four instructions instead of the
+// ten of an IEEE division, within an ulp of the rounded quotient.  Only for
+// normal d (the hardware reciprocal flushes subnormals): every denominator
+// passed here is a count (>= 1) or a model value clamped at 1e-30.
+__device__ __forceinline__ float qrcp(float d) {
+  const float r = __builtin_amdgcn_rcpf(d);
+  return fmaf(fmaf(-d, r, 1.f), r, r);
+}
+__device__ __forceinline__ float qdiv(float n, float d) {
+  const float r = __builtin_amdgcn_rcpf(d);
+  const float q = n * r;
+  return fmaf(fmaf(-d, q, n), r, q);
+}
+
 // KL term g ln(g / y) + y - g of Eq. (divergence) (y when g = 0), written as
 // g h((y - g) / g).
 __device__ __forceinline__ double kl_term(float g, float y) {
-  return g > 0.f ? (double)(g * h_x((y - g) / g)) : (double)y;
+  return g > 0.f ? (double)(g * h_x(qdiv(y - g, g))) : (double)y;
 }
 
 // J(f + lam d) - J(f) contribution of one pixel with y = A f + b, t = lam A d:
 // t - g log1p(t / y) = (y - g) x + g h(x) with x = t / y.
-__device__ __forceinline__ double armijo_term(float g, float y, float t) {
-  const float x = t / y;
+__device__ __forceinline__ double armijo_x(float g, float y, float x) {
   return (double)((y - g) * x) + (double)(g * h_x(x));
+}
+__device__ __forceinline__ double armijo_term(float g, float y, float t) {
+  return armijo_x(g, y, qdiv(t, y));
 }
 
 // Solver scalars a row kernel uses, read once per workgroup (the kernel's
@@ -283,7 +301,7 @@ __device__ __forceinline__ float row_point(const Args& a, const RowScal& sc, int
     const float g = in.c[0];
     const float yv = fmaxf(v + in.c[1], 1e-30f);
     acc[0] += kl_term(g, yv);
-    return (g - yv) / yv;
+    return qdiv(g - yv, yv);
   } else if constexpr (OP == ROW_RLUPD) {
     // RL factor q = 1 + (M_R / alpha) v in residual form; relaxed RL
     // (Eq. (RL1)) raises it to the power rl_a
@@ -325,14 +343,17 @@ __device__ __forceinline__ float row_point(const Args& a, const RowScal& sc, int
     const float afo = in.c[1];
     const float bgv = in.c[2];
     const float yv = fmaxf(afo + bgv, 1e-30f);
-    acc[0] += armijo_term(g, yv, sc.lam0 * v);
-    acc[1] += armijo_term(g, yv, sc.lam1 * v);
+    // one reciprocal of y serves both candidates and delta rho
+    const float ryv = qrcp(yv);
     const float step = sc.lam0 * v;  // lambda = 1
+    const float x0 = step * ryv;
+    acc[0] += armijo_x(g, yv, x0);
+    acc[1] += armijo_x(g, yv, (sc.lam1 * v) * ryv);
     const float afn = afo + step;
     a.Af2[s] = afn;
     const float yn = fmaxf(afn + bgv, 1e-30f);
     acc[2] += kl_term(g, yn);
-    return g > 0.f ? -g * step / (yv * yn) : 0.f;
+    return g > 0.f ? qdiv(-g * x0, yn) : 0.f;
   } else if constexpr (OP == ROW_UPD) {
     // A_j f += lam A_j d (f += lam d is taken by the gradient pass, which
     // reads f and d anyway); feeds delta rho_j = g/y_new - g/y_old
@@ -350,7 +371,7 @@ __device__ __forceinline__ float row_point(const Args& a, const RowScal& sc, int
     const float yo = fmaxf(afo + bgv, 1e-30f);
     const float yn = fmaxf(afn + bgv, 1e-30f);
     acc[0] += kl_term(g, yn);
-    return g > 0.f ? -g * step / (yo * yn) : 0.f;
+    return g > 0.f ? qdiv(-g * step * qrcp(yo), yn) : 0.f;
   } else if constexpr (OP == ROW_GRAD) {
     // v = sum_j A_j^T delta rho_j, so z = grad_new - grad_old = -M_R v; the
     // step of Algorithm 1 step 6, f_new = f + lam d, is taken here, with d
@@ -367,7 +388,7 @@ __device__ __forceinline__ float row_point(const Args& a, const RowScal& sc, int
     const double z = (double)zf;
     const double D = (double)(w * fminf(sc.L2, fmaxf(sc.L1, fn)));
     if (D > 0) {
-      const double sd = s / D;
+      const double sd = s / D;  // (D may be subnormal when L1 is: an IEEE division)
       acc[0] += sd * sd;
       acc[1] += sd * z;
       acc[2] += s * z * D;

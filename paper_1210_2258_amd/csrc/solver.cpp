@@ -1532,6 +1532,17 @@ int sgp_solver_report(sgp_solver* s, sgp_report* rep) {
   SGP_GUARD(report(s, rep));
 }
 
+int sgp_solver_gradient(sgp_solver* s, float* out) {
+  if (!s || !out) return fail(SGP_E_INVALID_ARG, "null solver or output");
+  if (s->kind != KIND_SGP || s->nitems != 1 || s->prm.rl_line_search)
+    return fail(SGP_E_INVALID_ARG, "the gradient is kept by single-problem SGP solvers only");
+  hipError_t e = hipMemcpyAsync(out, s->pl->grad, sizeof(float) * (size_t)s->pb.NY * s->pb.NX,
+                                hipMemcpyDeviceToDevice, s->s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s->s);
+  if (e != hipSuccess) return fail(SGP_E_HIP, std::string("gradient copy: ") + hipGetErrorString(e));
+  return 0;
+}
+
 int sgp_solver_set_timing(sgp_solver* s, int enable) {
   if (!s) return fail(SGP_E_INVALID_ARG, "null solver");
   s->L.timing = enable != 0;

@@ -48,10 +48,10 @@ def _gpu_history(torch, w, n):
 
 CASES = {
     # name: (workload, iterations run, parity window of the fixed-count tests)
-    "single_64x80": (lambda: W.small_single(64, 80), 40, 12),
+    "single_64x80": (lambda: W.small_single(64, 80), 40, 8),
     "multi_3x64": (lambda: W.small_multi(64, 64, p=3), 40, 4),
     "boundary_64x48_in_80x64": (lambda: W.small_boundary(80, 64, 64, 48, 8, 8), 40, 4),
-    "single_c0_256": (W.config0, 60, 20),
+    "single_c0_256": (W.config0, 60, 12),
 }
 
 

@@ -151,12 +151,15 @@ def test_relaxed_rl_rejects_bad_exponents(torch_dev):
 # fields, transforms and pointwise terms in float32, sums in float64) takes
 # the KL gap past 1e-6 at iteration 9 on the 64x80 case, 5 on the three-image
 # case, 6 on the boundary case and 13 on the 256x256 field
-# (tests/test_fp32_model_floor.py); the GPU's own first crossings are 18, 6, 5
-# and 22 (tests/test_gpu_drift.py).  The windows end before the GPU's
-# crossing with a margin: 12, 4, 4 and 20 iterations (full sizes:
-# tests/test_gpu_fullsize.py).  Later iterations are checked one at a time
-# (test_sgp_one_iteration_at_depth) and by their decisions.
-SGP_K = {"single_64x80": 12, "single_c0_256": 20, "multi_3x64": 4, "boundary_64x48_in_80x64": 4}
+# (tests/test_fp32_model_floor.py).  A GPU run's own crossing is a draw of
+# the same chaotic process (any change of rounding moves it: 18 or 19, 6 or
+# 9, 5, 22 or 20 with two builds; tests/test_gpu_drift.py checks that it is
+# never more than two iterations earlier than the model's), so the windows
+# end one iteration before the earlier of the two: 8, 4, 4 and 12 (full
+# sizes: tests/test_gpu_fullsize.py).  Later iterations are checked one at a
+# time from the GPU's own state (test_sgp_one_iteration_at_depth) and by
+# their decisions.
+SGP_K = {"single_64x80": 8, "single_c0_256": 12, "multi_3x64": 4, "boundary_64x48_in_80x64": 4}
 
 
 @pytest.mark.parametrize("case", list(CASES))
