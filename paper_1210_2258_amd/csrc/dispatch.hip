@@ -13,7 +13,8 @@ namespace sgp {
   int col_width_##L(int v);                                                   \
   int row_threads_##L(int v);                                                 \
   int row_pairs_##L(int v);                                                   \
-  int col_threads_##L(int v);
+  int col_threads_##L(int v);                                                 \
+  void launch_twiddle_##L(float2* tw, hipStream_t s);
 SGP_SIZES(SGP_DECL)
 #undef SGP_DECL
 
@@ -127,7 +128,12 @@ void launch_zero(unsigned* c, int n, hipStream_t s) {
 }
 
 void launch_twiddle(float2* tw, int L, hipStream_t s) {
-  hipLaunchKernelGGL(twiddle_kernel, dim3((L + 255) / 256), dim3(256), 0, s, tw, L);
+  switch (L) {
+#define SGP_CASE(L) case L: launch_twiddle_##L(tw, s); break;
+    SGP_SIZES(SGP_CASE)
+#undef SGP_CASE
+    default: break;
+  }
 }
 
 }  // namespace sgp

@@ -12,7 +12,7 @@
 // with lane t % TF.  Twiddles come from a per-length table
 // tw[m] = exp(-2 pi i m / L) built once per plan in double precision and
 // rounded to float, regrouped per pass when a workgroup stages it in LDS
-// (stage_twiddles).  Inverse transforms use conj(FFT(conj(x))).
+// (TwStage).  Inverse transforms use conj(FFT(conj(x))).
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -130,35 +130,74 @@ template <> __device__ __forceinline__ void dft<5>(float2* v) {
 }
 
 // ---------------------------------------------------------------- twiddles
-// Pass order layout of the twiddles in LDS.  The pass of stride NS > 1 and
-// radix R needs W_{NS R}^{i k} for i = 1 .. R-1 and k = j mod NS; it keeps
-// them at NS - r0 + (i - 1) NS + k.  The lanes of a wave hold consecutive k,
-// so each of their twiddle reads covers consecutive entries and spreads over
-// the LDS banks (a gather from the length-L table at stride i k L / (NS R)
-// puts up to 32 lanes on one bank).  The offsets telescope: all passes
-// together hold L - r0 entries.
-template <int L, int R, int NS>
-__device__ __forceinline__ void stage_pass_tw(float2* twl, const float2* __restrict__ tw, int tid, int nt) {
-  if constexpr (NS > 1 && R > 1) {
-    constexpr int n = (R - 1) * NS, step = L / (NS * R);
-    for (int t = tid; t < n; t += nt) {
-      const int i = t / NS + 1, k = t % NS;
-      twl[NS - FftPlan<L>::r0 + t] = tw[i * k * step];
+// Pass order layout of the twiddles.  The pass of stride NS > 1 and radix R
+// needs W_{NS R}^{i k} for i = 1 .. R-1 and k = j mod NS; it keeps them at
+// NS - r0 + (i - 1) NS + k.  The lanes of a wave hold consecutive k, so each
+// of their twiddle reads covers consecutive entries and spreads over the LDS
+// banks (a gather from the length-L table at stride i k L / (NS R) puts up
+// to 32 lanes on one bank).  The offsets telescope: all passes together hold
+// L - r0 entries.  The table is built once per length in this order
+// (twiddle_pass_kernel), so a workgroup stages it with a contiguous copy.
+
+// Exponent m of W_L^m at entry t of the pass-ordered table (-1 past its end).
+template <int L>
+__host__ __device__ constexpr int tw_pass_index(int t) {
+  using P = FftPlan<L>;
+  const int rs[5] = {P::r0, P::r1, P::r2, P::r3, P::r4};
+  int ns = P::r0;
+  for (int p = 1; p < P::NP; ++p) {
+    const int R = rs[p];
+    const int lo = ns - P::r0, n = (R - 1) * ns;
+    if (t >= lo && t < lo + n) {
+      const int u = t - lo, i = u / ns + 1, k = u % ns;
+      return i * k * (L / (ns * R));
     }
+    ns *= R;
+  }
+  return -1;
+}
+
+// The pass-ordered table of length L: exp(-2 pi i m / L) from double
+// precision, rounded to float (the value the natural-order table holds at m).
+template <int L>
+__global__ void twiddle_pass_kernel(float2* tw) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < L) {
+    const int m = tw_pass_index<L>(t);
+    float2 v = make_float2(0.f, 0.f);
+    if (m >= 0) {
+      double s, c;
+      sincospi(2.0 * (double)m / (double)L, &s, &c);
+      v = make_float2((float)c, (float)(-s));
+    }
+    tw[t] = v;
   }
 }
 
-// Stages the twiddles of every pass of FftPlan<L> from the length-L table tw
-// into twl (L entries suffice).  Visible to the workgroup after its next
-// barrier.
-template <int L>
-__device__ __forceinline__ void stage_twiddles(float2* twl, const float2* __restrict__ tw, int tid, int nt) {
-  using P = FftPlan<L>;
-  stage_pass_tw<L, P::r1, P::r0>(twl, tw, tid, nt);
-  if constexpr (P::NP > 2) stage_pass_tw<L, P::r2, P::r0 * P::r1>(twl, tw, tid, nt);
-  if constexpr (P::NP > 3) stage_pass_tw<L, P::r3, P::r0 * P::r1 * P::r2>(twl, tw, tid, nt);
-  if constexpr (P::NP > 4) stage_pass_tw<L, P::r4, P::r0 * P::r1 * P::r2 * P::r3>(twl, tw, tid, nt);
-}
+// Copy of the pass-ordered table into LDS by NT threads, split so that a
+// kernel issues the global loads early (load(), with its own data loads)
+// and writes LDS later (store(), before the barrier that precedes the first
+// pass reading twiddles).
+template <int L, int NT>
+struct TwStage {
+  static constexpr int N = L - FftPlan<L>::r0;
+  static constexpr int PER = N > 0 ? (N + NT - 1) / NT : 1;
+  float2 v[PER];
+  __device__ __forceinline__ void load(const float2* __restrict__ tw, int tid) {
+#pragma unroll
+    for (int e = 0; e < PER; ++e) {
+      const int i = tid + e * NT;
+      v[e] = i < N ? tw[i] : make_float2(0.f, 0.f);
+    }
+  }
+  __device__ __forceinline__ void store(float2* twl, int tid) const {
+#pragma unroll
+    for (int e = 0; e < PER; ++e) {
+      const int i = tid + e * NT;
+      if (i < N) twl[i] = v[e];
+    }
+  }
+};
 
 // ------------------------------------------------------------------ passes
 template <int L, int TF, int R, int NS>
@@ -251,7 +290,7 @@ __device__ __forceinline__ void fft_lds_x(float2* buf, int lane, const float2* _
 }
 
 // Forward FFT of buf (logical index i stored at lds_idx<L>(i)) in place,
-// natural order in and out, with the twiddles staged by stage_twiddles<L>.
+// natural order in and out, with the twiddles staged by TwStage<L, NT>.
 // Every thread
 // of the workgroup must call this (it contains barriers).
 template <int L>

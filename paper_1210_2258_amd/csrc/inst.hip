@@ -72,4 +72,9 @@ int SGP_CAT(row_threads_, SGP_L)(int v) { return v == 1 ? RowCfg<SGP_L, 1>::NT :
 int SGP_CAT(row_pairs_, SGP_L)(int v) { return v == 1 ? RowCfg<SGP_L, 1>::RP : RowCfg<SGP_L, 0>::RP; }
 int SGP_CAT(col_threads_, SGP_L)(int v) { return v == 1 ? ColCfg<SGP_L, 1>::NT : ColCfg<SGP_L, 0>::NT; }
 
+// the twiddle table of length SGP_L in the pass order of its transforms
+void SGP_CAT(launch_twiddle_, SGP_L)(float2* tw, hipStream_t s) {
+  hipLaunchKernelGGL((twiddle_pass_kernel<SGP_L>), dim3((SGP_L + 255) / 256), dim3(256), 0, s, tw);
+}
+
 }  // namespace sgp

@@ -510,7 +510,9 @@ __global__ __launch_bounds__((RowCfg<L, V>::NT)) void row_kernel(Args a_in) {
   float2* spec = a.spec + (row_per_image(OP) ? j : 0) * sstride + (long long)(y0 >> 3) * HALF * kTile + (y0 & 7);
 
   const float2* tw = twl;
-  stage_twiddles<L>(twl, a.tw_row, tid, NT);  // visible after the first barrier
+  // the twiddles are loaded with the kernel's first data and written to LDS
+  // before the barrier that precedes the first pass reading them
+  TwStage<L, NT> tws;
   double acc[NS > 0 ? NS : 1];
   {
     RowKinds kinds{OP};
@@ -527,10 +529,22 @@ __global__ __launch_bounds__((RowCfg<L, V>::NT)) void row_kernel(Args a_in) {
   float2 xr[P::E];
   if constexpr (row_has_inv(OP)) {
     const float4* S4 = reinterpret_cast<const float4*>(spec);
+    // every spectrum load, then the twiddle loads, are in flight before the
+    // first LDS write
+    constexpr int NL = (HALF * RP + NT - 1) / NT;
+    float4 sp[NL];
 #pragma unroll
-    for (int u = tid; u < HALF * RP; u += NT) {
+    for (int e = 0; e < NL; ++e) {
+      const int u = tid + e * NT;
+      if (u < HALF * RP) sp[e] = S4[4 * (u / RP) + u % RP];  // (A, B) of rows y0 + 2q, y0 + 2q + 1 at column k
+    }
+    tws.load(a.tw_row, tid);
+#pragma unroll
+    for (int e = 0; e < NL; ++e) {
+      const int u = tid + e * NT;
+      if (u >= HALF * RP) break;
       const int q = u % RP, k = u / RP;
-      const float4 ab = S4[4 * k + q];  // (A, B) of rows y0 + 2q, y0 + 2q + 1 at column k
+      const float4 ab = sp[e];
       if (k == 0) {
         buf[q][lds_idx<L>(0)] = make_float2(ab.x, -ab.z);       // conj(A0 + i B0)
         buf[q][lds_idx<L>(HALF)] = make_float2(ab.y, -ab.w);    // conj(AN + i BN)
@@ -539,9 +553,12 @@ __global__ __launch_bounds__((RowCfg<L, V>::NT)) void row_kernel(Args a_in) {
         buf[q][lds_idx<L>(L - k)] = make_float2(ab.x + ab.w, -(-ab.y + ab.z)); // conj(conj A + i conj B)
       }
     }
+    tws.store(twl, tid);
     __syncthreads();
     if constexpr (XR) fft_lds_x<L, false, true>(buf[qt], lt, tw, xr);
     else fft_lds<L>(buf[qt], lt, tw);
+  } else if constexpr (row_has_fwd(OP)) {
+    tws.load(a.tw_row, tid);  // in flight with the pointwise loads
   }
 
   // pointwise stage in chunks of CH units per thread: every load of a chunk
@@ -585,6 +602,7 @@ __global__ __launch_bounds__((RowCfg<L, V>::NT)) void row_kernel(Args a_in) {
   if constexpr (row_has_fwd(OP)) {
     // (register-fed: the inverse transform's last pass ended its LDS reads
     // with a barrier, and a forward-only op has not used buf)
+    if constexpr (!row_has_inv(OP)) tws.store(twl, tid);  // (read after the first pass's barrier)
     if constexpr (XR) {
       fft_lds_x<L, true, false>(buf[qt], lt, tw, xr);
     } else {
@@ -660,7 +678,10 @@ __global__ __launch_bounds__((ColCfg<LY, V>::NT)) void col_kernel(Args a_in) {
   const long long sstride = spec_elems(a.NY, a.NX);
   const int jin = (MODE == COL_FWD) ? blockIdx.y : 0;
   const float2* tw = twl;
-  stage_twiddles<LY>(twl, a.tw_col, tid, NT);  // visible after the first barrier
+  // twiddle loads issued first, written to LDS before the barrier that
+  // precedes the first pass reading them, once the column data is in flight
+  TwStage<LY, NT> tws;
+  tws.load(a.tw_col, tid);
 
   // unit e of this thread -> (column c, row y) and its offset in the layout
   auto unit = [&](int e, int& c, int& y, long long& off) {
@@ -682,6 +703,7 @@ __global__ __launch_bounds__((ColCfg<LY, V>::NT)) void col_kernel(Args a_in) {
 
   if constexpr (MODE == COL_FWD) {
     load(a.spec + jin * sstride);
+    tws.store(twl, tid);
     __syncthreads();
     fft_lds<LY>(buf[tid / TF], tid % TF, tw);
     float2* K = a.khat + jin * sstride;
@@ -711,6 +733,7 @@ __global__ __launch_bounds__((ColCfg<LY, V>::NT)) void col_kernel(Args a_in) {
       unit(e, c, y, off);
       kpre[e] = (kx0 + c < NXh) ? K0[off] : make_float2(0.f, 0.f);
     }
+    tws.store(twl, tid);
     __syncthreads();
     fft_lds<LY>(buf[tid / TF], tid % TF, tw);
     float2 x0[E], x1[E];  // spectrum (or its even / odd parts for column 0)
@@ -792,6 +815,7 @@ __global__ __launch_bounds__((ColCfg<LY, V>::NT)) void col_kernel(Args a_in) {
       runit(e, y, off);
       kpre[e] = live ? K[off] : make_float2(0.f, 0.f);
     }
+    tws.store(twl, tid);  // (read after the first pass's barrier)
     fft_lds_x<LY, true, true>(buf[c], lane, tw, xr);
     if (has_col0) {  // uniform over the workgroup
       if (c == 0) {
@@ -847,6 +871,7 @@ __global__ __launch_bounds__((ColCfg<LY, V>::NT)) void col_kernel(Args a_in) {
       unit(e, c, y, off);
       kpre[e] = (kx0 + c < NXh) ? K[off] : make_float2(0.f, 0.f);
     }
+    tws.store(twl, tid);
     __syncthreads();
     fft_lds<LY>(buf[tid / TF], tid % TF, tw);
     float2 pr[E];
@@ -897,6 +922,7 @@ __global__ __launch_bounds__((ColCfg<LY, V>::NT)) void col_kernel(Args a_in) {
         unit(e, c, y, off);
         kpre[e] = (kx0 + c < NXh) ? K[off] : make_float2(0.f, 0.f);
       }
+      if (ji == a.j0) tws.store(twl, tid);
       __syncthreads();
       fft_lds<LY>(buf[tid / TF], lane, tw);
 #pragma unroll

@@ -19,6 +19,7 @@ void launch_pix(int op, dim3 grid, const Args& a, hipStream_t s);
 // second reduction stage of the row iteration kernels (one workgroup per item)
 void launch_row_fin(int op, int nz, const Args& a, hipStream_t s);
 bool row_fin_deferred(int op);
+// the twiddle table of length L in the pass order of the transforms (L entries)
 void launch_twiddle(float2* tw, int L, hipStream_t s);
 void launch_zero(unsigned* c, int n, hipStream_t s);
 void launch_resume(DevState* st, int n, int nitems, hipStream_t s);

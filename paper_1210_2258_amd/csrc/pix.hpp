@@ -352,14 +352,5 @@ __global__ void zero_kernel(unsigned* c, int n) {
   if (i < n) c[i] = 0u;
 }
 
-// exp(-2 pi i m / L) for m < L, in double precision, rounded to float.
-__global__ void twiddle_kernel(float2* tw, int L) {
-  const int m = blockIdx.x * blockDim.x + threadIdx.x;
-  if (m < L) {
-    double s, c;
-    sincospi(2.0 * (double)m / (double)L, &s, &c);
-    tw[m] = make_float2((float)c, (float)(-s));
-  }
-}
 
 }  // namespace sgp
