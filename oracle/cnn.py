@@ -18,7 +18,9 @@ network itself is not part of the paper):
 conv is a 5x5 cross-correlation with periodic padding,
     out[co](y, x) = bias[co] + sum_{ci,ky,kx} W[co, ci, ky, kx] in[ci]((y+ky-2) mod H, (x+kx-2) mod W),
 and every convolution weight (not the biases) is rounded to bfloat16 (round
-to nearest even) before use.
+to nearest even) before use.  For inference the hidden activations a1..a3
+are also stored as bfloat16 (forward(..., act_bf16=True)); training keeps
+them in float32.
 The training loss on a batch is the mean over pixels of
 (sqrt(y + eps) - sqrt(t + eps))^2 with t = f_target / s, eps = 1e-3.
 Adam (beta1 0.9, beta2 0.999, eps 1e-8) updates float32 master weights.
@@ -122,9 +124,13 @@ def scale_of(g, b):
     return max(float(np.mean(np.asarray(g, np.float64) - b)), 1e-3)
 
 
-def forward(theta, g, b, bf16=True):
+def forward(theta, g, b, bf16=True, act_bf16=False):
     """Returns (f0, cache) for one image.  bf16=False skips the weight
-    rounding (only for finite-difference checks of the gradient formula)."""
+    rounding (only for finite-difference checks of the gradient formula).
+    act_bf16=True also stores the three hidden activations as bfloat16, as
+    the inference path does: each one, after its ReLU, is rounded to float32
+    and then to the nearest bfloat16 (ties to even); the output layer is not
+    rounded."""
     rnd = bf16_round if bf16 else (lambda a: a)
     layers = [(rnd(w).astype(np.float64), bb.astype(np.float64)) for w, bb in unpack(theta)]
     s = scale_of(g, b)
@@ -134,6 +140,8 @@ def forward(theta, g, b, bf16=True):
     for li, (w, bb) in enumerate(layers):
         pre = conv(h, w, bb)
         h = np.maximum(pre, 0.0) if li < 3 else pre
+        if act_bf16 and li < 3:
+            h = bf16_round(h.astype(np.float32)).astype(np.float64)
         acts.append(h)
     o = acts[-1][0]
     y = softplus(o)
