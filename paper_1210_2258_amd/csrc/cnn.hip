@@ -185,6 +185,164 @@ __global__ __launch_bounds__(NT) void conv16_mfma_kernel(const float* __restrict
   }
 }
 
+// ---------------------------------------------------- inference, bfloat16
+// Inference keeps the hidden activations as bfloat16 in pixel-major order,
+// a[img][y][x][16] (32 bytes per pixel), so that the two 16 -> 16 layers run
+// on the bf16 matrix cores: v_mfma_f32_16x16x32_bf16 with lane l supplying
+// A[l % 16][8 (l / 16) + j] and B[8 (l / 16) + j][l % 16] (j < 8) and
+// receiving D[4 (l / 16) + r][l % 16] in register r (checked on the GPU with
+// an in-bounds probe before use).  A = weights (16 output channels x K),
+// B = input patches (K x 16 pixels of one tile row), K = 25 taps x 16 input
+// channels with the channel fastest, padded to 13 steps of 32 (a 26th tap
+// of zero weight).  Sums are FP32 in the matrix core's order.
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+constexpr int kKSteps = 13;                  // ceil(25 * 16 / 32)
+constexpr int kPackedW = kKSteps * 64 * 8;   // bf16 words of one packed 16 -> 16 layer
+
+__device__ __forceinline__ unsigned short bf16_bits(float v) {  // nearest bfloat16, ties to even
+  const unsigned u = __float_as_uint(v);
+  return (unsigned short)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
+}
+__device__ __forceinline__ float bf16_val(unsigned short h) { return __uint_as_float((unsigned)h << 16); }
+
+// Packed A operands of one 16 -> 16 layer from its bf16-rounded weights w
+// [co][ci][5][5]: wp[step][lane][j] = W[co = lane % 16][ci = 8 ((lane / 16) % 2) + j]
+// [tap = 2 step + (lane / 16) / 2], 0 for tap 25.
+__global__ void pack16_kernel(const float* __restrict__ w, unsigned short* __restrict__ wp) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= kPackedW) return;
+  const int j = i % 8, lane = (i / 8) % 64, step = i / (8 * 64);
+  const int co = lane % 16, g = lane / 16;
+  const int ci = 8 * (g % 2) + j, tap = 2 * step + g / 2;
+  wp[i] = tap < K * K ? bf16_bits(w[(co * C + ci) * K * K + tap]) : (unsigned short)0;
+}
+
+// a1 = bf16(relu(conv 1 -> 16 (x))) in pixel-major order.  grid (W/T, H/T, images)
+__global__ __launch_bounds__(NT) void conv1_bf16_kernel(const float* __restrict__ in, const float* __restrict__ w,
+                                                         const float* __restrict__ bias,
+                                                         unsigned short* __restrict__ out, int H, int W) {
+  __shared__ float tile[TH][TH];
+  const int img = blockIdx.z;
+  const int x0 = blockIdx.x * T, y0 = blockIdx.y * T;
+  const long long N = (long long)H * W;
+  const float* inb = in + (long long)img * N;
+  for (int i = threadIdx.x; i < TH * TH; i += NT) {
+    const int r = i / TH, q = i % TH;
+    tile[r][q] = inb[(long long)wrap(y0 + r - 2, H) * W + wrap(x0 + q - 2, W)];
+  }
+  __syncthreads();
+  const int ty = threadIdx.x / T, tx = threadIdx.x % T;
+  float acc[C];
+#pragma unroll
+  for (int co = 0; co < C; ++co) acc[co] = bias[co];
+#pragma unroll
+  for (int ky = 0; ky < K; ++ky) {
+#pragma unroll
+    for (int kx = 0; kx < K; ++kx) {
+      const float v = tile[ty + ky][tx + kx];
+#pragma unroll
+      for (int co = 0; co < C; ++co) acc[co] = fmaf(w[co * K * K + ky * K + kx], v, acc[co]);
+    }
+  }
+  unsigned pk[C / 2];
+#pragma unroll
+  for (int c2 = 0; c2 < C / 2; ++c2)
+    pk[c2] = (unsigned)bf16_bits(fmaxf(acc[2 * c2], 0.f)) | ((unsigned)bf16_bits(fmaxf(acc[2 * c2 + 1], 0.f)) << 16);
+  uint4* o = reinterpret_cast<uint4*>(out + (((long long)img * H + y0 + ty) * W + x0 + tx) * C);
+  o[0] = make_uint4(pk[0], pk[1], pk[2], pk[3]);
+  o[1] = make_uint4(pk[4], pk[5], pk[6], pk[7]);
+}
+
+// bf16(relu(conv 16 -> 16 (in))), pixel-major bf16 in and out: a workgroup of
+// four waves computes one 16x16 output tile; wave w takes tile rows
+// 4w .. 4w + 3, each row one chain of 13 matrix-core steps.  The packed
+// weights stay in registers; the input tile with its 2-pixel halo is staged
+// in LDS as [row][column][channel].  grid (W/T, H/T, images)
+__global__ __launch_bounds__(NT) void conv16_bf16_kernel(const unsigned short* __restrict__ in,
+                                                          const unsigned short* __restrict__ wp,
+                                                          const float* __restrict__ bias,
+                                                          unsigned short* __restrict__ out, int H, int W) {
+  __shared__ uint4 tile[TH * TH * 2];  // [r][q][two halves of 8 channels]
+  const int img = blockIdx.z;
+  const int x0 = blockIdx.x * T, y0 = blockIdx.y * T;
+  const unsigned short* inb = in + (long long)img * H * W * C;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  bf16x8 a[kKSteps];
+  const uint4* wp4 = reinterpret_cast<const uint4*>(wp);
+#pragma unroll
+  for (int st = 0; st < kKSteps; ++st) {
+    const uint4 u = wp4[st * 64 + lane];
+    a[st] = __builtin_bit_cast(bf16x8, u);
+  }
+  for (int i = threadIdx.x; i < TH * TH * 2; i += NT) {
+    const int p = i >> 1, h = i & 1, r = p / TH, q = p % TH;
+    const long long off = ((long long)wrap(y0 + r - 2, H) * W + wrap(x0 + q - 2, W)) * C + 8 * h;
+    tile[i] = *reinterpret_cast<const uint4*>(inb + off);
+  }
+  __syncthreads();
+  const int n = lane & 15, g = lane >> 4;
+  float bc[4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) bc[r] = bias[4 * g + r];
+#pragma unroll
+  for (int rr = 0; rr < 4; ++rr) {
+    const int row = 4 * wave + rr;
+    floatx4 acc = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int st = 0; st < kKSteps; ++st) {
+      const int tap = 2 * st + g / 2;
+      const int t = tap < K * K ? tap : K * K - 1;  // the padding tap has zero weight
+      const int ky = t / K, kx = t % K;
+      const uint4 u = tile[((row + ky) * TH + n + kx) * 2 + (g & 1)];
+      acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[st], __builtin_bit_cast(bf16x8, u), acc, 0, 0, 0);
+    }
+    // acc[r]: channel 4g + r at pixel (row, n) of the tile
+    const unsigned lo = (unsigned)bf16_bits(fmaxf(acc[0] + bc[0], 0.f)) |
+                        ((unsigned)bf16_bits(fmaxf(acc[1] + bc[1], 0.f)) << 16);
+    const unsigned hi = (unsigned)bf16_bits(fmaxf(acc[2] + bc[2], 0.f)) |
+                        ((unsigned)bf16_bits(fmaxf(acc[3] + bc[3], 0.f)) << 16);
+    *reinterpret_cast<uint2*>(out + (((long long)img * H + y0 + row) * W + x0 + n) * C + 4 * g) = make_uint2(lo, hi);
+  }
+}
+
+// o = conv 16 -> 1 (a3), a3 pixel-major bf16, o float32.  grid (W/T, H/T, images)
+__global__ __launch_bounds__(NT) void conv16to1_bf16_kernel(const unsigned short* __restrict__ in,
+                                                             const float* __restrict__ w,
+                                                             const float* __restrict__ bias,
+                                                             float* __restrict__ out, int H, int W) {
+  __shared__ uint4 tile[TH * TH * 2];
+  const int img = blockIdx.z;
+  const int x0 = blockIdx.x * T, y0 = blockIdx.y * T;
+  const unsigned short* inb = in + (long long)img * H * W * C;
+  for (int i = threadIdx.x; i < TH * TH * 2; i += NT) {
+    const int p = i >> 1, h = i & 1, r = p / TH, q = p % TH;
+    const long long off = ((long long)wrap(y0 + r - 2, H) * W + wrap(x0 + q - 2, W)) * C + 8 * h;
+    tile[i] = *reinterpret_cast<const uint4*>(inb + off);
+  }
+  __syncthreads();
+  const int ty = threadIdx.x / T, tx = threadIdx.x % T;
+  float acc = bias[0];
+#pragma unroll
+  for (int ky = 0; ky < K; ++ky) {
+#pragma unroll
+    for (int kx = 0; kx < K; ++kx) {
+      const int p = ((ty + ky) * TH + tx + kx) * 2;
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const uint4 u = tile[p + h];
+        const unsigned uu[4] = {u.x, u.y, u.z, u.w};
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int ci = 8 * h + 2 * e;
+          acc = fmaf(w[ci * K * K + ky * K + kx], bf16_val((unsigned short)(uu[e] & 0xFFFFu)), acc);
+          acc = fmaf(w[(ci + 1) * K * K + ky * K + kx], bf16_val((unsigned short)(uu[e] >> 16)), acc);
+        }
+      }
+    }
+  }
+  out[(long long)img * H * W + (long long)(y0 + ty) * W + (x0 + tx)] = acc;
+}
+
 // din[ci](q) = sum_co sum_k W[co][ci][k] dout[co](q - k + 2), times the ReLU
 // mask (act > 0) of the layer input.  grid (W/T, H/T, images)
 template <int CIN, int COUT>
@@ -397,6 +555,7 @@ __global__ void round_kernel(const float* theta, float* wr, int n) {
 
 struct Net {
   float *theta = nullptr, *m = nullptr, *v = nullptr, *grad = nullptr, *wr = nullptr;
+  unsigned short* wp = nullptr;  // packed bf16 A operands of the two 16 -> 16 layers (inference)
   int step = 0;
   // work buffers, sized for cap_px pixels over at most cap_n images; the
   // training buffers exist only once a training call has been made
@@ -430,10 +589,11 @@ struct Net {
     cap_train = false;
   }
   void free_params() {
-    void* p[] = {theta, m, v, grad, wr};
+    void* p[] = {theta, m, v, grad, wr, wp};
     for (void* q : p)
       if (q) (void)hipFree(q);
     theta = m = v = grad = wr = nullptr;
+    wp = nullptr;
   }
 };
 
@@ -493,6 +653,24 @@ static int forward(Net* net, int n, int H, int W, bool train, hipStream_t s) {
   return 0;
 }
 
+// inference forward of n images into o: hidden activations as bfloat16 in
+// pixel-major order (a[0], a[1] hold them at half their float32 capacity),
+// the 16 -> 16 layers on the bf16 matrix cores
+static int forward_infer(Net* net, int n, int H, int W, hipStream_t s) {
+  const dim3 grid(W / T, H / T, n);
+  unsigned short* a0 = reinterpret_cast<unsigned short*>(net->a[0]);
+  unsigned short* a1 = reinterpret_cast<unsigned short*>(net->a[1]);
+  for (int l = 1; l <= 2; ++l)
+    hipLaunchKernelGGL(pack16_kernel, dim3((kPackedW + 255) / 256), dim3(256), 0, s, wl(net, l),
+                       net->wp + (l - 1) * kPackedW);
+  hipLaunchKernelGGL(conv1_bf16_kernel, grid, dim3(NT), 0, s, net->x, wl(net, 0), bl(net, 0), a0, H, W);
+  hipLaunchKernelGGL(conv16_bf16_kernel, grid, dim3(NT), 0, s, a0, net->wp, bl(net, 1), a1, H, W);
+  hipLaunchKernelGGL(conv16_bf16_kernel, grid, dim3(NT), 0, s, a1, net->wp + kPackedW, bl(net, 2), a0, H, W);
+  hipLaunchKernelGGL(conv16to1_bf16_kernel, grid, dim3(NT), 0, s, a0, wl(net, 3), bl(net, 3), net->o, H, W);
+  CNN_HIP(hipGetLastError());
+  return 0;
+}
+
 // network input (and training target) of n images into x (t)
 static int prep(Net* net, int n, int H, int W, bool train, hipStream_t s) {
   const long long N = (long long)H * W;
@@ -544,7 +722,7 @@ int sgp_cnn_create(const float* host_params, size_t nparams, sgp_cnn** out) {
   sgp_cnn* net = new sgp_cnn();
   int rc;
   if ((rc = dal(&net->theta, kParams)) || (rc = dal(&net->m, kParams)) || (rc = dal(&net->v, kParams)) ||
-      (rc = dal(&net->grad, kParams)) || (rc = dal(&net->wr, kParams))) {
+      (rc = dal(&net->grad, kParams)) || (rc = dal(&net->wr, kParams)) || (rc = dal(&net->wp, 2 * kPackedW))) {
     delete net;
     return rc;
   }
@@ -584,7 +762,7 @@ int sgp_cnn_infer(sgp_cnn* h, int n, const float* const* g, const float* b, int 
   if ((rc = ensure(net, n, ny, nx, false))) return rc;
   if ((rc = set_tables(net, n, g, b, nullptr, f0, s))) return rc;
   if ((rc = prep(net, n, ny, nx, false, s))) return rc;
-  if ((rc = forward(net, n, ny, nx, false, s))) return rc;
+  if ((rc = forward_infer(net, n, ny, nx, s))) return rc;
   const long long N = (long long)ny * nx;
   hipLaunchKernelGGL(output_kernel, dim3((unsigned)((N + 255) / 256), n), dim3(256), 0, s, net->o, net->s,
                      net->f0tab, ny, nx);

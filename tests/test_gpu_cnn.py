@@ -57,10 +57,23 @@ def test_forward_matches_oracle(torch_dev, shape):
     net = CnnNet(theta)
     f0 = net.infer([_dev(torch, g) for g in gs], bs)
     for i in range(3):
-        ref, _ = OC.forward(theta, gs[i], bs[i])
+        # inference stores the hidden activations as bfloat16: the oracle
+        # rounds them the same way.  Where the FP32 pre-activation and the
+        # oracle's FP64 one fall on opposite sides of a bfloat16 rounding
+        # point the two activations differ by one bfloat16 step (2^-8
+        # relative), which moves the output pixels around it.  Perturbing
+        # the oracle's pre-activations by relative 1e-7 (the size of FP32
+        # accumulation error) moves these nine outputs by up to 5.8e-5 in
+        # relative L2 (3e-7: up to 9e-4), so the bar is 2e-4; and the flips
+        # are local: at most 1% of the pixels may differ by more than 1e-4.
+        ref, _ = OC.forward(theta, gs[i], bs[i], act_bf16=True)
         got = f0[i].cpu().numpy()
         assert got.shape == ref.shape
-        assert _rel(got, ref) <= 1e-5, (i, _rel(got, ref))
+        err = _rel(got, ref)
+        far = float(np.mean(np.abs(got - ref) > 1e-4 * np.abs(ref).max()))
+        print(f"network start {shape} image {i}: rel L2 {err:.1e}, pixels off by > 1e-4: {far:.2%}", flush=True)
+        assert err <= 2e-4, (i, err)
+        assert far <= 0.01, (i, far)
         assert np.all(got >= 0)
     net.close()
 
