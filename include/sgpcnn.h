@@ -55,8 +55,9 @@ int sgp_cnn_get_params(sgp_cnn* h, float* host_out, size_t nparams);
 /* f0[i] = network start image of g[i] (all n images ny x nx).  Runs on
  * hip_stream (NULL: the default stream) and returns after it finishes.
  * Inference stores the hidden activations a1..a3 as bfloat16 (nearest, ties
- * to even, after the ReLU) and runs the two 16->16 layers on the bf16
- * matrix cores (FP32 accumulation); training (below) keeps them in float32. */
+ * to even, after the ReLU) and runs the three layers with 16 input channels
+ * on the bf16 matrix cores (FP32 accumulation); training (below) keeps the
+ * activations in float32. */
 int sgp_cnn_infer(sgp_cnn* h, int n, const float* const* g, const float* b, int ny, int nx, float* const* f0,
                   void* hip_stream);
 

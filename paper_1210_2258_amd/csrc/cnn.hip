@@ -205,16 +205,17 @@ __device__ __forceinline__ unsigned short bf16_bits(float v) {  // nearest bfloa
 }
 __device__ __forceinline__ float bf16_val(unsigned short h) { return __uint_as_float((unsigned)h << 16); }
 
-// Packed A operands of one 16 -> 16 layer from its bf16-rounded weights w
-// [co][ci][5][5]: wp[step][lane][j] = W[co = lane % 16][ci = 8 ((lane / 16) % 2) + j]
-// [tap = 2 step + (lane / 16) / 2], 0 for tap 25.
-__global__ void pack16_kernel(const float* __restrict__ w, unsigned short* __restrict__ wp) {
+// Packed A operands of a layer with 16 input channels and cout <= 16 output
+// channels from its bf16-rounded weights w [co][ci][5][5]: wp[step][lane][j]
+// = W[co = lane % 16][ci = 8 ((lane / 16) % 2) + j][tap = 2 step + (lane / 16) / 2],
+// 0 for tap 25 and for co >= cout.
+__global__ void pack16_kernel(const float* __restrict__ w, int cout, unsigned short* __restrict__ wp) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= kPackedW) return;
   const int j = i % 8, lane = (i / 8) % 64, step = i / (8 * 64);
   const int co = lane % 16, g = lane / 16;
   const int ci = 8 * (g % 2) + j, tap = 2 * step + g / 2;
-  wp[i] = tap < K * K ? bf16_bits(w[(co * C + ci) * K * K + tap]) : (unsigned short)0;
+  wp[i] = tap < K * K && co < cout ? bf16_bits(w[(co * C + ci) * K * K + tap]) : (unsigned short)0;
 }
 
 // a1 = bf16(relu(conv 1 -> 16 (x))) in pixel-major order.  grid (W/T, H/T, images)
@@ -257,11 +258,15 @@ __global__ __launch_bounds__(NT) void conv1_bf16_kernel(const float* __restrict_
 // four waves computes one 16x16 output tile; wave w takes tile rows
 // 4w .. 4w + 3, each row one chain of 13 matrix-core steps.  The packed
 // weights stay in registers; the input tile with its 2-pixel halo is staged
-// in LDS as [row][column][channel].  grid (W/T, H/T, images)
+// in LDS as [row][column][channel].  FINAL: the output layer, conv 16 -> 1
+// (weights of channels 1..15 packed as zero), written unrounded as float32
+// planes to outf.  grid (W/T, H/T, images)
+template <bool FINAL>
 __global__ __launch_bounds__(NT) void conv16_bf16_kernel(const unsigned short* __restrict__ in,
                                                           const unsigned short* __restrict__ wp,
                                                           const float* __restrict__ bias,
-                                                          unsigned short* __restrict__ out, int H, int W) {
+                                                          unsigned short* __restrict__ out, float* __restrict__ outf,
+                                                          int H, int W) {
   __shared__ uint4 tile[TH * TH * 2];  // [r][q][two halves of 8 channels]
   const int img = blockIdx.z;
   const int x0 = blockIdx.x * T, y0 = blockIdx.y * T;
@@ -283,7 +288,7 @@ __global__ __launch_bounds__(NT) void conv16_bf16_kernel(const unsigned short* _
   const int n = lane & 15, g = lane >> 4;
   float bc[4];
 #pragma unroll
-  for (int r = 0; r < 4; ++r) bc[r] = bias[4 * g + r];
+  for (int r = 0; r < 4; ++r) bc[r] = FINAL ? bias[0] : bias[4 * g + r];
 #pragma unroll
   for (int rr = 0; rr < 4; ++rr) {
     const int row = 4 * wave + rr;
@@ -297,50 +302,16 @@ __global__ __launch_bounds__(NT) void conv16_bf16_kernel(const unsigned short* _
       acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[st], __builtin_bit_cast(bf16x8, u), acc, 0, 0, 0);
     }
     // acc[r]: channel 4g + r at pixel (row, n) of the tile
+    if constexpr (FINAL) {
+      if (g == 0) outf[((long long)img * H + y0 + row) * W + x0 + n] = acc[0] + bc[0];
+      continue;
+    }
     const unsigned lo = (unsigned)bf16_bits(fmaxf(acc[0] + bc[0], 0.f)) |
                         ((unsigned)bf16_bits(fmaxf(acc[1] + bc[1], 0.f)) << 16);
     const unsigned hi = (unsigned)bf16_bits(fmaxf(acc[2] + bc[2], 0.f)) |
                         ((unsigned)bf16_bits(fmaxf(acc[3] + bc[3], 0.f)) << 16);
     *reinterpret_cast<uint2*>(out + (((long long)img * H + y0 + row) * W + x0 + n) * C + 4 * g) = make_uint2(lo, hi);
   }
-}
-
-// o = conv 16 -> 1 (a3), a3 pixel-major bf16, o float32.  grid (W/T, H/T, images)
-__global__ __launch_bounds__(NT) void conv16to1_bf16_kernel(const unsigned short* __restrict__ in,
-                                                             const float* __restrict__ w,
-                                                             const float* __restrict__ bias,
-                                                             float* __restrict__ out, int H, int W) {
-  __shared__ uint4 tile[TH * TH * 2];
-  const int img = blockIdx.z;
-  const int x0 = blockIdx.x * T, y0 = blockIdx.y * T;
-  const unsigned short* inb = in + (long long)img * H * W * C;
-  for (int i = threadIdx.x; i < TH * TH * 2; i += NT) {
-    const int p = i >> 1, h = i & 1, r = p / TH, q = p % TH;
-    const long long off = ((long long)wrap(y0 + r - 2, H) * W + wrap(x0 + q - 2, W)) * C + 8 * h;
-    tile[i] = *reinterpret_cast<const uint4*>(inb + off);
-  }
-  __syncthreads();
-  const int ty = threadIdx.x / T, tx = threadIdx.x % T;
-  float acc = bias[0];
-#pragma unroll
-  for (int ky = 0; ky < K; ++ky) {
-#pragma unroll
-    for (int kx = 0; kx < K; ++kx) {
-      const int p = ((ty + ky) * TH + tx + kx) * 2;
-#pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        const uint4 u = tile[p + h];
-        const unsigned uu[4] = {u.x, u.y, u.z, u.w};
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const int ci = 8 * h + 2 * e;
-          acc = fmaf(w[ci * K * K + ky * K + kx], bf16_val((unsigned short)(uu[e] & 0xFFFFu)), acc);
-          acc = fmaf(w[(ci + 1) * K * K + ky * K + kx], bf16_val((unsigned short)(uu[e] >> 16)), acc);
-        }
-      }
-    }
-  }
-  out[(long long)img * H * W + (long long)(y0 + ty) * W + (x0 + tx)] = acc;
 }
 
 // din[ci](q) = sum_co sum_k W[co][ci][k] dout[co](q - k + 2), times the ReLU
@@ -555,7 +526,7 @@ __global__ void round_kernel(const float* theta, float* wr, int n) {
 
 struct Net {
   float *theta = nullptr, *m = nullptr, *v = nullptr, *grad = nullptr, *wr = nullptr;
-  unsigned short* wp = nullptr;  // packed bf16 A operands of the two 16 -> 16 layers (inference)
+  unsigned short* wp = nullptr;  // packed bf16 A operands of layers 2-4 (inference)
   int step = 0;
   // work buffers, sized for cap_px pixels over at most cap_n images; the
   // training buffers exist only once a training call has been made
@@ -660,13 +631,15 @@ static int forward_infer(Net* net, int n, int H, int W, hipStream_t s) {
   const dim3 grid(W / T, H / T, n);
   unsigned short* a0 = reinterpret_cast<unsigned short*>(net->a[0]);
   unsigned short* a1 = reinterpret_cast<unsigned short*>(net->a[1]);
-  for (int l = 1; l <= 2; ++l)
-    hipLaunchKernelGGL(pack16_kernel, dim3((kPackedW + 255) / 256), dim3(256), 0, s, wl(net, l),
+  for (int l = 1; l <= 3; ++l)
+    hipLaunchKernelGGL(pack16_kernel, dim3((kPackedW + 255) / 256), dim3(256), 0, s, wl(net, l), kCout[l],
                        net->wp + (l - 1) * kPackedW);
   hipLaunchKernelGGL(conv1_bf16_kernel, grid, dim3(NT), 0, s, net->x, wl(net, 0), bl(net, 0), a0, H, W);
-  hipLaunchKernelGGL(conv16_bf16_kernel, grid, dim3(NT), 0, s, a0, net->wp, bl(net, 1), a1, H, W);
-  hipLaunchKernelGGL(conv16_bf16_kernel, grid, dim3(NT), 0, s, a1, net->wp + kPackedW, bl(net, 2), a0, H, W);
-  hipLaunchKernelGGL(conv16to1_bf16_kernel, grid, dim3(NT), 0, s, a0, wl(net, 3), bl(net, 3), net->o, H, W);
+  hipLaunchKernelGGL(conv16_bf16_kernel<false>, grid, dim3(NT), 0, s, a0, net->wp, bl(net, 1), a1, nullptr, H, W);
+  hipLaunchKernelGGL(conv16_bf16_kernel<false>, grid, dim3(NT), 0, s, a1, net->wp + kPackedW, bl(net, 2), a0,
+                     nullptr, H, W);
+  hipLaunchKernelGGL(conv16_bf16_kernel<true>, grid, dim3(NT), 0, s, a0, net->wp + 2 * kPackedW, bl(net, 3),
+                     nullptr, net->o, H, W);
   CNN_HIP(hipGetLastError());
   return 0;
 }
@@ -722,7 +695,7 @@ int sgp_cnn_create(const float* host_params, size_t nparams, sgp_cnn** out) {
   sgp_cnn* net = new sgp_cnn();
   int rc;
   if ((rc = dal(&net->theta, kParams)) || (rc = dal(&net->m, kParams)) || (rc = dal(&net->v, kParams)) ||
-      (rc = dal(&net->grad, kParams)) || (rc = dal(&net->wr, kParams)) || (rc = dal(&net->wp, 2 * kPackedW))) {
+      (rc = dal(&net->grad, kParams)) || (rc = dal(&net->wr, kParams)) || (rc = dal(&net->wp, 3 * kPackedW))) {
     delete net;
     return rc;
   }
