@@ -429,6 +429,11 @@ def config_rates(torch, m, steps, warmup, with_oracle):
     return out
 
 
+def note(msg):
+    """One progress line per finished leg, on stderr (the JSON line stays alone on stdout)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -474,6 +479,7 @@ def main():
                                "ms_per_iter": None, "set_by": "--tiles"}
     elif not args.no_autotune:
         tune(m, g, psf, b, 96, tiles)
+        note(f"tile autotune done: {tiles}")
 
     # ---- throughput: W warm-up iterations, then exactly K timed iterations
     # (the graphs the timed call replays are captured before it)
@@ -503,11 +509,13 @@ def main():
     achieved = BYTES_PER_PX[dom] * npx / (avg_ms * 1e-3) / 1e9
     iter_ms_events = sum(v[2] for v in kern.values()) / 8
     iter_roofline = ITER_BYTES_PER_PX * npx / (ms_per_step * 1e-3) / 1e9
+    note(f"throughput {its:.0f} iter/s, per-kernel timing done")
 
     out_ttd = {}
     f_full = None
     if not args.no_ttd:
         out_ttd, f_full = time_to_discrepancy(torch, m, g, psf, b)
+        note("time to discrepancy done")
     traffic = counter_traffic(dom, npx)
     
     out = {
@@ -538,18 +546,24 @@ def main():
     }
     if batch_items is not None:
         out["batch_512"] = batch_legs(torch, m, batch_items, None if args.no_autotune else tiles)
+        note("batch legs done")
     if tiles:
         out["tile_schedule"] = tiles
     if not args.no_multi:
         out["multi_image_3x1024"] = multi_image_legs(torch, m, W.config2())
+        note("multi-image legs done")
     if not args.no_mosaic and f_full is not None:
         out["mosaic_2048"] = mosaic_leg(torch, m, w, g, psf, f_full, None if args.no_autotune else tiles)
+        note("mosaic leg done")
     if not args.no_mall and args.size == 2048:
         out["beyond_mall_4x2048"] = beyond_mall_leg(torch, m, g, psf, b)
+        note("beyond-MALL leg done")
     if not args.no_sweep:
         out["rebin_sweep"] = rebin_sweep(torch, m, with_oracle=not args.no_cpu)
+        note("rebin sweep done")
     if not args.no_configs:
         out["configs"] = config_rates(torch, m, 100, 10, not args.no_cpu)
+        note("config rates done")
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_iters, out_ttd.get("iters_to_discrepancy"))
     print(json.dumps(out))
