@@ -755,7 +755,6 @@ __global__ __launch_bounds__((ColCfg<LY, V>::NT)) void col_kernel(Args a_in) {
     for (int jo = jlo; jo < jhi; ++jo) {
       int lane = tid % TF;
       asm volatile("" : "+v"(lane));  // keeps per-pass address arithmetic inside the loop
-      const float2* K = a.khat + jo * sstride;
       const float2* KN = a.knyq + (long long)jo * LY;
 #pragma unroll
       for (int e = 0; e < E; ++e) {
@@ -763,7 +762,7 @@ __global__ __launch_bounds__((ColCfg<LY, V>::NT)) void col_kernel(Args a_in) {
         unit(e, c, y, off);
         float2 pr = make_float2(0.f, 0.f);
         if (kx0 + c < NXh) {
-          const float2 kv = jo == jlo ? kpre[e] : K[off];
+          const float2 kv = kpre[e];
           if (has_col0 && c == 0) {
             const float2 kn = KN[y];
             const float2 p0 = CONJ ? cmulc(x0[e], kv) : cmul(x0[e], kv);
@@ -774,6 +773,15 @@ __global__ __launch_bounds__((ColCfg<LY, V>::NT)) void col_kernel(Args a_in) {
           }
         }
         buf[c][lds_idx<LY>(y)] = cconj(pr);
+      }
+      if (jo + 1 < jhi) {  // the next image's transfer function, in flight during this transform
+        const float2* K1 = a.khat + (jo + 1) * sstride;
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+          int c, y; long long off;
+          unit(e, c, y, off);
+          kpre[e] = (kx0 + c < NXh) ? K1[off] : make_float2(0.f, 0.f);
+        }
       }
       __syncthreads();
       fft_lds<LY>(buf[tid / TF], lane, tw);
@@ -906,13 +914,18 @@ __global__ __launch_bounds__((ColCfg<LY, V>::NT)) void col_kernel(Args a_in) {
       if (kx0 + c < NXh) a.spec[jo * sstride + off] = cconj(buf[c][lds_idx<LY>(y)]);
     }
   } else {  // COL_CORRSUM
-    float2 acc[E];
+    const int jb = a.j0, je = a.j0 + (a.jn ? a.jn : a.p);
+    float2 acc[E], sp[E];  // sp: spectrum of the image transformed next
 #pragma unroll
-    for (int e = 0; e < E; ++e) acc[e] = make_float2(0.f, 0.f);
-    for (int ji = a.j0; ji < a.j0 + (a.jn ? a.jn : a.p); ++ji) {
+    for (int e = 0; e < E; ++e) {
+      int c, y; long long off;
+      unit(e, c, y, off);
+      acc[e] = make_float2(0.f, 0.f);
+      sp[e] = (kx0 + c < NXh) ? a.spec[jb * sstride + off] : make_float2(0.f, 0.f);
+    }
+    for (int ji = jb; ji < je; ++ji) {
       int lane = tid % TF;
       asm volatile("" : "+v"(lane));  // keeps per-pass address arithmetic inside the loop
-      load(a.spec + ji * sstride);
       const float2* K = a.khat + ji * sstride;
       const float2* KN = a.knyq + (long long)ji * LY;
       float2 kpre[E];
@@ -922,7 +935,21 @@ __global__ __launch_bounds__((ColCfg<LY, V>::NT)) void col_kernel(Args a_in) {
         unit(e, c, y, off);
         kpre[e] = (kx0 + c < NXh) ? K[off] : make_float2(0.f, 0.f);
       }
-      if (ji == a.j0) tws.store(twl, tid);
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        int c, y; long long off;
+        unit(e, c, y, off);
+        buf[c][lds_idx<LY>(y)] = sp[e];
+      }
+      if (ji == jb) tws.store(twl, tid);
+      if (ji + 1 < je) {  // the next image's spectrum, in flight during this transform
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+          int c, y; long long off;
+          unit(e, c, y, off);
+          sp[e] = (kx0 + c < NXh) ? a.spec[(ji + 1) * sstride + off] : make_float2(0.f, 0.f);
+        }
+      }
       __syncthreads();
       fft_lds<LY>(buf[tid / TF], lane, tw);
 #pragma unroll
