@@ -43,8 +43,11 @@ __host__ __device__ constexpr int lds_idx(int o) {
 }
 
 // ------------------------------------------------------------------ plans
-// L: transform length; E: elements per thread (a multiple of every radix);
-// TF = L / E threads per transform; R[]: radices in pass order.
+// L: transform length; E: elements per thread; TF = L / E threads per
+// transform; R[]: radices in pass order.  The first and last pass give every
+// thread E / R butterflies; a middle pass whose butterfly count L / R is not
+// a multiple of TF leaves the threads past it idle (1280: four points per
+// thread, 320 threads, the radix-5 pass on 256 of them).
 template <int L> struct FftPlan;
 #define SGP_FFT_PLAN(L_, E_, NP_, R0, R1, R2, R3, R4)                        \
   template <> struct FftPlan<L_> {                                          \
@@ -67,7 +70,7 @@ SGP_FFT_PLAN(80, 20, 3, 5, 4, 4, 1, 1)
 SGP_FFT_PLAN(160, 20, 4, 5, 4, 4, 2, 1)
 SGP_FFT_PLAN(320, 20, 4, 5, 4, 4, 4, 1)
 SGP_FFT_PLAN(640, 20, 5, 5, 4, 4, 4, 2)
-SGP_FFT_PLAN(1280, 20, 5, 5, 4, 4, 4, 4)
+SGP_FFT_PLAN(1280, 4, 5, 4, 4, 5, 4, 4)
 SGP_FFT_PLAN(2560, 40, 4, 5, 8, 8, 8, 1)
 #undef SGP_FFT_PLAN
 
@@ -203,19 +206,22 @@ struct TwStage {
 template <int L, int TF, int R, int NS>
 __device__ __forceinline__ void stockham_pass(float2* buf, int lane, const float2* __restrict__ tw) {
   constexpr int NB = L / R;
-  constexpr int PER = NB / TF;
-  static_assert(PER * TF == NB, "threads per transform must divide the butterfly count");
+  constexpr int PER = (NB + TF - 1) / TF;
+  constexpr bool ALL = PER * TF == NB;  // else butterflies j >= NB are idle
   float2 v[PER][R];
 #pragma unroll
   for (int q = 0; q < PER; ++q) {
     const int j = lane + q * TF;
+    if (ALL || j < NB) {
 #pragma unroll
-    for (int i = 0; i < R; ++i) v[q][i] = buf[lds_idx<L>(j + i * NB)];
+      for (int i = 0; i < R; ++i) v[q][i] = buf[lds_idx<L>(j + i * NB)];
+    }
   }
   __syncthreads();
 #pragma unroll
   for (int q = 0; q < PER; ++q) {
     const int j = lane + q * TF;
+    if (!ALL && j >= NB) continue;
     const int k = j % NS;
     if constexpr (NS > 1) {
 #pragma unroll
@@ -238,21 +244,25 @@ __device__ __forceinline__ void stockham_pass(float2* buf, int lane, const float
 template <int L, int TF, int R, int NS, bool FROM_REGS, bool TO_REGS>
 __device__ __forceinline__ void stockham_pass_x(float2* buf, int lane, const float2* __restrict__ tw, float2* x) {
   constexpr int NB = L / R;
-  constexpr int PER = NB / TF;
-  static_assert(PER * TF == NB, "threads per transform must divide the butterfly count");
+  constexpr int PER = (NB + TF - 1) / TF;
+  constexpr bool ALL = PER * TF == NB;  // else butterflies j >= NB are idle
+  static_assert(ALL || (!FROM_REGS && !TO_REGS), "a register-fed pass gives every thread whole butterflies");
   static_assert(!FROM_REGS || NS == 1, "only the first pass reads registers");
   static_assert(!TO_REGS || NS * R == L, "only the last pass writes registers");
   float2 v[PER][R];
 #pragma unroll
   for (int q = 0; q < PER; ++q) {
     const int j = lane + q * TF;
+    if (ALL || j < NB) {
 #pragma unroll
-    for (int i = 0; i < R; ++i) v[q][i] = FROM_REGS ? x[q + PER * i] : buf[lds_idx<L>(j + i * NB)];
+      for (int i = 0; i < R; ++i) v[q][i] = FROM_REGS ? x[q + PER * i] : buf[lds_idx<L>(j + i * NB)];
+    }
   }
   if constexpr (!FROM_REGS) __syncthreads();
 #pragma unroll
   for (int q = 0; q < PER; ++q) {
     const int j = lane + q * TF;
+    if (!ALL && j >= NB) continue;
     const int k = j % NS;
     if constexpr (NS > 1) {
 #pragma unroll

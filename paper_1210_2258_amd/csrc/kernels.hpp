@@ -469,7 +469,8 @@ __device__ __forceinline__ int xcd_remap(int w, int n, int g) {
 template <int L, int V = 0> struct RowCfg {
   static constexpr int TF = FftPlan<L>::TF;
   static constexpr int RP0 = SGP_ROW_THREADS / TF;
-  static constexpr int RPD = RP0 < 1 ? 1 : (RP0 > kRP ? kRP : RP0);
+  // row pairs per workgroup: a power of two (workgroups tile the 8-row blocks)
+  static constexpr int RPD = RP0 >= kRP ? kRP : RP0 >= 2 ? 2 : 1;
   static constexpr int RP = (V == 1 && RPD >= 2 && (RPD / 2) * TF >= 64) ? RPD / 2 : RPD;
   static constexpr int NT = RP * TF;
 };
@@ -644,15 +645,16 @@ __global__ __launch_bounds__((RowCfg<L, V>::NT)) void row_kernel(Args a_in) {
 
 // --------------------------------------------------------------- columns
 // C columns per workgroup.  Tile variant V = 0: as many as fit 256 threads
-// and 40 KB of column data; V = 1: twice as many when 512 threads and the
-// doubled LDS tile still fit, else half as many when that still fills a
-// wavefront (otherwise it equals V = 0).
+// (at least one) and 40 KB of column data; V = 1: twice as many when at
+// most 512 threads (1024 for a one-column tile) and the doubled LDS tile
+// still fit, else half as many when that still fills a wavefront (otherwise
+// it equals V = 0).
 template <int LY, int V = 0> struct ColCfg {
   static constexpr int TF = FftPlan<LY>::TF;
   static constexpr int C1 = 256 / TF;
   static constexpr int C2 = 40960 / (LY * 8);
   static constexpr int CD = (C1 < C2 ? C1 : C2) < 1 ? 1 : (C1 < C2 ? C1 : C2);
-  static constexpr bool DBL = 2 * CD <= C2 && 2 * CD * TF <= 512;
+  static constexpr bool DBL = 2 * CD <= C2 && 2 * CD * TF <= (CD == 1 ? 1024 : 512);
   static constexpr bool HLV = CD >= 2 && (CD / 2) * TF >= 64;
   static constexpr int C = V == 0 ? CD : DBL ? 2 * CD : HLV ? CD / 2 : CD;
   static constexpr int NT = C * TF;

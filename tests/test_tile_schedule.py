@@ -23,7 +23,7 @@ def test_variant_shapes(L):
     for v in (v0, v1):
         # rows: 2 RP rows per workgroup inside the 8-row block of the spectrum layout
         assert v["row_pairs"] in (1, 2, 4) and v["row_threads"] % v["row_pairs"] == 0
-        assert v["row_threads"] <= 1024 and v["col_threads"] <= 512
+        assert v["row_threads"] <= 1024 and v["col_threads"] <= (1024 if v["col_width"] <= 2 else 512)
         # columns: the LDS tile of C columns stays within 40 KB unless one column exceeds it
         assert v["col_width"] == 1 or v["col_width"] * L * 8 <= 40960
         assert v["col_threads"] % v["col_width"] == 0
@@ -42,8 +42,10 @@ def test_variant_one_differs_where_expected():
     # 2048: 512-thread row workgroups (2 row pairs) and 2-column workgroups
     assert m.tile_info(2048, 0) == dict(row_threads=1024, row_pairs=4, col_threads=256, col_width=1)
     assert m.tile_info(2048, 1) == dict(row_threads=512, row_pairs=2, col_threads=512, col_width=2)
-    # 1280: the 40 KB tile cannot grow, so the column variant halves it
-    assert m.tile_info(1280, 1)["col_width"] == m.tile_info(1280, 0)["col_width"] // 2
+    # 1280: four points per thread, 320 threads per transform; one column per
+    # workgroup, two in variant 1 (640 threads); two row pairs, one in variant 1
+    assert m.tile_info(1280, 0) == dict(row_threads=640, row_pairs=2, col_threads=320, col_width=1)
+    assert m.tile_info(1280, 1) == dict(row_threads=320, row_pairs=1, col_threads=640, col_width=2)
 
 
 def test_unsupported_length_and_variant():
