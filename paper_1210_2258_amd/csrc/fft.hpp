@@ -47,7 +47,9 @@ __host__ __device__ constexpr int lds_idx(int o) {
 // transform; R[]: radices in pass order.  The first and last pass give every
 // thread E / R butterflies; a middle pass whose butterfly count L / R is not
 // a multiple of TF leaves the threads past it idle (1280: four points per
-// thread, 320 threads, the radix-5 pass on 256 of them).
+// thread, 320 threads, the radix-5 pass on 256 of them).  Four points per
+// thread from 128 to 1280 (more waves per transform, one pass more); 2048
+// keeps eight, where four measured slower.
 template <int L> struct FftPlan;
 #define SGP_FFT_PLAN(L_, E_, NP_, R0, R1, R2, R3, R4)                        \
   template <> struct FftPlan<L_> {                                          \
@@ -57,10 +59,10 @@ template <int L> struct FftPlan;
 SGP_FFT_PLAN(16, 4, 2, 4, 4, 1, 1, 1)
 SGP_FFT_PLAN(32, 8, 2, 8, 4, 1, 1, 1)
 SGP_FFT_PLAN(64, 8, 2, 8, 8, 1, 1, 1)
-SGP_FFT_PLAN(128, 8, 3, 8, 4, 4, 1, 1)
-SGP_FFT_PLAN(256, 8, 3, 8, 8, 4, 1, 1)
-SGP_FFT_PLAN(512, 8, 3, 8, 8, 8, 1, 1)
-SGP_FFT_PLAN(1024, 8, 4, 8, 8, 4, 4, 1)
+SGP_FFT_PLAN(128, 4, 4, 4, 2, 4, 4, 1)
+SGP_FFT_PLAN(256, 4, 4, 4, 4, 4, 4, 1)
+SGP_FFT_PLAN(512, 4, 4, 4, 4, 8, 4, 1)
+SGP_FFT_PLAN(1024, 4, 5, 4, 4, 4, 4, 4)
 #ifndef SGP_E2048
 #define SGP_E2048 8
 #endif
