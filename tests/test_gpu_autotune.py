@@ -103,11 +103,13 @@ def test_variant_parity_full_size(torch_dev, c1_oracle, combo):
     assert abs(rep["kl"] - io["kl"]) <= 1e-6 * io["kl"]
 
 
-@pytest.mark.parametrize("shape", [(2048, 2048), (2048, 160), (1024, 80)])
+@pytest.mark.parametrize("shape", [(2048, 2048), (2048, 160), (1024, 80), (1280, 1280), (512, 256),
+                                   (256, 1024)])
 @pytest.mark.parametrize("combo", COMBOS)
 def test_operator_under_variants(torch_dev, shape, combo):
     """A and A^T under every tile combination (two-column register path at
-    2048, four columns at 1024) against the oracle's FFT convolution."""
+    2048, two 640-thread columns at 1280, four points per thread from 128 to
+    1280) against the oracle's FFT convolution."""
     import paper_1210_2258_amd as m
     torch = torch_dev
     ny, nx = shape

@@ -51,7 +51,8 @@ def _check_log(tr, log, n):
 
 # ------------------------------------------------------------------ operators
 @pytest.mark.parametrize("shape", [(16, 16), (64, 64), (32, 80), (80, 160), (256, 128), (1280, 640),
-                                   (1024, 1024), (1024, 80), (2048, 2048)])
+                                   (640, 1280), (512, 512), (128, 512), (1024, 1024), (1024, 80),
+                                   (2048, 2048)])
 def test_operator_matches_oracle(torch_dev, shape):
     import paper_1210_2258_amd as m
     torch = torch_dev
