@@ -360,36 +360,46 @@ int sgp_flux_multiplier(const double* z, const double* D, long long n, double c,
 
 /* ---------------------------------------------------------------------------
  * FFT tile schedule and its autotuner.  The FFTs are the main cost of an
- * iteration (Sect. 3.4, Sect. 5); the radix sequence of each length is fixed,
- * and the workgroup shape of its row and column passes comes in two tile
- * variants per length L:
- *   rows    variant 0: as many row pairs per workgroup as fit 1024 threads
- *                      (at most the 8-row block); variant 1: half as many;
- *   columns variant 0: as many columns as fit 256 threads and 40 KB of LDS;
- *           variant 1: twice as many (512 threads) where the LDS tile allows,
- *                      else half as many.
- * A variant that cannot differ at some L (it would leave a wavefront
- * partly empty or overflow the LDS) equals variant 0 there.  Both variants
- * compute the same per-pixel arithmetic; the FP64 reductions may add their
- * per-workgroup partial sums in another grouping.  The schedule is one
+ * iteration (Sect. 3.4, Sect. 5).  Each length L has four tile variants
+ * 0..3 for its row passes and for its column passes: bit 1 selects the
+ * transform plan (points per thread and radix sequence), bit 0 the
+ * workgroup shape:
+ *   plan 0: four points per thread from 128 to 1280 (radix 4 passes, one
+ *           radix 8 or 5 pass where the length needs it), eight at 2048
+ *           (8,8,8,4), the radix-5-first plans of the other 5 * 2^k lengths;
+ *   plan 1: eight points per thread from 128 to 1024 (radix 8 first);
+ *           lengths without a second plan run plan 0;
+ *   rows    shape 0: as many row pairs per workgroup as fit 1024 threads
+ *                    (at most the 8-row block); shape 1: half as many;
+ *   columns shape 0: as many columns as fit 256 threads (at least one) and
+ *                    40 KB of LDS; shape 1: twice as many (512 threads, 1024
+ *                    for a one-column tile) where the LDS tile allows, else
+ *                    half as many.
+ * A shape that cannot differ at some L (it would leave a wavefront partly
+ * empty or overflow the LDS) equals shape 0 there.  All variants compute
+ * the same per-pixel arithmetic; another plan rounds the transforms
+ * differently (to the FP32 accuracy of the FFT), another shape may add the
+ * FP64 per-workgroup partial sums in another grouping.  The schedule is one
  * process-wide table indexed by L (variant 0 where unset); a solver or
  * one-shot call reads it when it starts (rows of length NX, columns of
  * length NY) and keeps those variants.  Table calls are thread-safe.
  * ------------------------------------------------------------------------- */
 
-/* Shape of tile variant `variant` (0/1) at FFT length L: threads per
+/* Shape of tile variant `variant` (0..3) at FFT length L: threads per
  * workgroup and row pairs of the row kernel, threads and columns of the
- * column kernel (each output optional).  Host only, no device needed.
- * SGP_E_UNSUPPORTED_SIZE for a length the library has no FFT for. */
+ * column kernel (each output optional); its transforms take
+ * L * row_pairs / row_threads points per thread.  Host only, no device
+ * needed.  SGP_E_UNSUPPORTED_SIZE for a length the library has no FFT for,
+ * SGP_E_INVALID_ARG for a variant outside 0..3. */
 int sgp_tile_info(int L, int variant, int* row_threads, int* row_pairs, int* col_threads, int* col_width);
 /* Sets / reads the variants used for rows and for columns of length L. */
 int sgp_set_tile_schedule(int L, int row_variant, int col_variant);
 int sgp_get_tile_schedule(int L, int* row_variant, int* col_variant);
 /* Writes the table to a text file (a comment line, then one line
  * "L row_variant col_variant" per length set) / reads such a file and
- * applies every line.  A malformed line, unsupported length or variant other
- * than 0/1 fails the whole load with SGP_E_INVALID_ARG (naming the line) and
- * applies nothing; so does a file that cannot be opened. */
+ * applies every line.  A malformed line, unsupported length or variant
+ * outside 0..3 fails the whole load with SGP_E_INVALID_ARG (naming the line)
+ * and applies nothing; so does a file that cannot be opened. */
 int sgp_save_tile_schedule(const char* path);
 int sgp_load_tile_schedule(const char* path);
 /* Autotuner: times `iters` SGP iterations of the caller's problem (periodic,
@@ -401,8 +411,9 @@ int sgp_load_tile_schedule(const char* path);
  * graph block, times whole graph replays).  The fastest combination is
  * chosen unless it is within 1% of (0,0), which then stays; the choice is
  * set in the table and returned in *row_variant / *col_variant (optional).
- * ms (optional, 4 doubles): ms per iteration of (row, column) = (0,0),
- * (0,1), (1,0), (1,1); -1 for a combination equal to one already timed.
+ * ms (optional, 16 doubles): ms per iteration of (row, column) = (r, c) at
+ * ms[4 r + c]; -1 for a combination equal to one already timed (a variant
+ * that runs the same kernels as a lower one).
  * f: device [NY][NX], caller-owned scratch that is overwritten.  The problem
  * must run 4 iters iterations without a stop (fixed-count SGP: only a
  * numerical failure stops it), otherwise SGP_E_INVALID_ARG.  On any error

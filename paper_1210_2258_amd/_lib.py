@@ -404,10 +404,14 @@ def release_cache():
     return load().sgp_release_cache()
 
 
+TILE_VARIANTS = 4  # per length: bit 0 the workgroup shape, bit 1 the transform plan
+
+
 def tile_info(L, variant):
-    """Workgroup shape of tile variant ``variant`` at FFT length L (no GPU
-    needed): row-kernel threads and row pairs, column-kernel threads and
-    columns."""
+    """Workgroup shape of tile variant ``variant`` (0..3) at FFT length L (no
+    GPU needed): row-kernel threads and row pairs, column-kernel threads and
+    columns; the points per thread of its transforms are L * row_pairs /
+    row_threads."""
     lib = load()
     v = [ctypes.c_int() for _ in range(4)]
     _raise(lib.sgp_tile_info(int(L), int(variant), *[ctypes.byref(x) for x in v]))
@@ -434,9 +438,11 @@ def load_tile_schedule(path):
 
 def autotune(g, psf, b, *, domain=None, iters=20, stream=None):
     """Times every distinct tile combination on this problem (``g``/``psf``
-    as for Solver) and keeps the fastest in the schedule table.  Returns
-    (row_variant, col_variant, ms) with ms[(r, c)] the median ms per
-    iteration (absent for a combination equal to another)."""
+    as for Solver) and keeps the fastest in the schedule table.  Variants
+    0..3: bit 0 the workgroup shape, bit 1 the transform plan.  Returns
+    (row_variant, col_variant, ms) with ms[(r, c)] the least ms per
+    iteration over the timed runs (absent for a combination equal to
+    another)."""
     import torch
     lib = load()
     _check_dev(g, "g")
@@ -447,10 +453,11 @@ def autotune(g, psf, b, *, domain=None, iters=20, stream=None):
                   oy, ox, 1 if domain is not None else 0)
     f = torch.empty((NY, NX), dtype=torch.float32, device=g.device)
     r, c = ctypes.c_int(), ctypes.c_int()
-    ms = (ctypes.c_double * 4)()
+    ms = (ctypes.c_double * (TILE_VARIANTS * TILE_VARIANTS))()
     _raise(lib.sgp_autotune(ctypes.byref(pr), ctypes.c_void_p(f.data_ptr()), int(iters), ctypes.byref(r),
                             ctypes.byref(c), ms, _stream(stream)))
-    times = {(k >> 1, k & 1): ms[k] for k in range(4) if ms[k] >= 0}
+    times = {(k // TILE_VARIANTS, k % TILE_VARIANTS): ms[k] for k in range(TILE_VARIANTS * TILE_VARIANTS)
+             if ms[k] >= 0}
     return r.value, c.value, times
 
 

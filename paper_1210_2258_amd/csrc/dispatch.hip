@@ -14,7 +14,9 @@ namespace sgp {
   int row_threads_##L(int v);                                                 \
   int row_pairs_##L(int v);                                                   \
   int col_threads_##L(int v);                                                 \
-  void launch_twiddle_##L(float2* tw, hipStream_t s);
+  int plan_of_##L(int v);                                                     \
+  int plan_points_##L(int a);                                                 \
+  void launch_twiddle_##L(float2* tw, int a, hipStream_t s);
 SGP_SIZES(SGP_DECL)
 #undef SGP_DECL
 
@@ -48,6 +50,24 @@ int row_pairs(int L, int v) {
 int row_threads(int L, int v) {
   switch (L) {
 #define SGP_CASE(L) case L: return row_threads_##L(v);
+    SGP_SIZES(SGP_CASE)
+#undef SGP_CASE
+    default: return 0;
+  }
+}
+
+int plan_of(int L, int v) {
+  switch (L) {
+#define SGP_CASE(L) case L: return plan_of_##L(v);
+    SGP_SIZES(SGP_CASE)
+#undef SGP_CASE
+    default: return 0;
+  }
+}
+
+int plan_points(int L, int a) {
+  switch (L) {
+#define SGP_CASE(L) case L: return plan_points_##L(a);
     SGP_SIZES(SGP_CASE)
 #undef SGP_CASE
     default: return 0;
@@ -127,9 +147,9 @@ void launch_zero(unsigned* c, int n, hipStream_t s) {
   hipLaunchKernelGGL(zero_kernel, dim3((n + 255) / 256), dim3(256), 0, s, c, n);
 }
 
-void launch_twiddle(float2* tw, int L, hipStream_t s) {
+void launch_twiddle(float2* tw, int L, int a, hipStream_t s) {
   switch (L) {
-#define SGP_CASE(L) case L: launch_twiddle_##L(tw, s); break;
+#define SGP_CASE(L) case L: launch_twiddle_##L(tw, a, s); break;
     SGP_SIZES(SGP_CASE)
 #undef SGP_CASE
     default: break;

@@ -47,33 +47,43 @@ __host__ __device__ constexpr int lds_idx(int o) {
 // transform; R[]: radices in pass order.  The first and last pass give every
 // thread E / R butterflies; a middle pass whose butterfly count L / R is not
 // a multiple of TF leaves the threads past it idle (1280: four points per
-// thread, 320 threads, the radix-5 pass on 256 of them).  Four points per
-// thread from 128 to 1280 (more waves per transform, one pass more); 2048
-// keeps eight, where four measured slower.
-template <int L> struct FftPlan;
-#define SGP_FFT_PLAN(L_, E_, NP_, R0, R1, R2, R3, R4)                        \
-  template <> struct FftPlan<L_> {                                          \
+// thread, 320 threads, the radix-5 pass on 256 of them).
+// Plan A = 0 is the default of each length: four points per thread from 128
+// to 1280 (more waves per transform, one pass more), eight at 2048.  Plan
+// A = 1, where a length has one, is the other choice the tile autotuner may
+// take: eight points per thread from 128 to 1024.  A length without an
+// alternative has FftPlan<L, 1> equal to FftPlan<L, 0> (alt = false), and no
+// kernels are built for it.  (Four points per thread at 2048, radices
+// 4,4,8,4,4, was slower and rounded its transforms less closely: five
+// passes against four.)
+template <int L, int A = 0> struct FftPlan : FftPlan<L, 0> {
+  static constexpr bool alt = false;
+};
+#define SGP_FFT_PLAN(L_, A_, E_, NP_, R0, R1, R2, R3, R4)                    \
+  template <> struct FftPlan<L_, A_> {                                      \
     static constexpr int len = L_, E = E_, TF = L_ / E_, NP = NP_;          \
     static constexpr int r0 = R0, r1 = R1, r2 = R2, r3 = R3, r4 = R4;       \
+    static constexpr bool alt = A_ == 1;                                    \
   };
-SGP_FFT_PLAN(16, 4, 2, 4, 4, 1, 1, 1)
-SGP_FFT_PLAN(32, 8, 2, 8, 4, 1, 1, 1)
-SGP_FFT_PLAN(64, 8, 2, 8, 8, 1, 1, 1)
-SGP_FFT_PLAN(128, 4, 4, 4, 2, 4, 4, 1)
-SGP_FFT_PLAN(256, 4, 4, 4, 4, 4, 4, 1)
-SGP_FFT_PLAN(512, 4, 4, 4, 4, 8, 4, 1)
-SGP_FFT_PLAN(1024, 4, 5, 4, 4, 4, 4, 4)
-#ifndef SGP_E2048
-#define SGP_E2048 8
-#endif
-SGP_FFT_PLAN(2048, SGP_E2048, 4, 8, 8, 8, 4, 1)
-SGP_FFT_PLAN(4096, 16, 4, 8, 8, 8, 8, 1)
-SGP_FFT_PLAN(80, 20, 3, 5, 4, 4, 1, 1)
-SGP_FFT_PLAN(160, 20, 4, 5, 4, 4, 2, 1)
-SGP_FFT_PLAN(320, 20, 4, 5, 4, 4, 4, 1)
-SGP_FFT_PLAN(640, 20, 5, 5, 4, 4, 4, 2)
-SGP_FFT_PLAN(1280, 4, 5, 4, 4, 5, 4, 4)
-SGP_FFT_PLAN(2560, 40, 4, 5, 8, 8, 8, 1)
+SGP_FFT_PLAN(16, 0, 4, 2, 4, 4, 1, 1, 1)
+SGP_FFT_PLAN(32, 0, 8, 2, 8, 4, 1, 1, 1)
+SGP_FFT_PLAN(64, 0, 8, 2, 8, 8, 1, 1, 1)
+SGP_FFT_PLAN(128, 0, 4, 4, 4, 2, 4, 4, 1)
+SGP_FFT_PLAN(128, 1, 8, 3, 8, 4, 4, 1, 1)
+SGP_FFT_PLAN(256, 0, 4, 4, 4, 4, 4, 4, 1)
+SGP_FFT_PLAN(256, 1, 8, 3, 8, 8, 4, 1, 1)
+SGP_FFT_PLAN(512, 0, 4, 4, 4, 4, 8, 4, 1)
+SGP_FFT_PLAN(512, 1, 8, 3, 8, 8, 8, 1, 1)
+SGP_FFT_PLAN(1024, 0, 4, 5, 4, 4, 4, 4, 4)
+SGP_FFT_PLAN(1024, 1, 8, 4, 8, 8, 4, 4, 1)
+SGP_FFT_PLAN(2048, 0, 8, 4, 8, 8, 8, 4, 1)
+SGP_FFT_PLAN(4096, 0, 16, 4, 8, 8, 8, 8, 1)
+SGP_FFT_PLAN(80, 0, 20, 3, 5, 4, 4, 1, 1)
+SGP_FFT_PLAN(160, 0, 20, 4, 5, 4, 4, 2, 1)
+SGP_FFT_PLAN(320, 0, 20, 4, 5, 4, 4, 4, 1)
+SGP_FFT_PLAN(640, 0, 20, 5, 5, 4, 4, 4, 2)
+SGP_FFT_PLAN(1280, 0, 4, 5, 4, 4, 5, 4, 4)
+SGP_FFT_PLAN(2560, 0, 40, 4, 5, 8, 8, 8, 1)
 #undef SGP_FFT_PLAN
 
 // ------------------------------------------------------------- butterflies
@@ -145,9 +155,9 @@ template <> __device__ __forceinline__ void dft<5>(float2* v) {
 // (twiddle_pass_kernel), so a workgroup stages it with a contiguous copy.
 
 // Exponent m of W_L^m at entry t of the pass-ordered table (-1 past its end).
-template <int L>
+template <class P>
 __host__ __device__ constexpr int tw_pass_index(int t) {
-  using P = FftPlan<L>;
+  constexpr int L = P::len;
   const int rs[5] = {P::r0, P::r1, P::r2, P::r3, P::r4};
   int ns = P::r0;
   for (int p = 1; p < P::NP; ++p) {
@@ -164,11 +174,12 @@ __host__ __device__ constexpr int tw_pass_index(int t) {
 
 // The pass-ordered table of length L: exp(-2 pi i m / L) from double
 // precision, rounded to float (the value the natural-order table holds at m).
-template <int L>
+template <class P>
 __global__ void twiddle_pass_kernel(float2* tw) {
+  constexpr int L = P::len;
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t < L) {
-    const int m = tw_pass_index<L>(t);
+    const int m = tw_pass_index<P>(t);
     float2 v = make_float2(0.f, 0.f);
     if (m >= 0) {
       double s, c;
@@ -183,9 +194,9 @@ __global__ void twiddle_pass_kernel(float2* tw) {
 // kernel issues the global loads early (load(), with its own data loads)
 // and writes LDS later (store(), before the barrier that precedes the first
 // pass reading twiddles).
-template <int L, int NT>
+template <class P, int NT>
 struct TwStage {
-  static constexpr int N = L - FftPlan<L>::r0;
+  static constexpr int N = P::len - P::r0;
   static constexpr int PER = N > 0 ? (N + NT - 1) / NT : 1;
   float2 v[PER];
   __device__ __forceinline__ void load(const float2* __restrict__ tw, int tid) {
@@ -205,8 +216,9 @@ struct TwStage {
 };
 
 // ------------------------------------------------------------------ passes
-template <int L, int TF, int R, int NS>
+template <class P, int R, int NS>
 __device__ __forceinline__ void stockham_pass(float2* buf, int lane, const float2* __restrict__ tw) {
+  constexpr int L = P::len, TF = P::TF;
   constexpr int NB = L / R;
   constexpr int PER = (NB + TF - 1) / TF;
   constexpr bool ALL = PER * TF == NB;  // else butterflies j >= NB are idle
@@ -227,7 +239,7 @@ __device__ __forceinline__ void stockham_pass(float2* buf, int lane, const float
     const int k = j % NS;
     if constexpr (NS > 1) {
 #pragma unroll
-      for (int i = 1; i < R; ++i) v[q][i] = cmul(v[q][i], tw[NS - FftPlan<L>::r0 + (i - 1) * NS + k]);
+      for (int i = 1; i < R; ++i) v[q][i] = cmul(v[q][i], tw[NS - P::r0 + (i - 1) * NS + k]);
     }
     dft<R>(v[q]);
     const int base = (j / NS) * NS * R + k;
@@ -243,8 +255,9 @@ __device__ __forceinline__ void stockham_pass(float2* buf, int lane, const float
 // element lane + TF e: x[e] on entry to the first pass, and on exit from the
 // last.  A register-fed first pass writes buf without a barrier before it:
 // the caller makes sure no thread still reads buf.
-template <int L, int TF, int R, int NS, bool FROM_REGS, bool TO_REGS>
+template <class P, int R, int NS, bool FROM_REGS, bool TO_REGS>
 __device__ __forceinline__ void stockham_pass_x(float2* buf, int lane, const float2* __restrict__ tw, float2* x) {
+  constexpr int L = P::len, TF = P::TF;
   constexpr int NB = L / R;
   constexpr int PER = (NB + TF - 1) / TF;
   constexpr bool ALL = PER * TF == NB;  // else butterflies j >= NB are idle
@@ -268,7 +281,7 @@ __device__ __forceinline__ void stockham_pass_x(float2* buf, int lane, const flo
     const int k = j % NS;
     if constexpr (NS > 1) {
 #pragma unroll
-      for (int i = 1; i < R; ++i) v[q][i] = cmul(v[q][i], tw[NS - FftPlan<L>::r0 + (i - 1) * NS + k]);
+      for (int i = 1; i < R; ++i) v[q][i] = cmul(v[q][i], tw[NS - P::r0 + (i - 1) * NS + k]);
     }
     dft<R>(v[q]);
     if constexpr (TO_REGS) {
@@ -288,32 +301,28 @@ __device__ __forceinline__ void stockham_pass_x(float2* buf, int lane, const flo
 // buf as in fft_lds.  Saves the LDS round trip of staging the data.  With
 // IN, every thread must have finished reading buf before the call; with OUT,
 // buf is free for writes after the call.
-template <int L, bool IN, bool OUT>
+template <class P, bool IN, bool OUT>
 __device__ __forceinline__ void fft_lds_x(float2* buf, int lane, const float2* __restrict__ tw,
-                                          float2 (&x)[FftPlan<L>::E]) {
-  using P = FftPlan<L>;
-  constexpr int TF = P::TF;
+                                          float2 (&x)[P::E]) {
   constexpr int N0 = 1, N1 = P::r0, N2 = N1 * P::r1, N3 = N2 * P::r2, N4 = N3 * P::r3;
-  stockham_pass_x<L, TF, P::r0, N0, IN, OUT && P::NP == 1>(buf, lane, tw, x);
-  stockham_pass_x<L, TF, P::r1, N1, false, OUT && P::NP == 2>(buf, lane, tw, x);
-  if constexpr (P::NP > 2) stockham_pass_x<L, TF, P::r2, N2, false, OUT && P::NP == 3>(buf, lane, tw, x);
-  if constexpr (P::NP > 3) stockham_pass_x<L, TF, P::r3, N3, false, OUT && P::NP == 4>(buf, lane, tw, x);
-  if constexpr (P::NP > 4) stockham_pass_x<L, TF, P::r4, N4, false, OUT && P::NP == 5>(buf, lane, tw, x);
+  stockham_pass_x<P, P::r0, N0, IN, OUT && P::NP == 1>(buf, lane, tw, x);
+  stockham_pass_x<P, P::r1, N1, false, OUT && P::NP == 2>(buf, lane, tw, x);
+  if constexpr (P::NP > 2) stockham_pass_x<P, P::r2, N2, false, OUT && P::NP == 3>(buf, lane, tw, x);
+  if constexpr (P::NP > 3) stockham_pass_x<P, P::r3, N3, false, OUT && P::NP == 4>(buf, lane, tw, x);
+  if constexpr (P::NP > 4) stockham_pass_x<P, P::r4, N4, false, OUT && P::NP == 5>(buf, lane, tw, x);
 }
 
 // Forward FFT of buf (logical index i stored at lds_idx<L>(i)) in place,
-// natural order in and out, with the twiddles staged by TwStage<L, NT>.
-// Every thread
-// of the workgroup must call this (it contains barriers).
-template <int L>
+// natural order in and out, by plan P, with the twiddles staged by
+// TwStage<P, NT>.  Every thread of the workgroup must call this (it contains
+// barriers).
+template <class P>
 __device__ __forceinline__ void fft_lds(float2* buf, int lane, const float2* __restrict__ tw) {
-  using P = FftPlan<L>;
-  constexpr int TF = P::TF;
-  stockham_pass<L, TF, P::r0, 1>(buf, lane, tw);
-  stockham_pass<L, TF, P::r1, P::r0>(buf, lane, tw);
-  if constexpr (P::NP > 2) stockham_pass<L, TF, P::r2, P::r0 * P::r1>(buf, lane, tw);
-  if constexpr (P::NP > 3) stockham_pass<L, TF, P::r3, P::r0 * P::r1 * P::r2>(buf, lane, tw);
-  if constexpr (P::NP > 4) stockham_pass<L, TF, P::r4, P::r0 * P::r1 * P::r2 * P::r3>(buf, lane, tw);
+  stockham_pass<P, P::r0, 1>(buf, lane, tw);
+  stockham_pass<P, P::r1, P::r0>(buf, lane, tw);
+  if constexpr (P::NP > 2) stockham_pass<P, P::r2, P::r0 * P::r1>(buf, lane, tw);
+  if constexpr (P::NP > 3) stockham_pass<P, P::r3, P::r0 * P::r1 * P::r2>(buf, lane, tw);
+  if constexpr (P::NP > 4) stockham_pass<P, P::r4, P::r0 * P::r1 * P::r2 * P::r3>(buf, lane, tw);
 }
 
 }  // namespace sgp

@@ -459,26 +459,29 @@ __device__ __forceinline__ int xcd_remap(int w, int n, int g) {
 
 // ------------------------------------------------------------------ rows
 // RP row pairs (2 RP rows) per workgroup; 4 / RP workgroups share a block.
-// Tile variant V = 0 takes as many row pairs as fit 1024 threads (at most
-// the 8-row block); V = 1 half as many, when that still fills a wavefront
-// (otherwise it equals V = 0).  The per-row transforms and pointwise work are
-// the same in both; the autotuner picks one per row length.
+// Tile variant V: bit 0 the workgroup shape, bit 1 the transform plan
+// (FftPlan<L, V >> 1>, the length's alternative points per thread and
+// radices).  Shape 0 takes as many row pairs as fit 1024 threads (at most
+// the 8-row block); shape 1 half as many, when that still fills a wavefront
+// (otherwise it equals shape 0).  The pointwise work is the same in all; the
+// autotuner picks one variant per row length.
 #ifndef SGP_ROW_THREADS
 #define SGP_ROW_THREADS 1024
 #endif
 template <int L, int V = 0> struct RowCfg {
-  static constexpr int TF = FftPlan<L>::TF;
+  using P = FftPlan<L, (V >> 1)>;
+  static constexpr int TF = P::TF;
   static constexpr int RP0 = SGP_ROW_THREADS / TF;
   // row pairs per workgroup: a power of two (workgroups tile the 8-row blocks)
   static constexpr int RPD = RP0 >= kRP ? kRP : RP0 >= 2 ? 2 : 1;
-  static constexpr int RP = (V == 1 && RPD >= 2 && (RPD / 2) * TF >= 64) ? RPD / 2 : RPD;
+  static constexpr int RP = ((V & 1) && RPD >= 2 && (RPD / 2) * TF >= 64) ? RPD / 2 : RPD;
   static constexpr int NT = RP * TF;
 };
 
 template <int L, int OP, int V = 0>
 __global__ __launch_bounds__((RowCfg<L, V>::NT)) void row_kernel(Args a_in) {
   Args a = batch_view(a_in);
-  using P = FftPlan<L>;
+  using P = typename RowCfg<L, V>::P;
   constexpr int TF = P::TF;
   constexpr int RP = RowCfg<L, V>::RP;
   constexpr int NT = RowCfg<L, V>::NT;
@@ -513,7 +516,7 @@ __global__ __launch_bounds__((RowCfg<L, V>::NT)) void row_kernel(Args a_in) {
   const float2* tw = twl;
   // the twiddles are loaded with the kernel's first data and written to LDS
   // before the barrier that precedes the first pass reading them
-  TwStage<L, NT> tws;
+  TwStage<P, NT> tws;
   double acc[NS > 0 ? NS : 1];
   {
     RowKinds kinds{OP};
@@ -556,8 +559,8 @@ __global__ __launch_bounds__((RowCfg<L, V>::NT)) void row_kernel(Args a_in) {
     }
     tws.store(twl, tid);
     __syncthreads();
-    if constexpr (XR) fft_lds_x<L, false, true>(buf[qt], lt, tw, xr);
-    else fft_lds<L>(buf[qt], lt, tw);
+    if constexpr (XR) fft_lds_x<P, false, true>(buf[qt], lt, tw, xr);
+    else fft_lds<P>(buf[qt], lt, tw);
   } else if constexpr (row_has_fwd(OP)) {
     tws.load(a.tw_row, tid);  // in flight with the pointwise loads
   }
@@ -605,10 +608,10 @@ __global__ __launch_bounds__((RowCfg<L, V>::NT)) void row_kernel(Args a_in) {
     // with a barrier, and a forward-only op has not used buf)
     if constexpr (!row_has_inv(OP)) tws.store(twl, tid);  // (read after the first pass's barrier)
     if constexpr (XR) {
-      fft_lds_x<L, true, false>(buf[qt], lt, tw, xr);
+      fft_lds_x<P, true, false>(buf[qt], lt, tw, xr);
     } else {
       __syncthreads();
-      fft_lds<L>(buf[qt], lt, tw);
+      fft_lds<P>(buf[qt], lt, tw);
     }
     float4* O4 = reinterpret_cast<float4*>(spec);
 #pragma unroll
@@ -644,26 +647,28 @@ __global__ __launch_bounds__((RowCfg<L, V>::NT)) void row_kernel(Args a_in) {
 }
 
 // --------------------------------------------------------------- columns
-// C columns per workgroup.  Tile variant V = 0: as many as fit 256 threads
-// (at least one) and 40 KB of column data; V = 1: twice as many when at
-// most 512 threads (1024 for a one-column tile) and the doubled LDS tile
-// still fit, else half as many when that still fills a wavefront (otherwise
-// it equals V = 0).
+// C columns per workgroup.  Tile variant V: bit 1 the transform plan as for
+// the rows; bit 0 the shape: 0 as many columns as fit 256 threads (at least
+// one) and 40 KB of column data; 1 twice as many when at most 512 threads
+// (1024 for a one-column tile) and the doubled LDS tile still fit, else half
+// as many when that still fills a wavefront (otherwise it equals shape 0).
 template <int LY, int V = 0> struct ColCfg {
-  static constexpr int TF = FftPlan<LY>::TF;
+  using P = FftPlan<LY, (V >> 1)>;
+  static constexpr int TF = P::TF;
   static constexpr int C1 = 256 / TF;
   static constexpr int C2 = 40960 / (LY * 8);
   static constexpr int CD = (C1 < C2 ? C1 : C2) < 1 ? 1 : (C1 < C2 ? C1 : C2);
   static constexpr bool DBL = 2 * CD <= C2 && 2 * CD * TF <= (CD == 1 ? 1024 : 512);
   static constexpr bool HLV = CD >= 2 && (CD / 2) * TF >= 64;
-  static constexpr int C = V == 0 ? CD : DBL ? 2 * CD : HLV ? CD / 2 : CD;
+  static constexpr int C = !(V & 1) ? CD : DBL ? 2 * CD : HLV ? CD / 2 : CD;
   static constexpr int NT = C * TF;
 };
 
 template <int LY, int MODE, int CONJ, int V = 0>
 __global__ __launch_bounds__((ColCfg<LY, V>::NT)) void col_kernel(Args a_in) {
   const Args a = batch_view(a_in);
-  constexpr int TF = FftPlan<LY>::TF;
+  using PC = typename ColCfg<LY, V>::P;
+  constexpr int TF = PC::TF;
   constexpr int C = ColCfg<LY, V>::C;
   constexpr int NT = ColCfg<LY, V>::NT;
   constexpr int E = LY * C / NT;  // units per thread
@@ -682,7 +687,7 @@ __global__ __launch_bounds__((ColCfg<LY, V>::NT)) void col_kernel(Args a_in) {
   const float2* tw = twl;
   // twiddle loads issued first, written to LDS before the barrier that
   // precedes the first pass reading them, once the column data is in flight
-  TwStage<LY, NT> tws;
+  TwStage<PC, NT> tws;
   tws.load(a.tw_col, tid);
 
   // unit e of this thread -> (column c, row y) and its offset in the layout
@@ -707,7 +712,7 @@ __global__ __launch_bounds__((ColCfg<LY, V>::NT)) void col_kernel(Args a_in) {
     load(a.spec + jin * sstride);
     tws.store(twl, tid);
     __syncthreads();
-    fft_lds<LY>(buf[tid / TF], tid % TF, tw);
+    fft_lds<PC>(buf[tid / TF], tid % TF, tw);
     float2* K = a.khat + jin * sstride;
     float2* KN = a.knyq + (long long)jin * LY;
 #pragma unroll
@@ -737,7 +742,7 @@ __global__ __launch_bounds__((ColCfg<LY, V>::NT)) void col_kernel(Args a_in) {
     }
     tws.store(twl, tid);
     __syncthreads();
-    fft_lds<LY>(buf[tid / TF], tid % TF, tw);
+    fft_lds<PC>(buf[tid / TF], tid % TF, tw);
     float2 x0[E], x1[E];  // spectrum (or its even / odd parts for column 0)
 #pragma unroll
     for (int e = 0; e < E; ++e) {
@@ -786,7 +791,7 @@ __global__ __launch_bounds__((ColCfg<LY, V>::NT)) void col_kernel(Args a_in) {
         }
       }
       __syncthreads();
-      fft_lds<LY>(buf[tid / TF], lane, tw);
+      fft_lds<PC>(buf[tid / TF], lane, tw);
       float2* O = a.spec + jo * sstride;
 #pragma unroll
       for (int e = 0; e < E; ++e) {
@@ -826,7 +831,7 @@ __global__ __launch_bounds__((ColCfg<LY, V>::NT)) void col_kernel(Args a_in) {
       kpre[e] = live ? K[off] : make_float2(0.f, 0.f);
     }
     tws.store(twl, tid);  // (read after the first pass's barrier)
-    fft_lds_x<LY, true, true>(buf[c], lane, tw, xr);
+    fft_lds_x<PC, true, true>(buf[c], lane, tw, xr);
     if (has_col0) {  // uniform over the workgroup
       if (c == 0) {
 #pragma unroll
@@ -858,7 +863,7 @@ __global__ __launch_bounds__((ColCfg<LY, V>::NT)) void col_kernel(Args a_in) {
 #pragma unroll
       for (int e = 0; e < E; ++e) xr[e] = cconj(CONJ ? cmulc(xr[e], kpre[e]) : cmul(xr[e], kpre[e]));
     }
-    fft_lds_x<LY, true, true>(buf[c], lane, tw, xr);
+    fft_lds_x<PC, true, true>(buf[c], lane, tw, xr);
     if (live) {
 #pragma unroll
       for (int e = 0; e < E; ++e) {
@@ -883,7 +888,7 @@ __global__ __launch_bounds__((ColCfg<LY, V>::NT)) void col_kernel(Args a_in) {
     }
     tws.store(twl, tid);
     __syncthreads();
-    fft_lds<LY>(buf[tid / TF], tid % TF, tw);
+    fft_lds<PC>(buf[tid / TF], tid % TF, tw);
     float2 pr[E];
 #pragma unroll
     for (int e = 0; e < E; ++e) {
@@ -908,7 +913,7 @@ __global__ __launch_bounds__((ColCfg<LY, V>::NT)) void col_kernel(Args a_in) {
       buf[c][lds_idx<LY>(y)] = cconj(pr[e]);
     }
     __syncthreads();
-    fft_lds<LY>(buf[tid / TF], tid % TF, tw);
+    fft_lds<PC>(buf[tid / TF], tid % TF, tw);
 #pragma unroll
     for (int e = 0; e < E; ++e) {
       int c, y; long long off;
@@ -953,7 +958,7 @@ __global__ __launch_bounds__((ColCfg<LY, V>::NT)) void col_kernel(Args a_in) {
         }
       }
       __syncthreads();
-      fft_lds<LY>(buf[tid / TF], lane, tw);
+      fft_lds<PC>(buf[tid / TF], lane, tw);
 #pragma unroll
       for (int e = 0; e < E; ++e) {
         int c, y; long long off;
@@ -980,7 +985,7 @@ __global__ __launch_bounds__((ColCfg<LY, V>::NT)) void col_kernel(Args a_in) {
       buf[c][lds_idx<LY>(y)] = cconj(acc[e]);
     }
     __syncthreads();
-    fft_lds<LY>(buf[tid / TF], tid % TF, tw);
+    fft_lds<PC>(buf[tid / TF], tid % TF, tw);
 #pragma unroll
     for (int e = 0; e < E; ++e) {
       int c, y; long long off;

@@ -71,8 +71,8 @@ struct Plan {
   float2* spec = nullptr;
   float2* khat = nullptr;
   float2* knyq = nullptr;
-  float2* tw_row = nullptr;
-  float2* tw_col = nullptr;
+  float2* tw_row[2] = {nullptr, nullptr};  // twiddle tables of transform plans 0 and 1, rows (length NX)
+  float2* tw_col[2] = {nullptr, nullptr};  // and columns (length NY)
   double* part = nullptr;
   unsigned* counter = nullptr;
   DevState* st = nullptr;
@@ -91,7 +91,8 @@ struct Plan {
 
   ~Plan() {
     if (external) return;
-    void* ptrs[] = {grad, d, invw, invwj, Af, Af2, Ad, aux, spec, khat, knyq, tw_row, tw_col, part, counter, st, trace,
+    void* ptrs[] = {grad, d, invw, invwj, Af, Af2, Ad, aux, spec, khat, knyq, tw_row[0], tw_row[1], tw_col[0],
+                    tw_col[1], part, counter, st, trace,
                     (void*)gtab, (void*)ftab, (void*)psftab, (void*)srctab, btab, zmap};
     for (void* q : ptrs)
       if (q) (void)hipFree(q);
@@ -163,8 +164,10 @@ static int make_plan(const PlanKey& key, hipStream_t s, std::unique_ptr<Plan>& p
   if ((rc = dalloc(&pl->spec, nSpec * key.p))) return rc;
   if ((rc = dalloc(&pl->khat, nSpec * key.p))) return rc;
   if ((rc = dalloc(&pl->knyq, (size_t)key.NY * key.p * n))) return rc;
-  if ((rc = dalloc(&pl->tw_row, (size_t)key.NX))) return rc;
-  if ((rc = dalloc(&pl->tw_col, (size_t)key.NY))) return rc;
+  for (int a = 0; a < 2; ++a) {
+    if ((rc = dalloc(&pl->tw_row[a], (size_t)key.NX))) return rc;
+    if ((rc = dalloc(&pl->tw_col[a], (size_t)key.NY))) return rc;
+  }
   if ((rc = dalloc(&pl->part, part_capacity(key) * n))) return rc;
   if ((rc = dalloc(&pl->counter, n))) return rc;
   if ((rc = dalloc(&pl->st, n))) return rc;
@@ -178,8 +181,10 @@ static int make_plan(const PlanKey& key, hipStream_t s, std::unique_ptr<Plan>& p
   if ((rc = dalloc(&pl->btab, std::max<size_t>(n, kMaxP)))) return rc;
   SGP_HIP(hipHostMalloc((void**)&pl->host_st, sizeof(DevState) * n, hipHostMallocDefault));
   SGP_HIP(hipMemsetAsync(pl->counter, 0, sizeof(unsigned) * n, s));
-  launch_twiddle(pl->tw_row, key.NX, s);
-  launch_twiddle(pl->tw_col, key.NY, s);
+  for (int a = 0; a < 2; ++a) {
+    launch_twiddle(pl->tw_row[a], key.NX, a, s);
+    launch_twiddle(pl->tw_col[a], key.NY, a, s);
+  }
   SGP_HIP(hipGetLastError());
   return 0;
 }
@@ -230,8 +235,10 @@ static size_t carve_plan(const PlanKey& key, char* base, Plan& pl) {
   take(&pl.spec, nSpec * key.p);
   take(&pl.khat, nSpec * key.p);
   take(&pl.knyq, (size_t)key.NY * key.p);
-  take(&pl.tw_row, (size_t)key.NX);
-  take(&pl.tw_col, (size_t)key.NY);
+  for (int a = 0; a < 2; ++a) {
+    take(&pl.tw_row[a], (size_t)key.NX);
+    take(&pl.tw_col[a], (size_t)key.NY);
+  }
   take(&pl.part, part_capacity(key));
   take(&pl.counter, 1);
   take(&pl.st, 1);
@@ -368,6 +375,7 @@ static int current_device(int* dev) {
 // Tile schedule: the workgroup-shape variant of the row and column kernels
 // of each FFT length, process-wide (every device is the same part).  A solver
 // reads it when it is created and keeps its variants for its lifetime.
+constexpr int kTileVariants = 4;  // tile variants per length: bit 0 workgroup shape, bit 1 transform plan
 struct TileChoice {
   int row = 0, col = 0;
 };
@@ -1017,7 +1025,6 @@ static int create_items(int kind, const std::vector<Problem>& items, const std::
   a.Af = pl->Af; a.Af2 = pl->Af2; a.Ad = pl->Ad; a.spec = pl->spec; a.khat = pl->khat; a.knyq = pl->knyq;
   a.psf = pb.psf; a.aux = pl->aux; a.src = S->prm.f0;
   a.ftrue = (S->prm.stop & SGP_STOP_RMSE) ? S->prm.f_true : nullptr;
-  a.tw_row = pl->tw_row; a.tw_col = pl->tw_col;
   a.part = pl->part; a.counter = pl->counter; a.st = pl->st;
   a.bvec = pl->btab;
   if (n == 1) SGP_HIP(hipMemcpy(pl->btab, pb.b, sizeof(float) * pb.p, hipMemcpyHostToDevice));
@@ -1051,6 +1058,8 @@ static int create_items(int kind, const std::vector<Problem>& items, const std::
   L.s = S->s; L.NY = pb.NY; L.NX = pb.NX; L.nz = n;
   tile_schedule(pb.NX, &L.vrow, nullptr);
   tile_schedule(pb.NY, nullptr, &L.vcol);
+  a.tw_row = pl->tw_row[plan_of(pb.NX, L.vrow)];  // the tables of the transform plans the variants run
+  a.tw_col = pl->tw_col[plan_of(pb.NY, L.vcol)];
   if ((rc = setup(S.get()))) return rc;
   out = std::move(S);
   return 0;
@@ -1239,8 +1248,10 @@ static int deconv_noalloc(const float* g, const float* psf, const float* b_map, 
   // must start at zero (every other buffer is written before it is read);
   // cleared by a fill kernel, so the call records no memset node
   launch_zero(pl.counter, 1, s);
-  launch_twiddle(pl.tw_row, nx, s);
-  launch_twiddle(pl.tw_col, ny, s);
+  for (int a = 0; a < 2; ++a) {
+    launch_twiddle(pl.tw_row[a], nx, a, s);
+    launch_twiddle(pl.tw_col[a], ny, a, s);
+  }
   SGP_HIP(hipGetLastError());
   std::unique_ptr<sgp_solver> S;
   rc = create_items(KIND_SGP, std::vector<Problem>{pb}, std::vector<float*>{f},
@@ -1278,11 +1289,13 @@ static int apply_operator(const float* psf, const float* x, int ny, int nx, int 
   Args& a = L.base;
   a.NY = ny; a.NX = nx; a.ny = ny; a.nx = nx; a.p = 1;
   a.psf = psf; a.spec = pl->spec; a.khat = pl->khat; a.knyq = pl->knyq; a.aux = pl->aux;
-  a.tw_row = pl->tw_row; a.tw_col = pl->tw_col; a.part = pl->part; a.counter = pl->counter; a.st = pl->st;
+  a.part = pl->part; a.counter = pl->counter; a.st = pl->st;
   a.invw_s = 1.f;
   L.s = s; L.NY = ny; L.NX = nx;
   tile_schedule(nx, &L.vrow, nullptr);
   tile_schedule(ny, nullptr, &L.vcol);
+  a.tw_row = pl->tw_row[plan_of(nx, L.vrow)];
+  a.tw_col = pl->tw_col[plan_of(ny, L.vcol)];
   L.pix(PIX_PSFSUM, (long long)ny * nx, 0, 0);
   SGP_HIP(hipMemcpyAsync(pl->host_st, pl->st, sizeof(DevState), hipMemcpyDeviceToHost, s));
   SGP_HIP(hipStreamSynchronize(s));
@@ -1654,7 +1667,7 @@ int sgp_flux_multiplier(const double* z, const double* D, long long n, double c,
 int sgp_tile_info(int L, int variant, int* row_threads_out, int* row_pairs_out, int* col_threads_out,
                   int* col_width_out) {
   if (!size_supported(L)) return fail(SGP_E_UNSUPPORTED_SIZE, "unsupported FFT length " + std::to_string(L));
-  if (variant != 0 && variant != 1) return fail(SGP_E_INVALID_ARG, "tile variant must be 0 or 1");
+  if (variant < 0 || variant >= kTileVariants) return fail(SGP_E_INVALID_ARG, "tile variant must be in 0..3");
   if (row_threads_out) *row_threads_out = row_threads(L, variant);
   if (row_pairs_out) *row_pairs_out = row_pairs(L, variant);
   if (col_threads_out) *col_threads_out = col_threads(L, variant);
@@ -1664,8 +1677,8 @@ int sgp_tile_info(int L, int variant, int* row_threads_out, int* row_pairs_out, 
 
 int sgp_set_tile_schedule(int L, int row_variant, int col_variant) {
   if (!size_supported(L)) return fail(SGP_E_UNSUPPORTED_SIZE, "unsupported FFT length " + std::to_string(L));
-  if ((row_variant != 0 && row_variant != 1) || (col_variant != 0 && col_variant != 1))
-    return fail(SGP_E_INVALID_ARG, "tile variants must be 0 or 1");
+  if (row_variant < 0 || row_variant >= kTileVariants || col_variant < 0 || col_variant >= kTileVariants)
+    return fail(SGP_E_INVALID_ARG, "tile variants must be in 0..3");
   set_tile_schedule(L, row_variant, col_variant);
   return SGP_OK;
 }
@@ -1676,7 +1689,7 @@ int sgp_get_tile_schedule(int L, int* row_variant, int* col_variant) {
   return SGP_OK;
 }
 
-static const char* kTileHeader = "# sgpdeconv tile schedule v1: length row_variant col_variant";
+static const char* kTileHeader = "# sgpdeconv tile schedule v2: length row_variant col_variant (0..3)";
 
 int sgp_save_tile_schedule(const char* path) {
   if (!path) return fail(SGP_E_INVALID_ARG, "null path");
@@ -1707,11 +1720,11 @@ int sgp_load_tile_schedule(const char* path) {
     if (*q == '#' || *q == '\n' || *q == '\r' || *q == 0) continue;
     int L, r, c;
     char extra;
-    if (std::sscanf(q, "%d %d %d %c", &L, &r, &c, &extra) != 3 || !size_supported(L) || (r != 0 && r != 1) ||
-        (c != 0 && c != 1)) {
+    if (std::sscanf(q, "%d %d %d %c", &L, &r, &c, &extra) != 3 || !size_supported(L) || r < 0 ||
+        r >= kTileVariants || c < 0 || c >= kTileVariants) {
       rc = fail(SGP_E_INVALID_ARG, std::string(path) + ":" + std::to_string(lineno) +
                                        ": expected 'length row_variant col_variant' with a supported length "
-                                       "and variants 0 or 1");
+                                       "and variants in 0..3");
       break;
     }
     parsed[L] = TileChoice{r, c};
@@ -1764,13 +1777,27 @@ static int autotune(const sgp_problem* prob, float* f, int iters, int* row_varia
   int prev_row, prev_col;  // restored if a timing run fails
   tile_schedule(LX, &prev_row, nullptr);
   tile_schedule(LY, nullptr, &prev_col);
-  const bool row_alt = row_pairs(LX, 1) != row_pairs(LX, 0);
-  const bool col_alt = col_width(LY, 1) != col_width(LY, 0);
-  double t[4] = {-1.0, -1.0, -1.0, -1.0};
+  // a variant that runs the same kernels as a lower one is not timed
+  auto same_row = [&](int v, int w) {
+    return plan_of(LX, v) == plan_of(LX, w) && row_pairs(LX, v) == row_pairs(LX, w) &&
+           row_threads(LX, v) == row_threads(LX, w);
+  };
+  auto same_col = [&](int v, int w) {
+    return plan_of(LY, v) == plan_of(LY, w) && col_width(LY, v) == col_width(LY, w) &&
+           col_threads(LY, v) == col_threads(LY, w);
+  };
+  auto distinct = [&](int v, bool row) {
+    for (int w = 0; w < v; ++w)
+      if (row ? same_row(v, w) : same_col(v, w)) return false;
+    return true;
+  };
+  constexpr int NC = kTileVariants * kTileVariants;
+  double t[NC];
+  for (double& x : t) x = -1.0;
   int best = -1, rc = SGP_OK;
-  for (int combo = 0; combo < 4; ++combo) {
-    const int vr = combo >> 1, vc = combo & 1;
-    if ((vr && !row_alt) || (vc && !col_alt)) continue;  // equal to a combination already timed
+  for (int combo = 0; combo < NC; ++combo) {
+    const int vr = combo / kTileVariants, vc = combo % kTileVariants;
+    if (!distinct(vr, true) || !distinct(vc, false)) continue;  // equal to a combination already timed
     {
       std::lock_guard<std::mutex> lock(g_tile_mutex);
       g_tile[LX].row = vr;
@@ -1788,15 +1815,15 @@ static int autotune(const sgp_problem* prob, float* f, int iters, int* row_varia
       g_tile[LX].row = prev_row;
       g_tile[LY].col = prev_col;
     } else {
-      g_tile[LX].row = best >> 1;
-      g_tile[LY].col = best & 1;
+      g_tile[LX].row = best / kTileVariants;
+      g_tile[LY].col = best % kTileVariants;
     }
   }
   if (rc < 0) return rc;
-  if (row_variant) *row_variant = best >> 1;
-  if (col_variant) *col_variant = best & 1;
+  if (row_variant) *row_variant = best / kTileVariants;
+  if (col_variant) *col_variant = best % kTileVariants;
   if (ms)
-    for (int i = 0; i < 4; ++i) ms[i] = t[i];
+    for (int i = 0; i < NC; ++i) ms[i] = t[i];
   return SGP_OK;
 }
 

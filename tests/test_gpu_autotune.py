@@ -1,7 +1,8 @@
-"""Tile variants of the FFT kernels and the autotuner on the GPU: every
-variant combination against the oracle to the parity bar (single, multi,
-boundary, full size), a batch under a non-default schedule equal to its
-single runs, and the autotuner's choice landing in the table."""
+"""Tile variants of the FFT kernels and the autotuner on the GPU: variant
+combinations (workgroup shapes and transform plans) against the oracle to
+the parity bar (single, multi, boundary, full size), a batch under a
+non-default schedule equal to its single runs, and the autotuner's choice
+landing in the table."""
 import numpy as np
 import pytest
 
@@ -11,7 +12,14 @@ from synth import workloads as W
 pytestmark = pytest.mark.gpu
 
 SIZES = [16, 32, 64, 128, 256, 512, 1024, 2048, 80, 160, 320, 640, 1280]
-COMBOS = [(0, 1), (1, 0), (1, 1)]
+# (row variant, column variant): bit 0 the workgroup shape, bit 1 the transform plan
+COMBOS = [(0, 1), (1, 0), (1, 1), (2, 2), (3, 3), (2, 0), (0, 3)]
+
+
+def _points(L, v):
+    import paper_1210_2258_amd as m
+    t = m.tile_info(L, v)
+    return L * t["row_pairs"] // t["row_threads"]
 
 
 @pytest.fixture(scope="module")
@@ -77,10 +85,12 @@ def test_variant_parity(torch_dev, case, combo):
         assert int(rep["trace"]["backtracks"][k]) == io["log"][k]["backtracks"], k
     assert _rel(f.cpu().numpy(), fo) <= 1e-4
     assert abs(rep["kl"] - io["kl"]) <= 1e-6 * io["kl"]
-    # the variants share the per-pixel arithmetic: only the grouping of the
-    # FP64 partial sums may differ
-    assert _rel(f.cpu().numpy(), f0.cpu().numpy().astype(np.float64)) <= 1e-6
-    assert abs(rep["kl"] - rep0["kl"]) <= 1e-9 * rep0["kl"]
+    # under the default transform plans the variants share the per-pixel
+    # arithmetic: only the grouping of the FP64 partial sums may differ
+    # (another plan rounds the transforms differently: the oracle bar above)
+    if _points(NX, combo[0]) == _points(NX, 0) and _points(NY, combo[1]) == _points(NY, 0):
+        assert _rel(f.cpu().numpy(), f0.cpu().numpy().astype(np.float64)) <= 1e-6
+        assert abs(rep["kl"] - rep0["kl"]) <= 1e-9 * rep0["kl"]
 
 
 @pytest.fixture(scope="module")
@@ -92,7 +102,8 @@ def c1_oracle():
 
 @pytest.mark.parametrize("combo", COMBOS)
 def test_variant_parity_full_size(torch_dev, c1_oracle, combo):
-    """2048x2048 under 512-thread row workgroups and/or two-column workgroups."""
+    """2048x2048 under 512-thread row workgroups and/or two-column
+    workgroups (variants 2 and 3 equal 0 and 1 there: no second plan)."""
     import paper_1210_2258_amd as m
     w, (fo, io) = c1_oracle
     m.set_tile_schedule(2048, *combo)
@@ -164,7 +175,8 @@ def test_autotune_sets_the_table(torch_dev):
     w = W.config0()
     g, psf = _dev(torch, w.g[0]), _dev(torch, w.psf[0])
     r, c, ms = m.autotune(g, psf, float(w.b[0]), iters=32)
-    assert (r, c) in ms and set(ms) == {(0, 0), (0, 1), (1, 0), (1, 1)}
+    # at 256 every variant is distinct: two shapes under each of two plans
+    assert (r, c) in ms and set(ms) == {(i, j) for i in range(4) for j in range(4)}
     assert all(t > 0 for t in ms.values())
     # the fastest, unless within 1% of the default shape
     if (r, c) == (0, 0):

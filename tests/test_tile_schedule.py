@@ -1,6 +1,7 @@
-"""Host logic of the FFT tile schedule (no GPU): the shapes of both tile
-variants at every supported length, the process-wide table, and its text
-file (save, load, rejection of malformed files)."""
+"""Host logic of the FFT tile schedule (no GPU): the shapes of the four tile
+variants (workgroup shape x transform plan) at every supported length, the
+process-wide table, and its text file (save, load, rejection of malformed
+files)."""
 import os
 
 import pytest
@@ -17,19 +18,27 @@ def _restore_defaults():
         m.set_tile_schedule(L, 0, 0)
 
 
+def _points(L, v):
+    return L * v["row_pairs"] // v["row_threads"]
+
+
 @pytest.mark.parametrize("L", SIZES)
 def test_variant_shapes(L):
-    v0, v1 = m.tile_info(L, 0), m.tile_info(L, 1)
-    for v in (v0, v1):
+    vs = [m.tile_info(L, k) for k in range(4)]
+    for v in vs:
         # rows: 2 RP rows per workgroup inside the 8-row block of the spectrum layout
         assert v["row_pairs"] in (1, 2, 4) and v["row_threads"] % v["row_pairs"] == 0
         assert v["row_threads"] <= 1024 and v["col_threads"] <= (1024 if v["col_width"] <= 2 else 512)
         # columns: the LDS tile of C columns stays within 40 KB unless one column exceeds it
         assert v["col_width"] == 1 or v["col_width"] * L * 8 <= 40960
         assert v["col_threads"] % v["col_width"] == 0
-    # one FFT's thread count is the same in both variants
-    assert v0["row_threads"] // v0["row_pairs"] == v1["row_threads"] // v1["row_pairs"]
-    assert v0["col_threads"] // v0["col_width"] == v1["col_threads"] // v1["col_width"]
+        # whole transforms per workgroup, and a multiple of the wavefront
+        assert v["row_threads"] % 64 == 0 or v["row_threads"] < 64
+        assert L % _points(L, v) == 0
+    for v0, v1 in ((vs[0], vs[1]), (vs[2], vs[3])):
+        # one FFT's thread count is the same under both shapes of a plan
+        assert v0["row_threads"] // v0["row_pairs"] == v1["row_threads"] // v1["row_pairs"]
+        assert v0["col_threads"] // v0["col_width"] == v1["col_threads"] // v1["col_width"]
     # variant 1: half the row pairs, or the same shape where that would not fill a wavefront
     if v1["row_pairs"] != v0["row_pairs"]:
         assert v1["row_pairs"] * 2 == v0["row_pairs"] and v1["row_threads"] >= 64
@@ -46,17 +55,30 @@ def test_variant_one_differs_where_expected():
     # workgroup, two in variant 1 (640 threads); two row pairs, one in variant 1
     assert m.tile_info(1280, 0) == dict(row_threads=640, row_pairs=2, col_threads=320, col_width=1)
     assert m.tile_info(1280, 1) == dict(row_threads=320, row_pairs=1, col_threads=640, col_width=2)
+    # no second plan at 1280: variants 2 and 3 run plan 0
+    assert m.tile_info(1280, 2) == m.tile_info(1280, 0) and m.tile_info(1280, 3) == m.tile_info(1280, 1)
+
+
+@pytest.mark.parametrize("L,p0,p1", [(128, 4, 8), (256, 4, 8), (512, 4, 8), (1024, 4, 8), (2048, 8, 8),
+                                     (1280, 4, 4)])
+def test_transform_plans(L, p0, p1):
+    """Plan 0 and plan 1 (tile variants 0/1 and 2/3) take the documented
+    points per thread."""
+    assert _points(L, m.tile_info(L, 0)) == _points(L, m.tile_info(L, 1)) == p0
+    assert _points(L, m.tile_info(L, 2)) == _points(L, m.tile_info(L, 3)) == p1
 
 
 def test_unsupported_length_and_variant():
     with pytest.raises(m.SgpError):
         m.tile_info(100, 0)
     with pytest.raises(m.SgpError):
-        m.tile_info(256, 2)
+        m.tile_info(256, 4)
+    with pytest.raises(m.SgpError):
+        m.tile_info(256, -1)
     with pytest.raises(m.SgpError):
         m.set_tile_schedule(96, 0, 0)
     with pytest.raises(m.SgpError):
-        m.set_tile_schedule(256, 0, 3)
+        m.set_tile_schedule(256, 0, 4)
     assert m.get_tile_schedule(256) == (0, 0)
 
 
@@ -64,19 +86,22 @@ def test_table_and_file_round_trip(tmp_path):
     assert m.get_tile_schedule(512) == (0, 0)  # default
     m.set_tile_schedule(512, 1, 0)
     m.set_tile_schedule(1280, 0, 1)
+    m.set_tile_schedule(2048, 3, 2)
     assert m.get_tile_schedule(512) == (1, 0) and m.get_tile_schedule(1280) == (0, 1)
     path = tmp_path / "tiles.txt"
     m.save_tile_schedule(str(path))
     lines = path.read_text().splitlines()
     assert lines[0].startswith("#")
-    assert "512 1 0" in lines and "1280 0 1" in lines
+    assert "512 1 0" in lines and "1280 0 1" in lines and "2048 3 2" in lines
     m.set_tile_schedule(512, 0, 0)
     m.set_tile_schedule(1280, 0, 0)
+    m.set_tile_schedule(2048, 0, 0)
     m.load_tile_schedule(str(path))
     assert m.get_tile_schedule(512) == (1, 0) and m.get_tile_schedule(1280) == (0, 1)
+    assert m.get_tile_schedule(2048) == (3, 2)
 
 
-@pytest.mark.parametrize("bad", ["256 1\n", "256 1 2\n", "100 0 0\n", "256 0 1 7\n", "x y z\n"])
+@pytest.mark.parametrize("bad", ["256 1\n", "256 1 4\n", "100 0 0\n", "256 0 1 7\n", "x y z\n"])
 def test_malformed_file_applies_nothing(tmp_path, bad):
     path = tmp_path / "tiles.txt"
     path.write_text("# schedule\n64 1 1\n" + bad)

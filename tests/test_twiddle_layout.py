@@ -1,7 +1,7 @@
 """The pass-ordered twiddle table (csrc/fft.hpp, tw_pass_index): entry
 NS - r0 + (i - 1) NS + k of the pass with stride NS and radix R holds
-W_L^m with m = i k L / (NS R), for every supported length; the entries of
-all passes tile [0, L - r0) exactly once.  The index function is compiled
+W_L^m with m = i k L / (NS R), for every supported length and each of its
+transform plans; the entries of all passes tile [0, L - r0) exactly once.  The index function is compiled
 for the host from the library's header and compared with the layout
 written out here from the radix plans (no GPU needed)."""
 import os
@@ -18,11 +18,13 @@ SIZES = (16, 32, 64, 128, 256, 512, 1024, 2048, 80, 160, 320, 640, 1280)
 
 
 def _plans():
+    """{(L, A): radices} from the plan table of fft.hpp."""
     src = open(os.path.join(CSRC, "fft.hpp")).read()
     out = {}
-    for m in re.finditer(r"SGP_FFT_PLAN\((\d+), (\w+), (\d+), (\d+), (\d+), (\d+), (\d+), (\d+)\)", src):
-        L, NP = int(m.group(1)), int(m.group(3))
-        out[L] = [int(m.group(i)) for i in range(4, 9)][:NP]
+    pat = r"SGP_FFT_PLAN\((\d+), (\d), (\d+), (\d+), (\d+), (\d+), (\d+), (\d+), (\d+)\)"
+    for m in re.finditer(pat, src):
+        L, A, NP = int(m.group(1)), int(m.group(2)), int(m.group(4))
+        out[(L, A)] = [int(m.group(i)) for i in range(5, 10)][:NP]
     return out
 
 
@@ -44,8 +46,11 @@ def _expected(L, radices):
 @pytest.mark.skipif(not os.path.exists(HIPCC), reason="hipcc not installed")
 def test_pass_ordered_twiddle_index(tmp_path):
     prog = tmp_path / "tw.cpp"
-    body = "".join(f'  for (int t = 0; t < {L}; ++t) std::printf("{L} %d %d\\n", t, sgp::tw_pass_index<{L}>(t));\n'
-                   for L in SIZES)
+    plans = _plans()
+    keys = sorted(k for k in plans if k[0] in SIZES)
+    assert {L for L, _ in keys} == set(SIZES) and any(A == 1 for _, A in keys)
+    body = "".join(f'  for (int t = 0; t < {L}; ++t) std::printf("{L} {A} %d %d\\n", t, '
+                   f'sgp::tw_pass_index<sgp::FftPlan<{L}, {A}>>(t));\n' for L, A in keys)
     prog.write_text('#include <cstdio>\n#include "fft.hpp"\nint main() {\n' + body + "  return 0;\n}\n")
     exe = tmp_path / "tw"
     r = subprocess.run([HIPCC, "-std=c++17", "-x", "hip", "--offload-arch=gfx950", "-I", CSRC, str(prog), "-o", str(exe)],
@@ -54,12 +59,11 @@ def test_pass_ordered_twiddle_index(tmp_path):
     got = {}
     for line in subprocess.run([str(exe)], stdout=subprocess.PIPE, text=True, check=True).stdout.split("\n"):
         if line:
-            L, t, m = map(int, line.split())
-            got[(L, t)] = m
-    plans = _plans()
-    for L in SIZES:
-        exp = _expected(L, plans[L])
-        r0 = plans[L][0]
+            L, A, t, m = map(int, line.split())
+            got[(L, A, t)] = m
+    for L, A in keys:
+        exp = _expected(L, plans[(L, A)])
+        r0 = plans[(L, A)][0]
         assert sorted(exp) == list(range(L - r0))
         for t in range(L):
-            assert got[(L, t)] == exp.get(t, -1), (L, t, got[(L, t)], exp.get(t, -1))
+            assert got[(L, A, t)] == exp.get(t, -1), (L, A, t, got[(L, A, t)], exp.get(t, -1))
