@@ -15,7 +15,6 @@ namespace sgp {
   int row_pairs_##L(int v);                                                   \
   int col_threads_##L(int v);                                                 \
   int plan_of_##L(int v);                                                     \
-  int plan_points_##L(int a);                                                 \
   void launch_twiddle_##L(float2* tw, int a, hipStream_t s);
 SGP_SIZES(SGP_DECL)
 #undef SGP_DECL
@@ -59,15 +58,6 @@ int row_threads(int L, int v) {
 int plan_of(int L, int v) {
   switch (L) {
 #define SGP_CASE(L) case L: return plan_of_##L(v);
-    SGP_SIZES(SGP_CASE)
-#undef SGP_CASE
-    default: return 0;
-  }
-}
-
-int plan_points(int L, int a) {
-  switch (L) {
-#define SGP_CASE(L) case L: return plan_points_##L(a);
     SGP_SIZES(SGP_CASE)
 #undef SGP_CASE
     default: return 0;

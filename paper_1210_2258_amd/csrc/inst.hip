@@ -106,9 +106,8 @@ int SGP_CAT(row_threads_, SGP_L)(int v) {
   return c == 0 ? RowCfg<SGP_L, 0>::NT : c == 1 ? RowCfg<SGP_L, 1>::NT : c == 2 ? RowCfg<SGP_L, 2>::NT
                                                                               : RowCfg<SGP_L, 3>::NT;
 }
-// the transform plan a variant runs (0 or 1), and the points per thread
+// the transform plan a variant runs (0 or 1)
 int SGP_CAT(plan_of_, SGP_L)(int v) { return kAlt ? (v >> 1) & 1 : 0; }
-int SGP_CAT(plan_points_, SGP_L)(int a) { return a && kAlt ? FftPlan<SGP_L, 1>::E : FftPlan<SGP_L, 0>::E; }
 
 // the twiddle table of length SGP_L in the pass order of plan a's transforms
 void SGP_CAT(launch_twiddle_, SGP_L)(float2* tw, int a, hipStream_t s) {

@@ -14,9 +14,8 @@ int row_threads(int L, int v);
 // row pairs handled by one row-kernel workgroup
 int row_pairs(int L, int v);
 int col_threads(int L, int v);
-// the transform plan (0 or 1) that variant v runs, and plan a's points per thread
+// the transform plan (0 or 1) that variant v runs
 int plan_of(int L, int v);
-int plan_points(int L, int a);
 void launch_row(int L, int v, int op, dim3 grid, const Args& a, hipStream_t s);
 void launch_col(int L, int v, int mode, int conj, dim3 grid, const Args& a, hipStream_t s);
 void launch_pix(int op, dim3 grid, const Args& a, hipStream_t s);

@@ -97,7 +97,6 @@ void launch_col(int, int, int, int, dim3, const Args&, hipStream_t) {}
 void launch_pix(int, dim3, const Args&, hipStream_t) {}
 void launch_twiddle(float2*, int, int, hipStream_t) {}
 int plan_of(int, int v) { return (v >> 1) & 1; }
-int plan_points(int L, int a) { return a ? 8 : 4; }
 void launch_zero(unsigned* c, int n, hipStream_t) { run_or_rec([=] { memset(c, 0, sizeof(unsigned) * n); }); }
 void launch_resume(DevState* st, int n, int nitems, hipStream_t) {
   run_or_rec([=] {
