@@ -392,11 +392,12 @@ def cpu_baseline(w, iters, gpu_iters_to_disc=None):
     return out
 
 
-def config_rates(torch, m, steps, warmup, with_oracle):
+def config_rates(torch, m, steps, warmup, with_oracle, tune_tiles=True):
     """SGP iterations per second on the multi-image (3 x 1024^2) and the
     boundary-corrected (1024^2 window in a 1280^2 domain) workloads, each
-    with its bytes model and fraction of the HBM roofline; with the oracle,
-    its seconds per iteration on the same input (2 timed iterations, one core)."""
+    with its bytes model and fraction of the HBM roofline, under the tile
+    schedule the autotuner picks on that problem; with the oracle, its
+    seconds per iteration on the same input (2 timed iterations, one core)."""
     from synth import workloads as W
     out = {}
     for name, w in (("multi_3x1024", W.config2()), ("boundary_1280", W.config3())):
@@ -407,6 +408,11 @@ def config_rates(torch, m, steps, warmup, with_oracle):
             NY, NX = w.domain[0], w.domain[1]
         else:
             NY, NX = ny, nx
+        tiles = None
+        if tune_tiles:
+            r, c, ms = m.autotune(g, psf, w.b, domain=w.domain, iters=96)
+            tiles = {"rows_variant": r, "cols_variant": c,
+                     "ms_per_iter": {f"{k[0]}{k[1]}": v for k, v in ms.items()}}
         S = m.Solver(m.KIND_SGP, g, psf, w.b, domain=w.domain, max_iter=steps + warmup + 10)
         S.prepare(steps)
         S.step(warmup)
@@ -422,6 +428,8 @@ def config_rates(torch, m, steps, warmup, with_oracle):
         row = {"images": p, "window": [ny, nx], "fft_domain": [NY, NX], "iter_per_s": 1.0 / dt,
                "ms_per_iteration": 1e3 * dt, "bytes_per_iteration": nb,
                "achieved_GBs": nb / dt / 1e9, "frac": nb / dt / 1e9 / HBM_PEAK_GBS}
+        if tiles is not None:
+            row["tile_schedule"] = tiles
         if with_oracle:
             _, per = oracle_rate(w, 2)
             row["oracle_s_per_iteration_one_core"] = per
@@ -562,7 +570,7 @@ def main():
         out["rebin_sweep"] = rebin_sweep(torch, m, with_oracle=not args.no_cpu)
         note("rebin sweep done")
     if not args.no_configs:
-        out["configs"] = config_rates(torch, m, 100, 10, not args.no_cpu)
+        out["configs"] = config_rates(torch, m, 100, 10, not args.no_cpu, tune_tiles=not args.no_autotune)
         note("config rates done")
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_iters, out_ttd.get("iters_to_discrepancy"))
