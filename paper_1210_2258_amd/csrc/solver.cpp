@@ -467,8 +467,10 @@ struct Launcher {
     a.fin_nblk = row_nblk;
     long long nb = (n + kPixThreads - 1) / kPixThreads;
     // the extra Armijo candidates are rarely needed: a small grid keeps the
-    // usual early exit cheap
-    const long long cap = op == PIX_ARMIJO ? kArmBlocks : kMaxPixBlocks;
+    // usual early exit cheap (one workgroup per 2048 pixels of an item, at
+    // most kArmBlocks; the same grid per item in single and batched runs,
+    // so their sums group alike)
+    const long long cap = op == PIX_ARMIJO ? std::min<long long>(kArmBlocks, (n + 2047) / 2048) : kMaxPixBlocks;
     nb = std::max<long long>(1, std::min<long long>(nb, cap));
     a.nblk = (int)nb;
     a.iter = iter;
