@@ -43,7 +43,8 @@ __host__ __device__ inline void fin_armijo(DevState* st, const double* dJ, int m
     const int mm = m0 + m;
     if (mm > st->max_backtracks) break;
     const double lam = st->lam_tab[mm];
-    if (!__builtin_isfinite(dJ[m])) {
+    // (+infinity: a candidate outside the domain of J, which fails the test)
+    if (__builtin_isnan(dJ[m])) {
       st->done = 1;
       st->reason = REASON_NUMERIC;
       return;
@@ -72,7 +73,7 @@ __host__ __device__ inline bool armijo_needs_more(const DevState* st, const doub
   for (int m = 0; m < n; ++m) {
     const int mm = m0 + m;
     if (mm > st->max_backtracks) break;
-    if (!__builtin_isfinite(dJ[m])) return false;
+    if (__builtin_isnan(dJ[m])) return false;
     if (dJ[m] <= st->beta * st->lam_tab[mm] * st->gd) return false;
     if (st->rl2 && mm == st->max_backtracks) return false;
   }

@@ -151,9 +151,18 @@ __device__ __forceinline__ double kl_term(float g, float y) {
 }
 
 // J(f + lam d) - J(f) contribution of one pixel with y = A f + b, t = lam A d:
-// t - g log1p(t / y) = (y - g) x + g h(x) with x = t / y.
+// t - g log1p(t / y) = (y - g) x + g h(x) with x = t / y.  The exact model
+// value y + t is positive for every lam <= 1 (f + lam d >= 0); when a step
+// many orders of magnitude above y makes it round to <= 0 (x <= -1) where
+// g > 0, the candidate lies outside the domain of J.  Such a pixel adds the
+// barrier g 1e30 (+infinity once g > 3.4e8), so the candidate fails the
+// Armijo test and the search goes on to a shorter step; where g = 0 the
+// term stays t.  (h(-1) = +infinity is capped at 1e30 so that 0 h stays 0;
+// x = NaN keeps the first product NaN, and the NaN h of x = +infinity passes
+// the cap, so both are still reported as numeric failures.)
 __device__ __forceinline__ double armijo_x(float g, float y, float x) {
-  return (double)((y - g) * x) + (double)(g * h_x(x));
+  const float h = h_x(fmaxf(x, -1.f));
+  return (double)((y - g) * x) + (double)(g * (h > 1e30f ? 1e30f : h));
 }
 __device__ __forceinline__ double armijo_term(float g, float y, float t) {
   return armijo_x(g, y, qdiv(t, y));

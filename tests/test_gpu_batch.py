@@ -105,3 +105,26 @@ def test_batch_equals_single_large_and_boundary(torch_dev):
         assert r1["iters"] == reps[i]["iters"] == 20, (i, r1["iters"], reps[i]["iters"])
         assert torch.equal(f1, fs[i]), i
         assert r1["kl"] == reps[i]["kl"], i
+
+
+@pytest.mark.parametrize("alpha0", [1e2, 1e5])
+def test_batch_equals_single_with_many_backtracks(torch_dev, alpha0):
+    """A large first steplength sends every item's line search past the first
+    two candidates into the Armijo kernel's candidate pass (and at 1e5 past
+    theta^9 into its second stage); the pass takes the same workgroups per
+    item in a batch as in a single run, so the batch still equals the single
+    runs bit for bit."""
+    import paper_1210_2258_amd as m
+    torch = torch_dev
+    items = _items()[:5]
+    gs = [_dev(torch, w.g[0]) for w in items]
+    ps = [_dev(torch, w.psf[0]) for w in items]
+    bs = [float(w.b[0]) for w in items]
+    kw = dict(max_iter=6, alpha0=alpha0)
+    fs, reps = m.batch_deconv(gs, ps, bs, **kw)
+    assert sum(r["backtracks"] for r in reps) >= 2 * len(items)
+    for i in range(len(items)):
+        f1, r1 = m.sgp_deconv(gs[i], ps[i], bs[i], **kw)
+        assert r1["backtracks"] == reps[i]["backtracks"], i
+        assert torch.equal(f1, fs[i]), i
+        assert r1["kl"] == reps[i]["kl"], i
