@@ -1,6 +1,7 @@
 // Test infrastructure: drives the batch entry point through the CPU stand-in
-// runtime (shim.cpp) in several call orders and checks each item's report
-// against the iteration count at which the stand-in stops it.
+// runtime (shim.cpp) in several call orders, and single problems through the
+// stepping loop, and checks each report against the iteration count at which
+// the stand-in stops the item.
 #include <cstdio>
 #include <cstdlib>
 #include <vector>
@@ -66,6 +67,21 @@ int main() {
   std::vector<int> half(order.begin(), order.begin() + order.size() / 2);
   run(half, true, 3000, "warm, half");
   run(order, true, 3000, "warm, all");
+  // one problem through the stepping loop: graph replays (sgp_deconv), and
+  // eager launches into the static workspace (sgp_deconv_noalloc); the
+  // stand-in stops it at shim_target(0) iterations
+  for (int max_iter : {1, 2, 50}) {
+    Item& it = items[0];
+    sgp_params p;
+    sgp_params_init(&p);
+    p.max_iter = max_iter;
+    sgp_report r1, r2;
+    const int rc1 = sgp_deconv(it.g, it.psf, nullptr, it.b, it.n, it.n, &p, it.f, &r1, nullptr);
+    const int rc2 = sgp_deconv_noalloc(it.g, it.psf, nullptr, it.b, it.n, it.n, &p, it.f, &r2, nullptr);
+    const int want = sgp::shim_target(0) < max_iter ? sgp::shim_target(0) : max_iter;
+    printf("single max_iter=%2d rc=%d/%d iters=%d/%d want %d\n", max_iter, rc1, rc2, r1.iters, r2.iters, want);
+    if (rc1 < 0 || rc2 < 0 || r1.iters != want || r2.iters != want) ++bad;
+  }
   sgp_release_cache();
   for (auto& it : items) { free(it.g); free(it.psf); free(it.f); free(it.f0); }
   printf(bad ? "FAILED %d\n" : "ALL OK\n", bad);

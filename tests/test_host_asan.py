@@ -3,8 +3,10 @@ driver with its per-item stops, compaction and graph re-capture) under
 AddressSanitizer on the CPU: solver.cpp is compiled for the host only and
 linked against a CPU stand-in for the HIP runtime whose graphs record and
 replay the launches and whose iteration end stops each batched item at a
-known count.  The harness checks every item's iteration count in its report
-and that the run has no invalid memory access or bad free."""
+known count.  The harness checks every item's iteration count in its report,
+for batches and for single problems through the stepping loop (graph replays
+and the eager launches of the entry point that allocates nothing), and that
+the run has no invalid memory access or bad free."""
 import os
 import shutil
 import subprocess
@@ -43,3 +45,4 @@ def test_batch_host_logic_under_asan(tmp_path):
                        env=env)
     out = r.stdout + r.stderr
     assert r.returncode == 0 and "ALL OK" in r.stdout and "AddressSanitizer" not in out, out[-4000:]
+    assert r.stdout.count("single max_iter") == 3, r.stdout[-2000:]
